@@ -1,0 +1,497 @@
+/*
+ * CPU oracle for exact order-independent transparency of planar quads
+ * (LucidRaster, arXiv 2405.13364).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow definition the GPU
+ * rasterizer is checked against.  Only the tests, the smoke check and the CPU
+ * timing leg of the benchmark may load it; the rendering library never does.
+ * It shares no code, header, table or constant with the HIP path.
+ *
+ * What it computes (Section 1 states the problem: find every fragment that
+ * contributes to a pixel, sort, blend in order; Section 2 "Pipeline
+ * description" fixes quads as the primitive and front-to-back blending from
+ * transparent black, Stage 3 "Sample blending"):
+ *
+ *   for every pixel centre, every visible quad whose area covers it gives one
+ *   fragment; fragments are ordered nearest first (ties by quad index) and
+ *   blended front to back.
+ *
+ * The paper leaves the numeric details open; the readings used here (all
+ * IEEE-754 binary64, round to nearest even, no contraction except where fma()
+ * is written -- build with -ffp-contract=off):
+ *
+ *   camera   c_i = fma(R_i2, d_2, fma(R_i1, d_1, R_i0 * d_0)), d = v - pos
+ *   near     any c.z <= z_near                       -> culled (NEAR)
+ *   project  sx = fma(f, c.x/c.z, cx), sy = fma(-f, c.y/c.z, cy),
+ *            f = (H/2) / tan(fov_y/2) on the host, cx = W/2, cy = H/2
+ *   guard    any |sx| or |sy| >= 2^15 or non-finite  -> culled (GUARD)
+ *   snap     X = rint(256 sx), Y = rint(256 sy)   (1/256 pixel grid)
+ *   cover    pixel (i,j) samples S = (256 i + 128, 256 j + 128); the quad is
+ *            the union of triangles (P0,P1,P2) and (P0,P2,P3); a triangle
+ *            with zero doubled area is empty; the others are oriented to
+ *            positive doubled area and contain S when every edge function is
+ *            > 0, or == 0 on a top-left edge (dy < 0, or dy == 0 and dx > 0).
+ *            Both triangles empty                    -> culled (DEGENERATE)
+ *   bbox     i in [ceil((Xmin-128)/256), floor((Xmax-128)/256)] clamped to
+ *            the screen; empty                       -> culled (NO_SAMPLE)
+ *   depth    plane through the vertex centroid with normal = cross product
+ *            of the diagonals; reciprocal view depth is affine on screen:
+ *            1/z(i,j) = A (i-imin) + B (j-jmin) + C0.  A degenerate or
+ *            non-finite plane                        -> culled (EDGE_ON)
+ *   key      k = (float) fma(A, i-imin, fma(B, j-jmin, C0)), clamped to +0
+ *            when not positive; larger k is nearer.
+ *   order    ascending (~bits(k) << 32 | quad index)
+ *   blend    T = 1, C = 0; per fragment a = A8/255, C += T a rgb/255,
+ *            T *= 1 - a; output premultiplied (C, 1 - T); RGBA8 is
+ *            clamp(floor(255 x + 0.5)).
+ *   unsorted quad index order, "over": C = a c + (1-a) C, al = a + (1-a) al.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define LRO_VISIBLE 0
+#define LRO_NEAR 1
+#define LRO_GUARD 2
+#define LRO_DEGENERATE 3
+#define LRO_NO_SAMPLE 4
+#define LRO_EDGE_ON 5
+
+typedef struct {
+    float pos[3];
+    float rot[9];
+    float fov_y;
+    float z_near;
+} lro_camera;
+
+/* Focal length in pixels (host libm tan). */
+double lro_focal(uint32_t height, float fov_y)
+{
+    return (0.5 * (double)height) / tan(0.5 * (double)fov_y);
+}
+
+static int64_t edge_fn(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px, int64_t py)
+{
+    return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+/* Coverage of sample (sx, sy) by the triangle (a, b, c) under the top-left
+ * rule.  Returns 0 for a zero-area triangle. */
+static int tri_covers(const int32_t *X, const int32_t *Y, int ia, int ib, int ic, int64_t sx,
+                      int64_t sy)
+{
+    int64_t ax = X[ia], ay = Y[ia], bx = X[ib], by = Y[ib], cx = X[ic], cy = Y[ic];
+    int64_t area2 = edge_fn(ax, ay, bx, by, cx, cy);
+    if (area2 == 0)
+        return 0;
+    if (area2 < 0) {
+        int64_t tx = bx, ty = by;
+        bx = cx; by = cy;
+        cx = tx; cy = ty;
+    }
+    const int64_t vx[3] = {ax, bx, cx}, vy[3] = {ay, by, cy};
+    for (int e = 0; e < 3; e++) {
+        int64_t x0 = vx[e], y0 = vy[e], x1 = vx[(e + 1) % 3], y1 = vy[(e + 1) % 3];
+        int64_t ev = edge_fn(x0, y0, x1, y1, sx, sy);
+        int64_t dx = x1 - x0, dy = y1 - y0;
+        int top_left = (dy < 0) || (dy == 0 && dx > 0);
+        if (ev < 0 || (ev == 0 && !top_left))
+            return 0;
+    }
+    return 1;
+}
+
+/* Does quad (X[4], Y[4]) cover the centre of pixel (i, j)?  One fragment at
+ * most: the union of its two triangles. */
+int lro_covers(const int32_t *X, const int32_t *Y, int32_t i, int32_t j)
+{
+    int64_t sx = 256 * (int64_t)i + 128, sy = 256 * (int64_t)j + 128;
+    return tri_covers(X, Y, 0, 1, 2, sx, sy) || tri_covers(X, Y, 0, 2, 3, sx, sy);
+}
+
+static int64_t floordiv256(int64_t a) { return a >= 0 ? a / 256 : -((-a + 255) / 256); }
+
+/*
+ * Per-quad setup.  v: float[n][4][3] world vertices.  Outputs per quad:
+ * X, Y int32[n][4] snapped vertices; bbox int32[n][4] = (imin, imax, jmin,
+ * jmax); A, B, C0 double[n]; cull uint8[n] (0 = visible, else the first
+ * failing test in the order near, guard, degenerate, no-sample, edge-on).
+ * Fields of culled quads are left as far as they were computed.
+ */
+void lro_setup(uint32_t n, const float *v, const lro_camera *cam, uint32_t W, uint32_t H, double f,
+               int32_t *X, int32_t *Y, int32_t *bbox, double *A, double *B, double *C0,
+               uint8_t *cull)
+{
+    const double cx = 0.5 * (double)W, cy = 0.5 * (double)H;
+    double R[9], P[3];
+    for (int k = 0; k < 9; k++)
+        R[k] = (double)cam->rot[k];
+    for (int k = 0; k < 3; k++)
+        P[k] = (double)cam->pos[k];
+    const double znear = (double)cam->z_near;
+
+    for (uint32_t q = 0; q < n; q++) {
+        double c[4][3];
+        int32_t *x = X + 4 * (size_t)q, *y = Y + 4 * (size_t)q, *bb = bbox + 4 * (size_t)q;
+        A[q] = B[q] = C0[q] = 0.0;
+        memset(x, 0, 16);
+        memset(y, 0, 16);
+        bb[0] = 1; bb[1] = 0; bb[2] = 1; bb[3] = 0;
+        /* camera transform */
+        for (int k = 0; k < 4; k++) {
+            const float *vk = v + 12 * (size_t)q + 3 * k;
+            double d0 = (double)vk[0] - P[0], d1 = (double)vk[1] - P[1], d2 = (double)vk[2] - P[2];
+            for (int r = 0; r < 3; r++)
+                c[k][r] = fma(R[3 * r + 2], d2, fma(R[3 * r + 1], d1, R[3 * r + 0] * d0));
+        }
+        /* near plane */
+        int near = 0;
+        for (int k = 0; k < 4; k++)
+            if (!(c[k][2] > znear))
+                near = 1;
+        if (near) {
+            cull[q] = LRO_NEAR;
+            continue;
+        }
+        /* projection and guard band */
+        double sx[4], sy[4];
+        int guard = 0;
+        for (int k = 0; k < 4; k++) {
+            double qx = c[k][0] / c[k][2];
+            double qy = c[k][1] / c[k][2];
+            sx[k] = fma(f, qx, cx);
+            sy[k] = fma(-f, qy, cy);
+            if (!(fabs(sx[k]) < 32768.0) || !(fabs(sy[k]) < 32768.0))
+                guard = 1;
+        }
+        if (guard) {
+            cull[q] = LRO_GUARD;
+            continue;
+        }
+        /* snap to the 1/256 pixel grid */
+        for (int k = 0; k < 4; k++) {
+            x[k] = (int32_t)rint(sx[k] * 256.0);
+            y[k] = (int32_t)rint(sy[k] * 256.0);
+        }
+        /* degenerate: both triangles have zero area */
+        int64_t a0 = edge_fn(x[0], y[0], x[1], y[1], x[2], y[2]);
+        int64_t a1 = edge_fn(x[0], y[0], x[2], y[2], x[3], y[3]);
+        if (a0 == 0 && a1 == 0) {
+            cull[q] = LRO_DEGENERATE;
+            continue;
+        }
+        /* pixel bounding box of the sample points inside the vertex bounds */
+        int64_t xmin = x[0], xmax = x[0], ymin = y[0], ymax = y[0];
+        for (int k = 1; k < 4; k++) {
+            if (x[k] < xmin) xmin = x[k];
+            if (x[k] > xmax) xmax = x[k];
+            if (y[k] < ymin) ymin = y[k];
+            if (y[k] > ymax) ymax = y[k];
+        }
+        int64_t imin = floordiv256(xmin - 128 + 255), imax = floordiv256(xmax - 128);
+        int64_t jmin = floordiv256(ymin - 128 + 255), jmax = floordiv256(ymax - 128);
+        if (imin < 0) imin = 0;
+        if (jmin < 0) jmin = 0;
+        if (imax > (int64_t)W - 1) imax = (int64_t)W - 1;
+        if (jmax > (int64_t)H - 1) jmax = (int64_t)H - 1;
+        bb[0] = (int32_t)imin; bb[1] = (int32_t)imax; bb[2] = (int32_t)jmin; bb[3] = (int32_t)jmax;
+        if (imin > imax || jmin > jmax) {
+            cull[q] = LRO_NO_SAMPLE;
+            continue;
+        }
+        /* depth plane: normal from the diagonals, through the centroid */
+        double e1[3], e2[3], nn[3], m[3];
+        for (int r = 0; r < 3; r++) {
+            e1[r] = c[2][r] - c[0][r];
+            e2[r] = c[3][r] - c[1][r];
+        }
+        {
+            double p, s;
+            p = e1[1] * e2[2]; s = e1[2] * e2[1]; nn[0] = p - s;
+            p = e1[2] * e2[0]; s = e1[0] * e2[2]; nn[1] = p - s;
+            p = e1[0] * e2[1]; s = e1[1] * e2[0]; nn[2] = p - s;
+        }
+        for (int r = 0; r < 3; r++)
+            m[r] = ((c[0][r] + c[1][r]) + (c[2][r] + c[3][r])) * 0.25;
+        double dd = (nn[0] * m[0] + nn[1] * m[1]) + nn[2] * m[2];
+        if (dd == 0.0 || !isfinite(dd)) {
+            cull[q] = LRO_EDGE_ON;
+            continue;
+        }
+        double g = f * dd;
+        double a = nn[0] / g;
+        double b = (-nn[1]) / g;
+        double u0 = ((double)imin + 0.5) - cx;
+        double w0 = ((double)jmin + 0.5) - cy;
+        double t1 = nn[0] * u0, t2 = nn[1] * w0;
+        double c0 = ((t1 - t2) + nn[2] * f) / g;
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c0)) {
+            cull[q] = LRO_EDGE_ON;
+            continue;
+        }
+        A[q] = a; B[q] = b; C0[q] = c0;
+        cull[q] = LRO_VISIBLE;
+    }
+}
+
+/* Depth key of quad q at pixel (i, j): larger is nearer, never negative. */
+float lro_key(double a, double b, double c0, const int32_t *bb, int32_t i, int32_t j)
+{
+    double v = fma(a, (double)(i - bb[0]), fma(b, (double)(j - bb[2]), c0));
+    float k = (float)v;
+    if (!(k > 0.0f))
+        k = 0.0f;
+    return k;
+}
+
+static uint64_t order_key(float k, uint32_t id)
+{
+    uint32_t bits;
+    memcpy(&bits, &k, 4);
+    return ((uint64_t)(~bits) << 32) | (uint64_t)id;
+}
+
+typedef struct {
+    uint64_t key;
+    uint32_t rgba;
+} frag_t;
+
+static int cmp_frag(const void *pa, const void *pb)
+{
+    uint64_t a = ((const frag_t *)pa)->key, b = ((const frag_t *)pb)->key;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Front-to-back blend of fragments already in order. */
+static void blend_front_to_back(const frag_t *fr, uint32_t cnt, double out[4])
+{
+    double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+    for (uint32_t k = 0; k < cnt; k++) {
+        uint32_t c = fr[k].rgba;
+        double a = (double)(c >> 24) / 255.0;
+        double w = T * a;
+        for (int ch = 0; ch < 3; ch++)
+            C[ch] = C[ch] + w * ((double)((c >> (8 * ch)) & 255u) / 255.0);
+        T = T * (1.0 - a);
+    }
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
+}
+
+/* "Over" blend in quad index order (the unsorted baseline). */
+static void blend_over(const frag_t *fr, uint32_t cnt, double out[4])
+{
+    double C[3] = {0.0, 0.0, 0.0}, al = 0.0;
+    for (uint32_t k = 0; k < cnt; k++) {
+        uint32_t c = fr[k].rgba;
+        double a = (double)(c >> 24) / 255.0;
+        for (int ch = 0; ch < 3; ch++)
+            C[ch] = a * ((double)((c >> (8 * ch)) & 255u) / 255.0) + (1.0 - a) * C[ch];
+        al = a + (1.0 - a) * al;
+    }
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = al;
+}
+
+static uint8_t to_u8(double x)
+{
+    double y = floor(255.0 * x + 0.5);
+    if (y < 0.0) y = 0.0;
+    if (y > 255.0) y = 255.0;
+    return (uint8_t)y;
+}
+
+/*
+ * Whole-frame render.  Per pixel it gathers every covering visible quad,
+ * orders the fragments (sorted, or quad index order when unsorted != 0) and
+ * blends them.  Outputs: rgba_f64[H][W][4], rgba8[H][W][4], count[H][W],
+ * order_offsets[W*H+1] and order_ids[...] (fragment quad indices in blend
+ * order; pass NULL to skip).  Returns the total number of fragments, or -1 on
+ * allocation failure.
+ */
+int64_t lro_render(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
+                   const double *A, const double *B, const double *C0, const uint8_t *cull,
+                   const uint32_t *rgba, uint32_t W, uint32_t H, int unsorted, double *rgba_f64,
+                   uint8_t *rgba8, uint32_t *count, uint64_t *order_offsets, uint32_t *order_ids)
+{
+    const size_t npix = (size_t)W * H;
+    uint64_t *off = (uint64_t *)calloc(npix + 1, sizeof(uint64_t));
+    if (!off)
+        return -1;
+    memset(count, 0, npix * sizeof(uint32_t));
+    /* pass 1: fragment count per pixel */
+    for (uint32_t q = 0; q < n; q++) {
+        if (cull[q] != LRO_VISIBLE)
+            continue;
+        const int32_t *bb = bbox + 4 * (size_t)q;
+        for (int32_t j = bb[2]; j <= bb[3]; j++)
+            for (int32_t i = bb[0]; i <= bb[1]; i++)
+                if (lro_covers(X + 4 * (size_t)q, Y + 4 * (size_t)q, i, j))
+                    count[(size_t)j * W + i]++;
+    }
+    for (size_t p = 0; p < npix; p++)
+        off[p + 1] = off[p] + count[p];
+    const uint64_t total = off[npix];
+    frag_t *fr = (frag_t *)malloc((total ? total : 1) * sizeof(frag_t));
+    uint64_t *fill = (uint64_t *)malloc((npix ? npix : 1) * sizeof(uint64_t));
+    if (!fr || !fill) {
+        free(off); free(fr); free(fill);
+        return -1;
+    }
+    memcpy(fill, off, npix * sizeof(uint64_t));
+    /* pass 2: fragments, appended in quad index order */
+    for (uint32_t q = 0; q < n; q++) {
+        if (cull[q] != LRO_VISIBLE)
+            continue;
+        const int32_t *bb = bbox + 4 * (size_t)q;
+        for (int32_t j = bb[2]; j <= bb[3]; j++)
+            for (int32_t i = bb[0]; i <= bb[1]; i++)
+                if (lro_covers(X + 4 * (size_t)q, Y + 4 * (size_t)q, i, j)) {
+                    size_t p = (size_t)j * W + i;
+                    float k = lro_key(A[q], B[q], C0[q], bb, i, j);
+                    fr[fill[p]].key = order_key(k, q);
+                    fr[fill[p]].rgba = rgba[q];
+                    fill[p]++;
+                }
+    }
+    /* per pixel: order and blend */
+    for (size_t p = 0; p < npix; p++) {
+        frag_t *pf = fr + off[p];
+        uint32_t cnt = count[p];
+        double o[4];
+        if (unsorted) {
+            blend_over(pf, cnt, o);
+        } else {
+            qsort(pf, cnt, sizeof(frag_t), cmp_frag);
+            blend_front_to_back(pf, cnt, o);
+        }
+        for (int ch = 0; ch < 4; ch++) {
+            if (rgba_f64) rgba_f64[4 * p + ch] = o[ch];
+            if (rgba8) rgba8[4 * p + ch] = to_u8(o[ch]);
+        }
+    }
+    if (order_offsets)
+        memcpy(order_offsets, off, (npix + 1) * sizeof(uint64_t));
+    if (order_ids)
+        for (uint64_t t = 0; t < total; t++)
+            order_ids[t] = (uint32_t)(fr[t].key & 0xffffffffu);
+    free(fr); free(fill); free(off);
+    return (int64_t)total;
+}
+
+/*
+ * The same result for a list of pixels, each computed on its own by testing
+ * every visible quad (used where a whole frame would take too long).
+ * pix[k] = j * W + i.  Outputs per pixel: rgba_f64[k][4], count[k] and, when
+ * ids != NULL, offsets[npix+1] / ids[<= ids_cap] in blend order.  Returns
+ * the number of fragments over all listed pixels, or -1 when ids_cap is too
+ * small or memory runs out.
+ */
+int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
+                   const double *A, const double *B, const double *C0, const uint8_t *cull,
+                   const uint32_t *rgba, uint32_t W, int unsorted, uint32_t npix,
+                   const uint32_t *pix, double *rgba_f64, uint32_t *count, uint64_t *offsets,
+                   uint32_t *ids, uint64_t ids_cap)
+{
+    size_t cap = 1024;
+    frag_t *fr = (frag_t *)malloc(cap * sizeof(frag_t));
+    if (!fr)
+        return -1;
+    uint64_t total = 0;
+    if (offsets)
+        offsets[0] = 0;
+    for (uint32_t k = 0; k < npix; k++) {
+        int32_t i = (int32_t)(pix[k] % W), j = (int32_t)(pix[k] / W);
+        uint32_t cnt = 0;
+        for (uint32_t q = 0; q < n; q++) {
+            if (cull[q] != LRO_VISIBLE)
+                continue;
+            const int32_t *bb = bbox + 4 * (size_t)q;
+            if (i < bb[0] || i > bb[1] || j < bb[2] || j > bb[3])
+                continue;
+            if (!lro_covers(X + 4 * (size_t)q, Y + 4 * (size_t)q, i, j))
+                continue;
+            if (cnt == cap) {
+                cap *= 2;
+                frag_t *nf = (frag_t *)realloc(fr, cap * sizeof(frag_t));
+                if (!nf) {
+                    free(fr);
+                    return -1;
+                }
+                fr = nf;
+            }
+            fr[cnt].key = order_key(lro_key(A[q], B[q], C0[q], bb, i, j), q);
+            fr[cnt].rgba = rgba[q];
+            cnt++;
+        }
+        double o[4];
+        if (unsorted) {
+            blend_over(fr, cnt, o);
+        } else {
+            qsort(fr, cnt, sizeof(frag_t), cmp_frag);
+            blend_front_to_back(fr, cnt, o);
+        }
+        for (int ch = 0; ch < 4; ch++)
+            rgba_f64[4 * (size_t)k + ch] = o[ch];
+        count[k] = cnt;
+        if (ids) {
+            if (total + cnt > ids_cap) {
+                free(fr);
+                return -1;
+            }
+            for (uint32_t t = 0; t < cnt; t++)
+                ids[total + t] = (uint32_t)(fr[t].key & 0xffffffffu);
+        }
+        total += cnt;
+        if (offsets)
+            offsets[k + 1] = total;
+    }
+    free(fr);
+    return (int64_t)total;
+}
+
+/*
+ * Bounding-box binning (Stage 2, phase 1 counts small quads by their AABB):
+ * bin (bx, by) of size s lists, in ascending quad index, every visible quad
+ * whose pixel bounding box overlaps it.  counts[nbx*nby]; when ids != NULL,
+ * offsets[nbins+1] and ids[] are filled (ids_cap entries at most).  Returns
+ * the number of (bin, quad) pairs or -1 when ids_cap is too small.
+ */
+int64_t lro_bins(uint32_t n, const int32_t *bbox, const uint8_t *cull, uint32_t W, uint32_t H,
+                 uint32_t s, uint32_t *counts, uint64_t *offsets, uint32_t *ids, uint64_t ids_cap)
+{
+    uint32_t nbx = (W + s - 1) / s, nby = (H + s - 1) / s;
+    size_t nbins = (size_t)nbx * nby;
+    memset(counts, 0, nbins * sizeof(uint32_t));
+    for (uint32_t q = 0; q < n; q++) {
+        if (cull[q] != LRO_VISIBLE)
+            continue;
+        const int32_t *bb = bbox + 4 * (size_t)q;
+        for (int32_t by = bb[2] / (int32_t)s; by <= bb[3] / (int32_t)s; by++)
+            for (int32_t bx = bb[0] / (int32_t)s; bx <= bb[1] / (int32_t)s; bx++)
+                counts[(size_t)by * nbx + bx]++;
+    }
+    uint64_t total = 0;
+    for (size_t b = 0; b < nbins; b++)
+        total += counts[b];
+    if (!ids)
+        return (int64_t)total;
+    if (total > ids_cap)
+        return -1;
+    offsets[0] = 0;
+    for (size_t b = 0; b < nbins; b++)
+        offsets[b + 1] = offsets[b] + counts[b];
+    uint64_t *fill = (uint64_t *)malloc((nbins ? nbins : 1) * sizeof(uint64_t));
+    if (!fill)
+        return -1;
+    memcpy(fill, offsets, nbins * sizeof(uint64_t));
+    for (uint32_t q = 0; q < n; q++) {
+        if (cull[q] != LRO_VISIBLE)
+            continue;
+        const int32_t *bb = bbox + 4 * (size_t)q;
+        for (int32_t by = bb[2] / (int32_t)s; by <= bb[3] / (int32_t)s; by++)
+            for (int32_t bx = bb[0] / (int32_t)s; bx <= bb[1] / (int32_t)s; bx++)
+                ids[fill[(size_t)by * nbx + bx]++] = q;
+    }
+    free(fill);
+    return (int64_t)total;
+}
