@@ -1,0 +1,199 @@
+/*
+ * lucidraster.h -- C ABI of an MI355X (gfx950) software rasterizer for exact
+ * order-independent transparency of planar quads, after "LucidRaster: GPU
+ * Software Rasterizer for Exact Order-Independent Transparency"
+ * (K. Jakubowski, arXiv 2405.13364).
+ *
+ * The problem (paper, Section 1): for every pixel, find every fragment that
+ * contributes to it, sort the fragments by depth and blend them in order.
+ * The pipeline follows Section 2: quad setup (Stage 1), binning into
+ * screen-space bins by prefix sums (Stage 2), and bin rasterization with a
+ * two-stage sort -- depth-sorted blocks of fragments refined by a per-pixel
+ * fixed-size sorter -- and front-to-back blending (Stage 3).  Unlike the
+ * paper, pixels whose per-pixel sorter would emit fragments out of order are
+ * detected exactly and recomputed by a full per-pixel sort, so every image is
+ * exact (Stage 3, "Sample blending", describes the detection; the paper
+ * leaves such pixels unfixed).
+ *
+ * Conventions (numeric readings of the paper, stated once here):
+ *   - camera space c = R (v - pos); the camera looks down +z, y up; screen x
+ *     points right, y down; f = (H/2) / tan(fov_y/2) is computed on the host;
+ *   - vertices are snapped to a 1/256-pixel grid; pixel (i, j) samples its
+ *     centre; a quad covers a sample when one of its triangles (P0,P1,P2),
+ *     (P0,P2,P3) does, under a top-left fill rule; one fragment per quad;
+ *   - depth order: reciprocal view depth from the plane through the vertex
+ *     centroid normal to the diagonals, evaluated in fp64 and rounded to
+ *     fp32; nearer first, ties by ascending quad index;
+ *   - blending: front to back from transparent black, fp32; the output is
+ *     premultiplied RGBA8 (rounded half up).
+ *
+ * Memory: the caller owns all device memory.  lr_create takes a device arena
+ * the library sub-allocates from (it calls no hipMalloc when an arena is
+ * given); render outputs are device pointers.  Every call returns an
+ * lr_status; no exception or abort crosses the ABI; outputs are only written
+ * on LR_OK.  Rendering calls are asynchronous on the given HIP stream; errors
+ * found by kernels (capacity overflow) are latched in the context and
+ * reported by the next lr_sync / lr_get_stats.
+ */
+#ifndef LUCIDRASTER_H
+#define LUCIDRASTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lr_status;
+#define LR_OK 0
+#define LR_ERR_INVALID_ARG -1   /* a NULL pointer, zero size, size out of range */
+#define LR_ERR_OUT_OF_MEMORY -2 /* the arena cannot hold the request */
+#define LR_ERR_DEVICE -3        /* a HIP call failed (text in lr_last_error) */
+#define LR_ERR_CAPACITY -4      /* a frame overflowed a device capacity; re-render */
+#define LR_ERR_NOT_FOUND -5     /* unknown scene handle */
+#define LR_ERR_BUSY -6          /* the context is in use by another thread */
+
+typedef struct lr_context_s *lr_context;
+typedef uint64_t lr_scene; /* 0 is never a valid handle */
+
+/* One input quad: four world-space vertices and one straight-alpha RGBA8
+ * colour (R in the low byte).  52 bytes, packed.  A quad's index in the
+ * uploaded array is its id (the depth tie-break). */
+#pragma pack(push, 4)
+typedef struct {
+    float v[4][3];
+    uint32_t rgba;
+} lr_quad;
+#pragma pack(pop)
+
+/* Pinhole camera: rows of rot are the camera x, y, z axes in world space. */
+typedef struct {
+    float pos[3];
+    float rot[3][3];
+    float fov_y;  /* radians */
+    float z_near; /* quads with any vertex at view depth <= z_near are culled */
+} lr_camera;
+
+/* Context configuration.  Zero fields take defaults. */
+typedef struct {
+    int32_t device;           /* HIP device ordinal */
+    void *stream;             /* default hipStream_t for calls given NULL */
+    void *arena;              /* device memory owned by the caller, or NULL */
+    uint64_t arena_bytes;     /* arena size; with arena == NULL the library
+                                 allocates this much once (default 1 GiB) */
+    uint32_t bin_size;        /* 16, 32 (default) or 64 pixels */
+    uint32_t block_h;         /* 8: 8x8 blocks (default); 4: 8x4 half-blocks */
+    uint32_t sorter_depth;    /* per-pixel sorter capacity K, 2..32 (default 8) */
+    uint32_t flags;           /* LR_FLAG_* */
+    uint64_t hbm_budget_bytes;/* serving admission budget (0: arena size) */
+} lr_config;
+
+#define LR_FLAG_TIMING 1u     /* record per-stage times (hipEvents) */
+
+/* Statistics of the last completed render on the context. */
+typedef struct {
+    uint64_t quads;           /* input quads */
+    uint64_t visible;         /* quads that passed setup */
+    uint64_t culled[6];       /* [1] near [2] guard band [3] degenerate
+                                 [4] no sample [5] edge-on plane */
+    uint64_t bin_pairs;       /* (bin, quad) pairs written by binning */
+    uint64_t block_entries;   /* non-empty (block, quad) pairs */
+    uint64_t fragments;       /* covered (pixel, quad) pairs */
+    uint64_t flagged_pixels;  /* pixels recomputed by the exact per-pixel sort */
+    uint64_t dense_blocks;    /* blocks whose lists exceeded the on-chip list */
+    uint32_t error_word;      /* device error bits (0: none) */
+    uint32_t reserved;
+    float stage_us[8];        /* setup, bin count, bin scan, bin scatter,
+                                 raster, dense raster, fallback, total */
+} lr_stats;
+
+/* A request for lr_render_batch. */
+typedef struct {
+    lr_scene scene;
+    lr_camera camera;
+    uint32_t width, height;
+    uint8_t *out_rgba8;       /* device, width*height*4 bytes */
+    uint32_t bin_size;        /* 0: context default */
+    uint32_t sorter_depth;    /* 0: context default */
+} lr_request;
+
+/* Human-readable name of a status code (static storage). */
+const char *lr_status_string(lr_status s);
+
+/* Last error message of the context (or of the process when ctx is NULL). */
+const char *lr_last_error(lr_context ctx);
+
+/* Create a context on cfg->device.  Fails with LR_ERR_INVALID_ARG for a bad
+ * config, LR_ERR_DEVICE when HIP is unavailable. */
+lr_status lr_create(const lr_config *cfg, lr_context *out);
+
+/* Wait for the context's work and free its host state (and the arena the
+ * library allocated itself, if any).  Caller memory is left untouched. */
+lr_status lr_destroy(lr_context ctx);
+
+/* Make quads resident on the device (A1 of the path: off the per-frame work).
+ * q points to n lr_quad records in host memory (q_on_device == 0) or device
+ * memory (q_on_device != 0).  The data is copied and transposed into the
+ * arena; q may be freed when the call returns.  1 <= n <= 2^24.  Stream
+ * ordered on the context stream. */
+lr_status lr_upload_scene(lr_context ctx, const lr_quad *q, uint32_t n, int q_on_device,
+                          lr_scene *out);
+
+/* Return a scene's arena space (after the context stream drains). */
+lr_status lr_release_scene(lr_context ctx, lr_scene scene);
+
+/* Render a scene into out_rgba8 (device, width*height*4 bytes, row-major, top
+ * row first, premultiplied RGBA8).  1 <= width, height <= 16384.  Runs on
+ * stream (NULL: the context stream) and returns without waiting. */
+lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                    uint32_t height, uint8_t *out_rgba8, void *stream);
+
+/* Same render, plus parity artefacts (each may be NULL):
+ *   rgba_f32  [H][W][4] fp32 premultiplied colour before rounding;
+ *   counts    [H][W] fragments per pixel;
+ *   flagged   [H][W] 1 where the per-pixel sorter detected an order
+ *             violation (those pixels were recomputed exactly);
+ *   order_offsets [W*H+1] (input, e.g. the exclusive scan of counts) and
+ *   order_ids [order_cap]: quad ids of each pixel in blend order. */
+lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                          uint32_t height, uint8_t *out_rgba8, void *stream, float *rgba_f32,
+                          uint32_t *counts, uint8_t *flagged, const uint32_t *order_offsets,
+                          uint32_t *order_ids, uint32_t order_cap);
+
+/* The unsorted baseline: the same setup and binning, then per pixel the
+ * covering quads blended in quad order with the "over" operator (fp32), as
+ * hardware alpha blending would without sorting (Section 3, "Performance
+ * results").  rgba_f32 may be NULL. */
+lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                             uint32_t height, uint8_t *out_rgba8, void *stream, float *rgba_f32);
+
+/* Render n requests back to back on one stream (uneven sizes allowed);
+ * every output is bit-identical to the corresponding lr_render. */
+lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, void *stream);
+
+/* Wait for all work the context issued; report a latched kernel error
+ * (LR_ERR_CAPACITY) and clear it. */
+lr_status lr_sync(lr_context ctx);
+
+/* Wait, then fill *out with the statistics of the last render. */
+lr_status lr_get_stats(lr_context ctx, lr_stats *out);
+
+/* Parity dump of the setup stage for a render configuration (synchronous).
+ * Per quad: X, Y [n][4] snapped vertices; bbox [n][4] (imin, imax, jmin, jmax
+ * of a visible quad); plane [n][3] (A, B, C0); cull [n] (0 visible, else the
+ * reason as in lr_stats.culled).  Host pointers; any may be NULL. */
+lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                         uint32_t height, int32_t *X, int32_t *Y, int32_t *bbox, double *plane,
+                         uint8_t *cull);
+
+/* Parity dump of binning (synchronous): per-bin counts [nbins] and, when ids
+ * is not NULL, the concatenated per-bin lists of quad ids (ids_cap entries at
+ * most; *total receives the number of pairs). */
+lr_status lr_debug_bins(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                        uint32_t height, uint32_t bin_size, uint32_t *counts, uint32_t *ids,
+                        uint64_t ids_cap, uint64_t *total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LUCIDRASTER_H */

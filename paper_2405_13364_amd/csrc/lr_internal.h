@@ -1,0 +1,122 @@
+// Internal layouts shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lr {
+
+// Cull reasons, in the order the setup stage tests them.
+enum Cull : uint8_t { VISIBLE = 0, NEAR = 1, GUARD = 2, DEGENERATE = 3, NO_SAMPLE = 4, EDGE_ON = 5 };
+
+// Quads whose snapped vertex extent stays within 2^18 sub-pixel units (1024
+// px) in x and y use 32-bit half-plane tests; wider quads take an exact fp64
+// path.  Bound: |a*di + b*dj| <= 2*ext^2/256 + 16*ext < 2^30 for ext <= 2^18.
+constexpr int32_t kNarrowExtent = 1 << 18;
+
+// Per visible quad, everything the raster stage reads for one candidate, in
+// one 128-byte record (one L2 line, loaded with scalar loads per candidate).
+//
+// Half-plane h of triangle T (h = 3T + e) holds (a, b, t): the sample of pixel
+// (imin + di, jmin + dj) is inside edge e iff a*di + b*dj >= t.  A zero-area
+// triangle stores (0, 0, 1), which no sample satisfies.  This is the
+// top-left rule made integral: with E the edge function in sub-pixel units
+// and R the sample of pixel (imin, jmin), E(S) = E(R) + 256 (a di + b dj), and
+// E(S) >= bias (bias 0 on top-left edges, 1 otherwise) iff
+// a di + b dj >= ceil((bias - E(R)) / 256).
+struct alignas(128) QuadRec {
+    int32_t hp[18];   // 6 x (a, b, t)                       bytes 0..71
+    uint32_t bb_i;    // imin | imax << 16                    72
+    uint32_t bb_j;    // jmin | jmax << 16                    76
+    uint32_t rgba;    //                                      80
+    uint32_t flags;   // kWide | triangle bits                84
+    double A, B, C0;  // reciprocal-depth plane (fp64)        88..111
+    float fA, fB, fC0;// the same rounded to fp32 (block keys) 112..123
+    uint32_t pad;     //                                      124
+};
+static_assert(sizeof(QuadRec) == 128, "QuadRec must be one 128-byte line");
+
+constexpr uint32_t kWide = 1u;       // use the fp64 coverage path
+constexpr uint32_t kT0Valid = 2u;    // triangle (P0, P1, P2) has non-zero area
+constexpr uint32_t kT0Swap = 4u;     // ... and is stored as (P0, P2, P1)
+constexpr uint32_t kT1Valid = 8u;    // triangle (P0, P2, P3)
+constexpr uint32_t kT1Swap = 16u;
+
+// Snapped vertices (sub-pixel units) of a quad.
+struct alignas(32) QuadXY {
+    int32_t X[4];
+    int32_t Y[4];
+};
+
+// Device counters of one frame (zeroed by the first kernel of the frame).
+struct FrameCounters {
+    uint32_t visible;
+    uint32_t cull[6];
+    uint32_t pairs_total;      // (bin, quad) pairs found by the scan
+    uint32_t error;            // kErr* bits
+    uint32_t flagged;          // pixels queued for the exact per-pixel sort
+    uint32_t dense;            // blocks queued for the dense list path
+    uint32_t pad;
+    unsigned long long entries;    // non-empty (block, quad) pairs
+    unsigned long long fragments;  // covered samples
+};
+
+constexpr uint32_t kErrPairs = 1u;      // bin lists overflowed their capacity
+constexpr uint32_t kErrFallback = 2u;   // a pixel had more fragments than the exact sort holds
+constexpr uint32_t kErrDense = 4u;      // a dense block overflowed the dense list (pixels sent to the exact sort)
+
+// Everything one frame's kernels need (passed by value).
+struct FrameArgs {
+    // scene (SoA): v[(k*3 + r) * n + q] for vertex k, component r; rgba[n]
+    const float *v;
+    const uint32_t *rgba_in;
+    uint32_t n;
+    // camera
+    float pos[3];
+    float rot[9];
+    float z_near;
+    double f, cx, cy;
+    uint32_t W, H;
+    // setup outputs
+    QuadRec *rec;
+    QuadXY *xy;
+    uint2 *bbox;      // (imin | imax << 16, jmin | jmax << 16); culled: (0xffff, 0xffff)
+    uint8_t *cull;
+    // binning
+    uint32_t bin_shift;     // log2(bin size)
+    uint32_t nbx, nby, nbins;
+    uint32_t unit_quads;    // quads per binning unit (multiple of 64)
+    uint32_t nunits;
+    uint32_t ntiles;        // ceil(nunits / 64)
+    uint32_t *table;        // [nunits][nbins]
+    uint32_t *tile_sums;    // [ntiles][nbins]
+    uint32_t *bin_start;    // [nbins + 1]
+    uint32_t *bin_count;    // [nbins]
+    uint32_t *pairs;        // [pair_cap]
+    uint32_t pair_cap;
+    uint32_t match_bits;    // bits needed to hold a bin index
+    // raster
+    uint32_t nblk_x, nblk_y;  // 8x8 blocks
+    uint32_t *fb_queue;       // flagged pixel indices [W*H]
+    uint32_t *dense_queue;    // dense block indices [nblk_x*nblk_y]
+    FrameCounters *ctr;
+    uint8_t *out;             // RGBA8
+    // debug outputs (may be null)
+    float *dbg_rgba;
+    uint32_t *dbg_count;
+    uint8_t *dbg_flag;
+    const uint32_t *dbg_off;
+    uint32_t *dbg_ids;
+    uint32_t dbg_cap;
+};
+
+// Kernel launches (lr_kernels.hip).
+hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s,
+                        hipEvent_t *ev /* 8 events or null */);
+hipError_t launch_setup_only(const FrameArgs &a, hipStream_t s);
+hipError_t launch_binning_only(const FrameArgs &a, hipStream_t s);
+hipError_t launch_transpose_scene(const void *quads_dev, uint32_t n, float *v, uint32_t *rgba,
+                                  hipStream_t s);
+bool sorter_depth_supported(int k);
+
+}  // namespace lr

@@ -1,0 +1,1233 @@
+// gfx950 kernels of the exact-transparency rasterizer.
+//
+// Stages (paper Section 2, "Pipeline description"):
+//   setup    one lane per quad: cull, project, snap, bbox, half-planes, depth
+//            plane (Stage 1);
+//   binning  per-bin lists of quad indices by counting, prefix sums and a
+//            stable scatter, so every list is in ascending quad index (Stage 2);
+//   raster   one wave per 8x8 block of a bin: coverage masks of the bin's
+//            quads, a block-level depth sort, then one lane per pixel walks
+//            the sorted entries through a K-deep per-pixel sorter and blends
+//            front to back (Stage 3).  A pixel whose sorter would emit an
+//            out-of-order fragment is detected and recomputed by an exact
+//            per-pixel sort.
+// The exactness contract: coverage and fragment keys are integer or exactly
+// specified IEEE operations (built with -ffp-contract=off; fma only where
+// written), and every pixel's blend sequence is its fragments in ascending
+// (~bits(key), quad index) order.
+#include "lr_internal.h"
+
+#include <math.h>
+
+namespace lr {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of m in lanes below this one.
+__device__ __forceinline__ uint32_t rank_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t lane)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+
+__device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m)
+{
+    return (uint32_t)__shfl_xor((int)v, m, 64);
+}
+
+// Transpose a 64x64 bit matrix held one row per lane (lane e holds row e as
+// lo | hi << 32).  Afterwards lane p holds column p: bit e set iff row e has
+// bit p.  Each level swaps one bit of the row index with the same bit of the
+// column index.
+__device__ __forceinline__ uint64_t transpose64(uint64_t m, uint32_t lane)
+{
+    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+    {
+        const bool up = lane & 32;
+        uint32_t recv = shfl_xor(up ? lo : hi, 32);
+        if (up)
+            lo = recv;
+        else
+            hi = recv;
+    }
+#define LR_TRANSPOSE_LEVEL(S, MASK)                                                  \
+    {                                                                                \
+        const bool up = lane & (S);                                                  \
+        uint32_t plo = shfl_xor(lo, (S)), phi = shfl_xor(hi, (S));                   \
+        lo = up ? ((lo & ~(MASK)) | ((plo >> (S)) & (MASK))) : ((lo & (MASK)) | ((plo & (MASK)) << (S))); \
+        hi = up ? ((hi & ~(MASK)) | ((phi >> (S)) & (MASK))) : ((hi & (MASK)) | ((phi & (MASK)) << (S))); \
+    }
+    LR_TRANSPOSE_LEVEL(16, 0x0000FFFFu)
+    LR_TRANSPOSE_LEVEL(8, 0x00FF00FFu)
+    LR_TRANSPOSE_LEVEL(4, 0x0F0F0F0Fu)
+    LR_TRANSPOSE_LEVEL(2, 0x33333333u)
+    LR_TRANSPOSE_LEVEL(1, 0x55555555u)
+#undef LR_TRANSPOSE_LEVEL
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Fragment order code: ascending code = nearer first (the high word of the
+// total order; the quad index is the low word).  k >= +0 always.
+__device__ __forceinline__ float frag_key(double A, double B, double C0, int di, int dj)
+{
+    double v = fma(A, (double)di, fma(B, (double)dj, C0));
+    float k = (float)v;
+    return (k > 0.0f) ? k : 0.0f;
+}
+
+__device__ __forceinline__ uint32_t order_code(float k) { return ~__float_as_uint(k); }
+
+// Front-to-back blend step (fp32), shared by every sorted path so that their
+// results are bit-identical.
+__device__ __forceinline__ void blend_ftb(uint32_t c, float &T, float &R, float &G, float &B)
+{
+    const float s = 1.0f / 255.0f;
+    float a = (float)(c >> 24) * s;
+    float w = T * a;
+    R = fmaf(w, (float)(c & 255u) * s, R);
+    G = fmaf(w, (float)((c >> 8) & 255u) * s, G);
+    B = fmaf(w, (float)((c >> 16) & 255u) * s, B);
+    T = T * (1.0f - a);
+}
+
+// "Over" step of the unsorted baseline (fp32).
+__device__ __forceinline__ void blend_over(uint32_t c, float &R, float &G, float &B, float &Al)
+{
+    const float s = 1.0f / 255.0f;
+    float a = (float)(c >> 24) * s;
+    float om = 1.0f - a;
+    R = fmaf(a, (float)(c & 255u) * s, om * R);
+    G = fmaf(a, (float)((c >> 8) & 255u) * s, om * G);
+    B = fmaf(a, (float)((c >> 16) & 255u) * s, om * B);
+    Al = fmaf(om, Al, a);
+}
+
+__device__ __forceinline__ uint32_t to_u8(float x)
+{
+    float y = floorf(x * 255.0f + 0.5f);
+    y = fminf(fmaxf(y, 0.0f), 255.0f);
+    return (uint32_t)y;
+}
+
+__device__ __forceinline__ uint32_t pack_rgba8(float R, float G, float B, float A)
+{
+    return to_u8(R) | (to_u8(G) << 8) | (to_u8(B) << 16) | (to_u8(A) << 24);
+}
+
+// ------------------------------------------------------------- frame begin
+
+__global__ void k_frame_begin(FrameCounters *c)
+{
+    uint32_t *p = reinterpret_cast<uint32_t *>(c);
+    for (uint32_t i = threadIdx.x; i < sizeof(FrameCounters) / 4; i += blockDim.x)
+        p[i] = 0;
+}
+
+// ------------------------------------------------------------------- setup
+
+__device__ __forceinline__ int64_t edge_fn(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px,
+                                           int64_t py)
+{
+    return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+// Half-planes of triangle (ia, ib, ic) relative to sample R = (Rx, Ry).
+__device__ void tri_halfplanes(const int32_t *X, const int32_t *Y, int ia, int ib, int ic, int64_t Rx,
+                               int64_t Ry, int32_t *hp, uint32_t &flags, uint32_t valid_bit,
+                               uint32_t swap_bit)
+{
+    int64_t vx[3] = {X[ia], X[ib], X[ic]}, vy[3] = {Y[ia], Y[ib], Y[ic]};
+    int64_t area2 = edge_fn(vx[0], vy[0], vx[1], vy[1], vx[2], vy[2]);
+    if (area2 == 0) {
+        for (int e = 0; e < 3; e++) {
+            hp[3 * e] = 0;
+            hp[3 * e + 1] = 0;
+            hp[3 * e + 2] = 1;
+        }
+        return;
+    }
+    flags |= valid_bit;
+    if (area2 < 0) {
+        flags |= swap_bit;
+        int64_t tx = vx[1], ty = vy[1];
+        vx[1] = vx[2]; vy[1] = vy[2];
+        vx[2] = tx; vy[2] = ty;
+    }
+    for (int e = 0; e < 3; e++) {
+        int64_t sx = vx[e], sy = vy[e], ex = vx[(e + 1) % 3], ey = vy[(e + 1) % 3];
+        int64_t dx = ex - sx, dy = ey - sy;
+        bool top_left = (dy < 0) || (dy == 0 && dx > 0);
+        int64_t er = dx * (Ry - sy) - dy * (Rx - sx);
+        int64_t num = (top_left ? 0 : 1) - er;
+        int64_t t = -((-num) >> 8);  // ceil(num / 256)
+        if (t > INT32_MAX) t = INT32_MAX;
+        if (t < INT32_MIN) t = INT32_MIN;
+        hp[3 * e] = (int32_t)(-dy);
+        hp[3 * e + 1] = (int32_t)dx;
+        hp[3 * e + 2] = (int32_t)t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_setup(FrameArgs a)
+{
+    const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+    uint32_t reason = 0xff;
+    if (q < a.n) {
+        const uint32_t n = a.n;
+        double c[4][3];
+        for (int k = 0; k < 4; k++) {
+            double d0 = (double)a.v[(k * 3 + 0) * (size_t)n + q] - (double)a.pos[0];
+            double d1 = (double)a.v[(k * 3 + 1) * (size_t)n + q] - (double)a.pos[1];
+            double d2 = (double)a.v[(k * 3 + 2) * (size_t)n + q] - (double)a.pos[2];
+            for (int r = 0; r < 3; r++)
+                c[k][r] = fma((double)a.rot[3 * r + 2], d2,
+                              fma((double)a.rot[3 * r + 1], d1, (double)a.rot[3 * r + 0] * d0));
+        }
+        uint2 bb = make_uint2(0xffffu, 0xffffu);
+        bool near = false;
+        for (int k = 0; k < 4; k++)
+            if (!(c[k][2] > (double)a.z_near))
+                near = true;
+        if (near) {
+            reason = NEAR;
+        } else {
+            double sx[4], sy[4];
+            bool guard = false;
+            for (int k = 0; k < 4; k++) {
+                double qx = c[k][0] / c[k][2];
+                double qy = c[k][1] / c[k][2];
+                sx[k] = fma(a.f, qx, a.cx);
+                sy[k] = fma(-a.f, qy, a.cy);
+                if (!(fabs(sx[k]) < 32768.0) || !(fabs(sy[k]) < 32768.0))
+                    guard = true;
+            }
+            if (guard) {
+                reason = GUARD;
+            } else {
+                QuadXY xy;
+                for (int k = 0; k < 4; k++) {
+                    xy.X[k] = (int32_t)rint(sx[k] * 256.0);
+                    xy.Y[k] = (int32_t)rint(sy[k] * 256.0);
+                }
+                a.xy[q] = xy;
+                int64_t a0 = edge_fn(xy.X[0], xy.Y[0], xy.X[1], xy.Y[1], xy.X[2], xy.Y[2]);
+                int64_t a1 = edge_fn(xy.X[0], xy.Y[0], xy.X[2], xy.Y[2], xy.X[3], xy.Y[3]);
+                if (a0 == 0 && a1 == 0) {
+                    reason = DEGENERATE;
+                } else {
+                    int64_t xmin = xy.X[0], xmax = xy.X[0], ymin = xy.Y[0], ymax = xy.Y[0];
+                    for (int k = 1; k < 4; k++) {
+                        xmin = min(xmin, (int64_t)xy.X[k]);
+                        xmax = max(xmax, (int64_t)xy.X[k]);
+                        ymin = min(ymin, (int64_t)xy.Y[k]);
+                        ymax = max(ymax, (int64_t)xy.Y[k]);
+                    }
+                    int64_t imin = (xmin - 128 + 255) >> 8, imax = (xmax - 128) >> 8;
+                    int64_t jmin = (ymin - 128 + 255) >> 8, jmax = (ymax - 128) >> 8;
+                    imin = max(imin, (int64_t)0);
+                    jmin = max(jmin, (int64_t)0);
+                    imax = min(imax, (int64_t)a.W - 1);
+                    jmax = min(jmax, (int64_t)a.H - 1);
+                    if (imin > imax || jmin > jmax) {
+                        reason = NO_SAMPLE;
+                    } else {
+                        double e1[3], e2[3], nn[3], m[3];
+                        for (int r = 0; r < 3; r++) {
+                            e1[r] = c[2][r] - c[0][r];
+                            e2[r] = c[3][r] - c[1][r];
+                        }
+                        {
+                            double p, s;
+                            p = e1[1] * e2[2]; s = e1[2] * e2[1]; nn[0] = p - s;
+                            p = e1[2] * e2[0]; s = e1[0] * e2[2]; nn[1] = p - s;
+                            p = e1[0] * e2[1]; s = e1[1] * e2[0]; nn[2] = p - s;
+                        }
+                        for (int r = 0; r < 3; r++)
+                            m[r] = ((c[0][r] + c[1][r]) + (c[2][r] + c[3][r])) * 0.25;
+                        double dd = (nn[0] * m[0] + nn[1] * m[1]) + nn[2] * m[2];
+                        double g = a.f * dd;
+                        double A = nn[0] / g;
+                        double B = (-nn[1]) / g;
+                        double u0 = ((double)imin + 0.5) - a.cx;
+                        double w0 = ((double)jmin + 0.5) - a.cy;
+                        double t1 = nn[0] * u0, t2 = nn[1] * w0;
+                        double C0 = ((t1 - t2) + nn[2] * a.f) / g;
+                        if (dd == 0.0 || !isfinite(dd) || !isfinite(A) || !isfinite(B) ||
+                            !isfinite(C0)) {
+                            reason = EDGE_ON;
+                        } else {
+                            reason = VISIBLE;
+                            QuadRec r;
+                            uint32_t flags = 0;
+                            if (xmax - xmin > kNarrowExtent || ymax - ymin > kNarrowExtent)
+                                flags |= kWide;
+                            const int64_t Rx = 256 * imin + 128, Ry = 256 * jmin + 128;
+                            tri_halfplanes(xy.X, xy.Y, 0, 1, 2, Rx, Ry, r.hp, flags, kT0Valid, kT0Swap);
+                            tri_halfplanes(xy.X, xy.Y, 0, 2, 3, Rx, Ry, r.hp + 9, flags, kT1Valid,
+                                           kT1Swap);
+                            r.bb_i = (uint32_t)imin | ((uint32_t)imax << 16);
+                            r.bb_j = (uint32_t)jmin | ((uint32_t)jmax << 16);
+                            r.rgba = a.rgba_in[q];
+                            r.flags = flags;
+                            r.A = A;
+                            r.B = B;
+                            r.C0 = C0;
+                            r.fA = (float)A;
+                            r.fB = (float)B;
+                            r.fC0 = (float)C0;
+                            r.pad = 0;
+                            a.rec[q] = r;
+                            bb = make_uint2(r.bb_i, r.bb_j);
+                        }
+                    }
+                }
+            }
+        }
+        a.bbox[q] = bb;
+        a.cull[q] = (uint8_t)reason;
+    }
+    const uint32_t lane = lane_id();
+    for (uint32_t r = 0; r < 6; r++) {
+        uint64_t m = ballot(reason == r);
+        if (m && lane == 0) {
+            if (r == 0)
+                atomicAdd(&a.ctr->visible, (uint32_t)__popcll(m));
+            atomicAdd(&a.ctr->cull[r], (uint32_t)__popcll(m));
+        }
+    }
+}
+
+// ----------------------------------------------------------------- binning
+//
+// The quads are split into units of a.unit_quads consecutive indices; one
+// wave owns a unit.  Count: a per-unit LDS histogram over bins, written as
+// one row of table[unit][bin].  Scan: per bin, an exclusive prefix over
+// units (in tiles of 64), then over bins.  Scatter: the same unit walks its
+// quads in order and ranks equal bins within each group of 64 pairs with
+// ballots, so each bin list ends up in ascending quad index.
+
+__device__ __forceinline__ bool quad_bins(uint2 bb, uint32_t shift, uint32_t &bx0, uint32_t &by0,
+                                          uint32_t &bw, uint32_t &np)
+{
+    uint32_t imin = bb.x & 0xffffu, imax = bb.x >> 16, jmin = bb.y & 0xffffu, jmax = bb.y >> 16;
+    if (imin > imax || jmin > jmax) {
+        np = 0;
+        return false;
+    }
+    bx0 = imin >> shift;
+    by0 = jmin >> shift;
+    bw = (imax >> shift) - bx0 + 1;
+    np = bw * ((jmax >> shift) - by0 + 1);
+    return true;
+}
+
+__global__ __launch_bounds__(64) void k_bin_count(FrameArgs a, const uint2 *__restrict__ bbox)
+{
+    extern __shared__ uint32_t s_hist[];
+    const uint32_t lane = threadIdx.x, u = blockIdx.x;
+    for (uint32_t b = lane; b < a.nbins; b += 64)
+        s_hist[b] = 0;
+    __syncthreads();
+    const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
+    for (uint32_t base = q0; base < q1; base += 64) {
+        uint32_t q = base + lane;
+        if (q < q1) {
+            uint32_t bx0, by0, bw, np;
+            if (quad_bins(bbox[q], a.bin_shift, bx0, by0, bw, np)) {
+                for (uint32_t k = 0; k < np; k++) {
+                    uint32_t by = by0 + k / bw, bx = bx0 + k % bw;
+                    atomicAdd(&s_hist[by * a.nbx + bx], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *row = a.table + (size_t)u * a.nbins;
+    for (uint32_t b = lane; b < a.nbins; b += 64)
+        row[b] = s_hist[b];
+}
+
+// table[u][b] -> exclusive prefix over the units of one tile; tile totals.
+__global__ __launch_bounds__(64) void k_bin_scan_tiles(FrameArgs a)
+{
+    const uint32_t b = blockIdx.x * 64 + threadIdx.x, tile = blockIdx.y;
+    if (b >= a.nbins)
+        return;
+    const uint32_t u0 = tile * 64, u1 = min(u0 + 64, a.nunits);
+    uint32_t run = 0;
+    for (uint32_t u = u0; u < u1; u++) {
+        uint32_t *p = a.table + (size_t)u * a.nbins + b;
+        uint32_t v = *p;
+        *p = run;
+        run += v;
+    }
+    a.tile_sums[(size_t)tile * a.nbins + b] = run;
+}
+
+// Per bin: prefix over tiles and the bin total; then the prefix over bins.
+__global__ __launch_bounds__(1024) void k_bin_scan_final(FrameArgs a)
+{
+    __shared__ uint32_t s_part[1024];
+    const uint32_t t = threadIdx.x;
+    const uint32_t per = (a.nbins + 1023) / 1024;
+    const uint32_t b0 = min(t * per, a.nbins), b1 = min(b0 + per, a.nbins);
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; b++) {
+        uint32_t run = 0;
+        for (uint32_t tile = 0; tile < a.ntiles; tile++) {
+            uint32_t *p = a.tile_sums + (size_t)tile * a.nbins + b;
+            uint32_t v = *p;
+            *p = run;
+            run += v;
+        }
+        a.bin_count[b] = run;
+        sum += run;
+    }
+    s_part[t] = sum;
+    __syncthreads();
+    // inclusive scan of the 1024 per-thread sums (Hillis-Steele)
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint32_t v = (t >= off) ? s_part[t - off] : 0;
+        __syncthreads();
+        s_part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = (t == 0) ? 0 : s_part[t - 1];
+    for (uint32_t b = b0; b < b1; b++) {
+        a.bin_start[b] = run;
+        run += a.bin_count[b];
+    }
+    if (t == 1023) {
+        uint32_t total = s_part[1023];
+        a.bin_start[a.nbins] = total;
+        a.ctr->pairs_total = total;
+        if (total > a.pair_cap)
+            a.ctr->error |= kErrPairs;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bin_scatter(FrameArgs a, const uint2 *__restrict__ bbox)
+{
+    extern __shared__ uint32_t s_off[];
+    __shared__ uint32_t s_pref[64];
+    __shared__ uint32_t s_rect[64][3];
+    const uint32_t lane = threadIdx.x, u = blockIdx.x;
+    const uint32_t *row = a.table + (size_t)u * a.nbins;
+    const uint32_t *tsum = a.tile_sums + (size_t)(u >> 6) * a.nbins;
+    for (uint32_t b = lane; b < a.nbins; b += 64)
+        s_off[b] = a.bin_start[b] + tsum[b] + row[b];
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
+    for (uint32_t base = q0; base < q1; base += 64) {
+        uint32_t q = base + lane;
+        uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
+        if (q < q1)
+            quad_bins(bbox[q], a.bin_shift, bx0, by0, bw, np);
+        // inclusive prefix of np over the wave
+        uint32_t incl = np;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
+            if (lane >= (uint32_t)off)
+                incl += v;
+        }
+        const uint32_t total = lane_value(incl, 63);
+        s_pref[lane] = incl;
+        s_rect[lane][0] = bx0;
+        s_rect[lane][1] = by0;
+        s_rect[lane][2] = bw;
+        __syncthreads();
+        for (uint32_t w = 0; w < total; w += 64) {
+            const uint32_t p = w + lane;
+            const bool valid = p < total;
+            uint32_t bin = 0, qv = 0;
+            if (valid) {
+                // owning quad: first lane whose inclusive prefix exceeds p
+                uint32_t lo = 0, hi = 63;
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (s_pref[mid] > p)
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                uint32_t k = p - (lo ? s_pref[lo - 1] : 0);
+                uint32_t rbw = s_rect[lo][2];
+                bin = (s_rect[lo][1] + k / rbw) * a.nbx + s_rect[lo][0] + k % rbw;
+                qv = base + lo;
+            }
+            // lanes holding the same bin: AND over the bits of the bin index
+            uint64_t peers = ballot(valid);
+            for (uint32_t bit = 0; bit < a.match_bits; bit++) {
+                const bool set = (bin >> bit) & 1u;
+                const uint64_t bm = ballot(set);
+                peers &= set ? bm : ~bm;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+            const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : lane;
+            uint32_t base_off = 0;
+            if (valid && rank == 0)
+                base_off = atomicAdd(&s_off[bin], (uint32_t)__popcll(peers));
+            // every lane reads its group leader's base offset
+            const uint32_t pos =
+                (uint32_t)__builtin_amdgcn_ds_bpermute((int)(leader << 2), (int)base_off) + rank;
+            if (valid && pos < a.pair_cap)
+                a.pairs[pos] = qv;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ raster
+
+// Work item -> 8x8 block.  Items are ordered bin by bin (blocks of a bin are
+// consecutive) and split into 8 contiguous ranges, one per XCD: workgroup w
+// is dispatched to XCD w % 8, so the blocks of one bin share that XCD's L2.
+__device__ __forceinline__ bool map_block(const FrameArgs &a, uint32_t w, uint32_t &bxk, uint32_t &byk)
+{
+    const uint32_t bpb = 1u << (a.bin_shift - 3);  // blocks per bin side
+    const uint32_t per_bin = bpb * bpb;
+    const uint32_t total = a.nbins * per_bin;
+    const uint32_t per_xcd = (total + 7) / 8;
+    const uint32_t wi = (w & 7) * per_xcd + (w >> 3);
+    if (wi >= total)
+        return false;
+    const uint32_t bin = wi / per_bin, in = wi % per_bin;
+    bxk = (bin % a.nbx) * bpb + in % bpb;
+    byk = (bin / a.nbx) * bpb + in / bpb;
+    return bxk < a.nblk_x && byk < a.nblk_y;
+}
+
+// Coverage of one quad over the 64 samples of a block (one bit per lane,
+// lane = 8*ly + lx), exact under the top-left rule.
+__device__ __forceinline__ uint64_t block_coverage(const QuadRec *__restrict__ rec,
+                                                   const QuadXY *__restrict__ xyp, uint32_t q, int px,
+                                                   int py)
+{
+    const QuadRec &r = rec[q];
+    const uint32_t flags = r.flags;
+    if (!(flags & kWide)) {
+        const int di = px - (int)(r.bb_i & 0xffffu);
+        const int dj = py - (int)(r.bb_j & 0xffffu);
+        const int *hp = r.hp;
+        int L0 = __mul24(hp[0], di) + __mul24(hp[1], dj);
+        int L1 = __mul24(hp[3], di) + __mul24(hp[4], dj);
+        int L2 = __mul24(hp[6], di) + __mul24(hp[7], dj);
+        int L3 = __mul24(hp[9], di) + __mul24(hp[10], dj);
+        int L4 = __mul24(hp[12], di) + __mul24(hp[13], dj);
+        int L5 = __mul24(hp[15], di) + __mul24(hp[16], dj);
+        uint64_t t0 = ballot(L0 >= hp[2] && L1 >= hp[5] && L2 >= hp[8]);
+        uint64_t t1 = ballot(L3 >= hp[11] && L4 >= hp[14] && L5 >= hp[17]);
+        return t0 | t1;
+    }
+    // wide quad: exact fp64 edge functions (all products below 2^50)
+    const QuadXY xy = xyp[q];
+    const double Sx = 256.0 * (double)px + 128.0, Sy = 256.0 * (double)py + 128.0;
+    bool in = false;
+    for (int T = 0; T < 2; T++) {
+        const uint32_t vb = T ? kT1Valid : kT0Valid, sb = T ? kT1Swap : kT0Swap;
+        if (!(flags & vb))
+            continue;
+        int ia = 0, ib = T ? 2 : 1, ic = T ? 3 : 2;
+        if (flags & sb) {
+            int t = ib;
+            ib = ic;
+            ic = t;
+        }
+        const int idx[3] = {ia, ib, ic};
+        bool inside = true;
+        for (int e = 0; e < 3; e++) {
+            const int s = idx[e], t = idx[(e + 1) % 3];
+            const double dx = (double)xy.X[t] - (double)xy.X[s];
+            const double dy = (double)xy.Y[t] - (double)xy.Y[s];
+            const double E = dx * (Sy - (double)xy.Y[s]) - dy * (Sx - (double)xy.X[s]);
+            const bool tl = (dy < 0.0) || (dy == 0.0 && dx > 0.0);
+            if (!(E > 0.0 || (E == 0.0 && tl)))
+                inside = false;
+        }
+        in = in || inside;
+    }
+    return ballot(in);
+}
+
+// Single-sample coverage (one lane, one quad), same rule.
+__device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q,
+                                               int px, int py)
+{
+    const uint32_t flags = r.flags;
+    if (!(flags & kWide)) {
+        const int di = px - (int)(r.bb_i & 0xffffu);
+        const int dj = py - (int)(r.bb_j & 0xffffu);
+        const int *hp = r.hp;
+        bool t0 = (__mul24(hp[0], di) + __mul24(hp[1], dj) >= hp[2]) &&
+                  (__mul24(hp[3], di) + __mul24(hp[4], dj) >= hp[5]) &&
+                  (__mul24(hp[6], di) + __mul24(hp[7], dj) >= hp[8]);
+        bool t1 = (__mul24(hp[9], di) + __mul24(hp[10], dj) >= hp[11]) &&
+                  (__mul24(hp[12], di) + __mul24(hp[13], dj) >= hp[14]) &&
+                  (__mul24(hp[15], di) + __mul24(hp[16], dj) >= hp[17]);
+        return t0 || t1;
+    }
+    const QuadXY xy = xyp[q];
+    const double Sx = 256.0 * (double)px + 128.0, Sy = 256.0 * (double)py + 128.0;
+    bool in = false;
+    for (int T = 0; T < 2; T++) {
+        const uint32_t vb = T ? kT1Valid : kT0Valid, sb = T ? kT1Swap : kT0Swap;
+        if (!(flags & vb))
+            continue;
+        int ia = 0, ib = T ? 2 : 1, ic = T ? 3 : 2;
+        if (flags & sb) {
+            int t = ib;
+            ib = ic;
+            ic = t;
+        }
+        const int idx[3] = {ia, ib, ic};
+        bool inside = true;
+        for (int e = 0; e < 3; e++) {
+            const int s = idx[e], t = idx[(e + 1) % 3];
+            const double dx = (double)xy.X[t] - (double)xy.X[s];
+            const double dy = (double)xy.Y[t] - (double)xy.Y[s];
+            const double E = dx * (Sy - (double)xy.Y[s]) - dy * (Sx - (double)xy.X[s]);
+            const bool tl = (dy < 0.0) || (dy == 0.0 && dx > 0.0);
+            if (!(E > 0.0 || (E == 0.0 && tl)))
+                inside = false;
+        }
+        in = in || inside;
+    }
+    return in;
+}
+
+// Block key: the quad's depth at the centroid of its covered samples in the
+// block (Stage 3, phase 2), fp32; smaller key = nearer.
+__device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t m, int px0, int py0)
+{
+    const float cnt = (float)__popcll(m);
+    const float sx = (float)(__popcll(m & 0xAAAAAAAAAAAAAAAAull) + 2 * __popcll(m & 0xCCCCCCCCCCCCCCCCull) +
+                             4 * __popcll(m & 0xF0F0F0F0F0F0F0F0ull));
+    const float sy = (float)(__popcll(m & 0xFF00FF00FF00FF00ull) + 2 * __popcll(m & 0xFFFF0000FFFF0000ull) +
+                             4 * __popcll(m & 0xFFFFFFFF00000000ull));
+    const float inv = 1.0f / cnt;
+    const float cx = (float)(px0 - (int)(r.bb_i & 0xffffu)) + sx * inv;
+    const float cy = (float)(py0 - (int)(r.bb_j & 0xffffu)) + sy * inv;
+    float k = r.fA * cx + r.fB * cy + r.fC0;
+    k = (k > 0.0f) ? k : 0.0f;  // NaN -> 0
+    return 0x7F800000u - min(__float_as_uint(k), 0x7F800000u);  // < 2^31
+}
+
+// Stable-order bitonic sort of n keys in LDS by one wave (ascending).
+template <typename KeyT>
+__device__ void wave_bitonic_sort(KeyT *keys, uint32_t n, KeyT pad, uint32_t lane)
+{
+    uint32_t P = 2;
+    while (P < n)
+        P <<= 1;
+    for (uint32_t i = n + lane; i < P; i += 64)
+        keys[i] = pad;
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = lane; t < P / 2; t += 64) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t ixj = i | j;
+                const KeyT x = keys[i], y = keys[ixj];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    keys[i] = y;
+                    keys[ixj] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+struct Stage {
+    double A, B, C0;
+    uint32_t ij;    // imin | jmin << 16
+    uint32_t rgba;
+};
+
+template <int CAP>
+struct RasterLds {
+    uint64_t mask[CAP];
+    uint32_t id[CAP];
+    uint32_t key[CAP];
+    Stage stage[64];
+    uint32_t sid[64];
+};
+
+constexpr uint32_t slot_bits(uint32_t cap)
+{
+    uint32_t b = 0;
+    while ((1u << b) < cap)
+        b++;
+    return b;
+}
+
+// Queue a pixel for the exact per-pixel sort (wave-aggregated).
+__device__ __forceinline__ void push_flagged(const FrameArgs &a, bool flag, uint32_t pix, uint32_t lane)
+{
+    const uint64_t m = ballot(flag);
+    if (!m)
+        return;
+    uint32_t base = 0;
+    if (lane == 0)
+        base = atomicAdd(&a.ctr->flagged, (uint32_t)__popcll(m));
+    base = lane_value(base, 0);
+    if (flag)
+        a.fb_queue[base + rank_below(m)] = pix;
+}
+
+// One 8x8 block, sorted path.  Returns false when the block's list exceeds
+// CAP (nothing written).
+template <int K, int CAP, bool DEBUG>
+__device__ bool raster_sorted_block(const FrameArgs &a, const QuadRec *__restrict__ rec,
+                                    const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
+                                    const uint32_t *__restrict__ pairs, RasterLds<CAP> &L, uint32_t bxk,
+                                    uint32_t byk, bool last_resort)
+{
+    constexpr uint32_t SB = slot_bits(CAP);
+    const uint32_t lane = threadIdx.x;
+    const int px0 = (int)bxk * 8, py0 = (int)byk * 8;
+    const int px = px0 + (int)(lane & 7), py = py0 + (int)(lane >> 3);
+    const bool on = px < (int)a.W && py < (int)a.H;
+    const uint64_t onmask = ballot(on);
+    const uint32_t pix = on ? (uint32_t)py * a.W + (uint32_t)px : 0;
+    const int px1 = min(px0 + 7, (int)a.W - 1), py1 = min(py0 + 7, (int)a.H - 1);
+    const uint32_t bin = ((uint32_t)py0 >> a.bin_shift) * a.nbx + ((uint32_t)px0 >> a.bin_shift);
+    const uint32_t start = uniform(a.bin_start[bin]);
+    const uint32_t cnt = uniform(a.bin_count[bin]);
+
+    // ---- phase 1: coverage masks and block keys of the bin's quads
+    uint32_t n = 0;
+    for (uint32_t base = 0; base < cnt; base += 64) {
+        const uint32_t l = base + lane;
+        uint32_t qid = 0;
+        bool ov = false;
+        if (l < cnt) {
+            qid = pairs[start + l];
+            const uint2 bb = bbox[qid];
+            ov = (int)(bb.x & 0xffffu) <= px1 && (int)(bb.x >> 16) >= px0 && (int)(bb.y & 0xffffu) <= py1 &&
+                 (int)(bb.y >> 16) >= py0;
+        }
+        uint64_t cand = ballot(ov);
+        while (cand) {
+            const uint32_t s = (uint32_t)__builtin_ctzll(cand);
+            cand &= cand - 1;
+            const uint32_t q = lane_value(qid, s);
+            const uint64_t m = block_coverage(rec, xyp, q, px, py) & onmask;
+            if (m) {
+                if (n < CAP && lane == 0) {
+                    L.mask[n] = m;
+                    L.id[n] = q;
+                    L.key[n] = ((block_depth_code(rec[q], m, px0, py0) >> (SB - 1)) << SB) | n;
+                }
+                n++;
+            }
+        }
+    }
+    if (n > CAP) {
+        if (!last_resort)
+            return false;
+        // no list can hold this block: every pixel takes the exact path
+        push_flagged(a, on, pix, lane);
+        if (lane == 0)
+            atomicOr(&a.ctr->error, kErrDense);
+        if (DEBUG && on && a.dbg_flag)
+            a.dbg_flag[pix] = 1;
+        return true;
+    }
+    __syncthreads();
+
+    // ---- phase 2: depth-sort the block's entries
+    wave_bitonic_sort<uint32_t>(L.key, n, 0xFFFFFFFFu, lane);
+
+    // ---- phase 3: per-pixel K-deep sorter and front-to-back blend
+    uint32_t qk[K], qc[K], qi[DEBUG ? K : 1];
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+        qk[j] = 0;  // "already emitted" placeholders: popped first, blend nothing
+        qc[j] = 0;
+        if (DEBUG)
+            qi[j] = 0;
+    }
+    uint32_t last = 0, nfrag = 0, npop = 0;
+    bool flagged = false;
+    float T = 1.0f, R = 0.0f, G = 0.0f, B = 0.0f;
+    const uint32_t obase = (DEBUG && on && a.dbg_off) ? a.dbg_off[pix] : 0;
+
+    auto emit = [&](uint32_t pk, uint32_t pc, uint32_t pi) {
+        flagged |= (pk - 1u) < last;  // pops must strictly increase (placeholders excepted)
+        last = pk;
+        blend_ftb(pc, T, R, G, B);
+        if (DEBUG && pk != 0) {
+            if (a.dbg_ids && on && obase + npop < a.dbg_cap)
+                a.dbg_ids[obase + npop] = pi;
+            npop++;
+        }
+    };
+
+    for (uint32_t seg = 0; seg < n; seg += 64) {
+        const uint32_t e = seg + lane;
+        uint64_t m = 0;
+        if (e < n) {
+            const uint32_t slot = L.key[e] & ((1u << SB) - 1);
+            m = L.mask[slot];
+            const uint32_t q = L.id[slot];
+            const QuadRec &r = rec[q];
+            Stage st;
+            st.A = r.A;
+            st.B = r.B;
+            st.C0 = r.C0;
+            st.ij = (r.bb_i & 0xffffu) | (r.bb_j << 16);
+            st.rgba = r.rgba;
+            L.stage[lane] = st;
+            if (DEBUG)
+                L.sid[lane] = q;
+        }
+        __syncthreads();
+        uint64_t col = transpose64(m, lane);
+        if (!on || flagged)
+            col = 0;
+        while (col) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(col);
+            col &= col - 1;
+            const Stage st = L.stage[k];
+            const float kf = frag_key(st.A, st.B, st.C0, px - (int)(st.ij & 0xffffu), py - (int)(st.ij >> 16));
+            const uint32_t x = order_code(kf);
+            const uint32_t xc = st.rgba;
+            const uint32_t xi = DEBUG ? L.sid[k] : 0;
+            nfrag++;
+            flagged |= (x == 0xFFFFFFFFu);  // zero key: leave it to the exact path
+            // insert x and emit the smallest of queue + x
+            bool lt[K];
+#pragma unroll
+            for (int j = 0; j < K; j++)
+                lt[j] = x < qk[j];
+            const uint32_t pk = lt[0] ? x : qk[0];
+            const uint32_t pc = lt[0] ? xc : qc[0];
+            uint32_t pi = 0;
+            if (DEBUG)
+                pi = lt[0] ? xi : qi[0];
+#pragma unroll
+            for (int j = 0; j < K - 1; j++) {
+                qk[j] = lt[j + 1] ? (lt[j] ? qk[j] : x) : qk[j + 1];
+                qc[j] = lt[j + 1] ? (lt[j] ? qc[j] : xc) : qc[j + 1];
+                if (DEBUG)
+                    qi[j] = lt[j + 1] ? (lt[j] ? qi[j] : xi) : qi[j + 1];
+            }
+            qk[K - 1] = lt[K - 1] ? qk[K - 1] : x;
+            qc[K - 1] = lt[K - 1] ? qc[K - 1] : xc;
+            if (DEBUG)
+                qi[K - 1] = lt[K - 1] ? qi[K - 1] : xi;
+            emit(pk, pc, pi);
+            if (flagged)
+                col = 0;
+        }
+        __syncthreads();
+    }
+    if (on && !flagged) {
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            emit(qk[j], qc[j], DEBUG ? qi[j] : 0);
+    }
+    push_flagged(a, on && flagged, pix, lane);
+    if (on && !flagged) {
+        reinterpret_cast<uint32_t *>(a.out)[pix] = pack_rgba8(R, G, B, 1.0f - T);
+        if (DEBUG && a.dbg_rgba) {
+            float4 o = make_float4(R, G, B, 1.0f - T);
+            reinterpret_cast<float4 *>(a.dbg_rgba)[pix] = o;
+        }
+    }
+    if (DEBUG && on) {
+        if (a.dbg_count)
+            a.dbg_count[pix] = nfrag;
+        if (a.dbg_flag)
+            a.dbg_flag[pix] = flagged ? 1 : 0;
+    }
+    // statistics (flagged pixels are counted by the exact path)
+    uint32_t wsum = (on && !flagged) ? nfrag : 0;
+    for (int off = 32; off > 0; off >>= 1)
+        wsum += shfl_xor(wsum, off);
+    if (lane == 0) {
+        atomicAdd(&a.ctr->entries, (unsigned long long)n);
+        atomicAdd(&a.ctr->fragments, (unsigned long long)wsum);
+    }
+    return true;
+}
+
+template <int K, bool DEBUG>
+__global__ __launch_bounds__(64) void k_raster(FrameArgs a, const QuadRec *__restrict__ rec,
+                                               const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
+                                               const uint32_t *__restrict__ pairs)
+{
+    __shared__ RasterLds<1024> L;
+    uint32_t bxk, byk;
+    if (!map_block(a, blockIdx.x, bxk, byk))
+        return;
+    if (a.ctr->error & kErrPairs)
+        return;  // bin lists are incomplete: the frame is reported as failed
+    if (!raster_sorted_block<K, 1024, DEBUG>(a, rec, xyp, bbox, pairs, L, bxk, byk, false)) {
+        if (threadIdx.x == 0) {
+            uint32_t slot = atomicAdd(&a.ctr->dense, 1u);
+            a.dense_queue[slot] = byk * a.nblk_x + bxk;
+        }
+    }
+}
+
+// Blocks whose list outgrew the on-chip list of k_raster: one wave per
+// block with a list eight times longer.
+template <int K, bool DEBUG>
+__global__ __launch_bounds__(64) void k_raster_dense(FrameArgs a, const QuadRec *__restrict__ rec,
+                                                     const QuadXY *__restrict__ xyp,
+                                                     const uint2 *__restrict__ bbox,
+                                                     const uint32_t *__restrict__ pairs)
+{
+    __shared__ RasterLds<8192> L;
+    if (a.ctr->error & kErrPairs)
+        return;
+    const uint32_t count = uniform(a.ctr->dense);
+    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const uint32_t blk = uniform(a.dense_queue[t]);
+        raster_sorted_block<K, 8192, DEBUG>(a, rec, xyp, bbox, pairs, L, blk % a.nblk_x, blk / a.nblk_x,
+                                            true);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- exact per pixel
+
+constexpr uint32_t kFallbackCap = 4096;
+
+template <bool DEBUG>
+__global__ __launch_bounds__(64) void k_fallback(FrameArgs a, const QuadRec *__restrict__ rec,
+                                                 const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
+                                                 const uint32_t *__restrict__ pairs)
+{
+    __shared__ unsigned long long s_key[kFallbackCap];
+    if (a.ctr->error & kErrPairs)
+        return;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t count = uniform(a.ctr->flagged);
+    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
+        const uint32_t p = uniform(a.fb_queue[t]);
+        const int i = (int)(p % a.W), j = (int)(p / a.W);
+        const uint32_t bin = ((uint32_t)j >> a.bin_shift) * a.nbx + ((uint32_t)i >> a.bin_shift);
+        const uint32_t start = uniform(a.bin_start[bin]);
+        const uint32_t cnt = uniform(a.bin_count[bin]);
+        uint32_t n = 0;
+        for (uint32_t base = 0; base < cnt; base += 64) {
+            const uint32_t l = base + lane;
+            bool cov = false;
+            unsigned long long key = 0;
+            if (l < cnt) {
+                const uint32_t q = pairs[start + l];
+                const uint2 bb = bbox[q];
+                if ((int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
+                    (int)(bb.y >> 16) >= j) {
+                    const QuadRec &r = rec[q];
+                    if (pixel_coverage(r, xyp, q, i, j)) {
+                        cov = true;
+                        const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
+                                                  j - (int)(r.bb_j & 0xffffu));
+                        key = ((unsigned long long)order_code(kf) << 32) | q;
+                    }
+                }
+            }
+            const uint64_t m = ballot(cov);
+            const uint32_t pos = n + rank_below(m);
+            if (cov && pos < kFallbackCap)
+                s_key[pos] = key;
+            n += (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        if (n > kFallbackCap) {
+            if (lane == 0)
+                atomicOr(&a.ctr->error, kErrFallback);
+            __syncthreads();
+            continue;
+        }
+        wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
+        float T = 1.0f, R = 0.0f, G = 0.0f, B = 0.0f;
+        const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
+        for (uint32_t base = 0; base < n; base += 64) {
+            const uint32_t e = base + lane;
+            uint32_t q = 0, c = 0;
+            if (e < n) {
+                q = (uint32_t)(s_key[e] & 0xffffffffu);
+                c = rec[q].rgba;
+                if (DEBUG && a.dbg_ids && obase + e < a.dbg_cap)
+                    a.dbg_ids[obase + e] = q;
+            }
+            const uint32_t lim = min(64u, n - base);
+            for (uint32_t s = 0; s < lim; s++)
+                blend_ftb(lane_value(c, s), T, R, G, B);
+        }
+        if (lane == 0) {
+            atomicAdd(&a.ctr->fragments, (unsigned long long)n);
+            reinterpret_cast<uint32_t *>(a.out)[p] = pack_rgba8(R, G, B, 1.0f - T);
+            if (DEBUG) {
+                if (a.dbg_rgba)
+                    reinterpret_cast<float4 *>(a.dbg_rgba)[p] = make_float4(R, G, B, 1.0f - T);
+                if (a.dbg_count)
+                    a.dbg_count[p] = n;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ unsorted baseline
+
+template <bool DEBUG>
+__global__ __launch_bounds__(64) void k_unsorted(FrameArgs a, const QuadRec *__restrict__ rec,
+                                                 const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
+                                                 const uint32_t *__restrict__ pairs)
+{
+    __shared__ uint64_t s_mask[64];
+    __shared__ uint32_t s_id[64];
+    __shared__ uint32_t s_col[64];
+    uint32_t bxk, byk;
+    if (!map_block(a, blockIdx.x, bxk, byk))
+        return;
+    if (a.ctr->error & kErrPairs)
+        return;
+    const uint32_t lane = threadIdx.x;
+    const int px0 = (int)bxk * 8, py0 = (int)byk * 8;
+    const int px = px0 + (int)(lane & 7), py = py0 + (int)(lane >> 3);
+    const bool on = px < (int)a.W && py < (int)a.H;
+    const uint64_t onmask = ballot(on);
+    const uint32_t pix = on ? (uint32_t)py * a.W + (uint32_t)px : 0;
+    const int px1 = min(px0 + 7, (int)a.W - 1), py1 = min(py0 + 7, (int)a.H - 1);
+    const uint32_t bin = ((uint32_t)py0 >> a.bin_shift) * a.nbx + ((uint32_t)px0 >> a.bin_shift);
+    const uint32_t start = uniform(a.bin_start[bin]);
+    const uint32_t cnt = uniform(a.bin_count[bin]);
+    float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
+    uint32_t nfrag = 0, ntot = 0, n = 0;
+
+    auto flush = [&]() {
+        __syncthreads();
+        uint64_t m = 0;
+        if (lane < n) {
+            m = s_mask[lane];
+            s_col[lane] = rec[s_id[lane]].rgba;
+        }
+        __syncthreads();
+        uint64_t col = transpose64(m, lane);
+        if (!on)
+            col = 0;
+        while (col) {
+            const uint32_t k = (uint32_t)__builtin_ctzll(col);
+            col &= col - 1;
+            blend_over(s_col[k], R, G, B, Al);
+            nfrag++;
+        }
+        __syncthreads();
+        ntot += n;
+        n = 0;
+    };
+
+    for (uint32_t base = 0; base < cnt; base += 64) {
+        const uint32_t l = base + lane;
+        uint32_t qid = 0;
+        bool ov = false;
+        if (l < cnt) {
+            qid = pairs[start + l];
+            const uint2 bb = bbox[qid];
+            ov = (int)(bb.x & 0xffffu) <= px1 && (int)(bb.x >> 16) >= px0 && (int)(bb.y & 0xffffu) <= py1 &&
+                 (int)(bb.y >> 16) >= py0;
+        }
+        uint64_t cand = ballot(ov);
+        while (cand) {
+            const uint32_t s = (uint32_t)__builtin_ctzll(cand);
+            cand &= cand - 1;
+            const uint32_t q = lane_value(qid, s);
+            const uint64_t m = block_coverage(rec, xyp, q, px, py) & onmask;
+            if (m) {
+                if (lane == 0) {
+                    s_mask[n] = m;
+                    s_id[n] = q;
+                }
+                n++;
+                if (n == 64)
+                    flush();
+            }
+        }
+    }
+    if (n)
+        flush();
+    if (on) {
+        reinterpret_cast<uint32_t *>(a.out)[pix] = pack_rgba8(R, G, B, Al);
+        if (DEBUG) {
+            if (a.dbg_rgba)
+                reinterpret_cast<float4 *>(a.dbg_rgba)[pix] = make_float4(R, G, B, Al);
+            if (a.dbg_count)
+                a.dbg_count[pix] = nfrag;
+        }
+    }
+    uint32_t wsum = nfrag;
+    for (int off = 32; off > 0; off >>= 1)
+        wsum += shfl_xor(wsum, off);
+    if (lane == 0) {
+        atomicAdd(&a.ctr->entries, (unsigned long long)ntot);
+        atomicAdd(&a.ctr->fragments, (unsigned long long)wsum);
+    }
+}
+
+// ---------------------------------------------------------- scene upload
+
+__global__ __launch_bounds__(256) void k_transpose_scene(const uint32_t *__restrict__ in, uint32_t n,
+                                                         float *__restrict__ v, uint32_t *__restrict__ rgba)
+{
+    const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= n)
+        return;
+    const uint32_t *r = in + 13 * (size_t)q;
+    for (int c = 0; c < 12; c++)
+        v[(size_t)c * n + q] = __uint_as_float(r[c]);
+    rgba[q] = r[12];
+}
+
+// ---------------------------------------------------------------- launches
+
+static uint32_t raster_grid(const FrameArgs &a)
+{
+    const uint32_t bpb = 1u << (a.bin_shift - 3);
+    const uint32_t total = a.nbins * bpb * bpb;
+    return ((total + 7) / 8) * 8;
+}
+
+static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEvent_t *ev, bool bins)
+{
+    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(64), 0, s, a.ctr);
+    if (a.n) {
+        hipLaunchKernelGGL(k_setup, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    }
+    if (ev)
+        (void)hipEventRecord(ev[1], s);
+    if (!bins)
+        return hipGetLastError();
+    if (a.n) {
+        hipLaunchKernelGGL(k_bin_count, dim3(a.nunits), dim3(64), a.nbins * 4, s, a,
+                           (const uint2 *)a.bbox);
+    } else {
+        // no quads: every bin count is zero
+    }
+    if (ev)
+        (void)hipEventRecord(ev[2], s);
+    if (a.n) {
+        hipLaunchKernelGGL(k_bin_scan_tiles, dim3((a.nbins + 63) / 64, a.ntiles), dim3(64), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_bin_scan_final, dim3(1), dim3(1024), 0, s, a);
+    if (ev)
+        (void)hipEventRecord(ev[3], s);
+    if (a.n) {
+        hipLaunchKernelGGL(k_bin_scatter, dim3(a.nunits), dim3(64), a.nbins * 4, s, a, (const uint2 *)a.bbox);
+    }
+    if (ev)
+        (void)hipEventRecord(ev[4], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_only(const FrameArgs &a, hipStream_t s)
+{
+    return launch_setup_and_bins(a, s, nullptr, false);
+}
+
+hipError_t launch_binning_only(const FrameArgs &a, hipStream_t s)
+{
+    return launch_setup_and_bins(a, s, nullptr, true);
+}
+
+bool sorter_depth_supported(int k)
+{
+    return k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 24 || k == 32;
+}
+
+template <int K, bool DEBUG>
+static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
+{
+    const uint32_t g = raster_grid(a);
+    hipLaunchKernelGGL((k_raster<K, DEBUG>), dim3(g), dim3(64), 0, s, a, (const QuadRec *)a.rec,
+                       (const QuadXY *)a.xy, (const uint2 *)a.bbox, (const uint32_t *)a.pairs);
+    if (ev)
+        (void)hipEventRecord(ev[5], s);
+    const uint32_t nblk = a.nblk_x * a.nblk_y;
+    hipLaunchKernelGGL((k_raster_dense<K, DEBUG>), dim3(min(nblk, 512u)), dim3(64), 0, s, a,
+                       (const QuadRec *)a.rec, (const QuadXY *)a.xy, (const uint2 *)a.bbox,
+                       (const uint32_t *)a.pairs);
+    if (ev)
+        (void)hipEventRecord(ev[6], s);
+    hipLaunchKernelGGL((k_fallback<DEBUG>), dim3(min(a.W * a.H, 2048u)), dim3(64), 0, s, a,
+                       (const QuadRec *)a.rec, (const QuadXY *)a.xy, (const uint2 *)a.bbox,
+                       (const uint32_t *)a.pairs);
+    if (ev)
+        (void)hipEventRecord(ev[7], s);
+}
+
+template <bool DEBUG>
+static void launch_sorted_k(const FrameArgs &a, int k, hipStream_t s, hipEvent_t *ev)
+{
+    switch (k) {
+    case 2: launch_sorted<2, DEBUG>(a, s, ev); break;
+    case 4: launch_sorted<4, DEBUG>(a, s, ev); break;
+    case 8: launch_sorted<8, DEBUG>(a, s, ev); break;
+    case 12: launch_sorted<12, DEBUG>(a, s, ev); break;
+    case 16: launch_sorted<16, DEBUG>(a, s, ev); break;
+    case 24: launch_sorted<24, DEBUG>(a, s, ev); break;
+    default: launch_sorted<32, DEBUG>(a, s, ev); break;
+    }
+}
+
+hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s, hipEvent_t *ev)
+{
+    if (ev)
+        (void)hipEventRecord(ev[0], s);
+    hipError_t e = launch_setup_and_bins(a, s, ev, true);
+    if (e != hipSuccess)
+        return e;
+    const bool dbg = a.dbg_rgba || a.dbg_count || a.dbg_flag || a.dbg_ids;
+    if (unsorted) {
+        const uint32_t g = raster_grid(a);
+        if (dbg)
+            hipLaunchKernelGGL((k_unsorted<true>), dim3(g), dim3(64), 0, s, a, (const QuadRec *)a.rec,
+                               (const QuadXY *)a.xy, (const uint2 *)a.bbox, (const uint32_t *)a.pairs);
+        else
+            hipLaunchKernelGGL((k_unsorted<false>), dim3(g), dim3(64), 0, s, a, (const QuadRec *)a.rec,
+                               (const QuadXY *)a.xy, (const uint2 *)a.bbox, (const uint32_t *)a.pairs);
+        if (ev) {
+            (void)hipEventRecord(ev[5], s);
+            (void)hipEventRecord(ev[6], s);
+            (void)hipEventRecord(ev[7], s);
+        }
+    } else if (dbg) {
+        launch_sorted_k<true>(a, sorter_depth, s, ev);
+    } else {
+        launch_sorted_k<false>(a, sorter_depth, s, ev);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_scene(const void *quads_dev, uint32_t n, float *v, uint32_t *rgba, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_transpose_scene, dim3((n + 255) / 256), dim3(256), 0, s,
+                       (const uint32_t *)quads_dev, n, v, rgba);
+    return hipGetLastError();
+}
+
+}  // namespace lr

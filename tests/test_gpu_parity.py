@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: setup records, bin lists, per-pixel fragment counts and blend order
+bit-exact; RGBA8 within 1 LSB and fp32 colour within 1e-5 of the oracle's
+fp64 result; fp32 colour bit-identical across sorter depths and bin sizes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13364_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 1e-5
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hand_scenes.json")
+
+
+@pytest.fixture(scope="module")
+def lr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_13364_amd import lucidraster
+    return lucidraster
+
+
+_ctx_cache = {}
+
+
+def ctx_for(lr, bin_size=32, k=8):
+    key = (bin_size, k)
+    if key not in _ctx_cache:
+        _ctx_cache[key] = lr.Context(arena_bytes=512 << 20, bin_size=bin_size, sorter_depth=k)
+    return _ctx_cache[key]
+
+
+def hand_scene():
+    data = json.load(open(GOLDEN))
+    quads = []
+    for case in data["cases"]:
+        for q in case["quads"]:
+            quads.append((scenes.screen_quad(q["corners"], q["z"], data["width"], data["height"]),
+                          int(scenes.pack_rgba(*q["rgba"]))))
+    return scenes.from_quads(quads, data["width"], data["height"], name="hand")
+
+
+def wide_scene():
+    # quads up to ~1500 px across on a 700x500 frame: the fp64 coverage path
+    return scenes.small(700, 500, 40, 21, side=(200.0, 1500.0), z=(1.0, 3.0), alpha=(0.2, 0.6))
+
+
+SCENES = {
+    "small": lambda: scenes.small(96, 72, 3000, 11, side=(2.0, 24.0)),
+    "ragged": lambda: scenes.small(101, 37, 1500, 12, side=(1.0, 30.0)),
+    "tiny_frame": lambda: scenes.small(9, 7, 200, 13, side=(1.0, 6.0)),
+    "one_pixel": lambda: scenes.small(1, 1, 50, 14, side=(1.0, 3.0)),
+    "c1": lambda: scenes.scene("c1"),
+    "hand": hand_scene,
+    "wide": wide_scene,
+    "gauss": lambda: scenes.small(160, 120, 20000, 15, side=(1.0, 20.0), gaussian=True, alpha=(0.05, 0.5)),
+}
+
+
+def moved_camera():
+    cam = scenes.Camera.jittered(3.0, -2.0)
+    cam.pos = (0.02, -0.03, 0.05)
+    return cam
+
+
+def gpu_render(lr, ctx, sc, cam=None, order=True):
+    cam = cam or sc.camera
+    h = ctx.upload(sc.v, sc.rgba)
+    try:
+        return ctx.render_debug(h, cam, sc.width, sc.height, order=order)
+    finally:
+        ctx.release(h)
+
+
+def check_frame(got, ref, where=""):
+    cnt = got["count"].cpu().numpy().astype(np.uint32)
+    np.testing.assert_array_equal(cnt, ref["count"], err_msg=f"counts {where}")
+    if "order_ids" in got:
+        ids = got["order_ids"].cpu().numpy().astype(np.uint32)
+        np.testing.assert_array_equal(ids, ref["order_ids"], err_msg=f"order {where}")
+    d8 = np.abs(got["rgba8"].cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32))
+    assert d8.max(initial=0) <= 1, f"rgba8 off by {d8.max()} {where}"
+    df = np.abs(got["rgba_f32"].cpu().numpy().astype(np.float64) - ref["rgba_f64"])
+    assert df.max(initial=0) <= F32_TOL, f"fp32 colour off by {df.max()} {where}"
+
+
+@pytest.mark.parametrize("name", sorted(SCENES))
+def test_setup_parity(lr, name):
+    sc = SCENES[name]()
+    for cam in (sc.camera, moved_camera()):
+        ctx = ctx_for(lr)
+        h = ctx.upload(sc.v, sc.rgba)
+        got = ctx.debug_setup(h, cam, sc.width, sc.height, sc.n)
+        ctx.release(h)
+        st = oracle.setup(sc.v, cam, sc.width, sc.height)
+        np.testing.assert_array_equal(got["cull"], st.cull)
+        vis = st.cull == 0
+        np.testing.assert_array_equal(got["X"][vis], st.X[vis])
+        np.testing.assert_array_equal(got["Y"][vis], st.Y[vis])
+        np.testing.assert_array_equal(got["bbox"][vis], st.bbox[vis])
+        pl = np.stack([st.A, st.B, st.C0], axis=1)
+        np.testing.assert_array_equal(got["plane"][vis].view(np.uint64), pl[vis].view(np.uint64))
+
+
+@pytest.mark.parametrize("bin_size", [16, 32, 64])
+@pytest.mark.parametrize("name", ["small", "c1", "ragged", "wide"])
+def test_bins_parity(lr, name, bin_size):
+    sc = SCENES[name]()
+    ctx = ctx_for(lr)
+    h = ctx.upload(sc.v, sc.rgba)
+    counts, ids = ctx.debug_bins(h, sc.camera, sc.width, sc.height, bin_size)
+    ctx.release(h)
+    st = oracle.setup(sc.v, sc.camera, sc.width, sc.height)
+    rc, roff, rids = oracle.bins(st, sc.width, sc.height, bin_size)
+    np.testing.assert_array_equal(counts, rc)
+    np.testing.assert_array_equal(ids, rids)
+
+
+@pytest.mark.parametrize("name", sorted(SCENES))
+def test_render_parity(lr, name):
+    sc = SCENES[name]()
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    got = gpu_render(lr, ctx_for(lr), sc)
+    check_frame(got, ref, name)
+
+
+def test_render_parity_moved_camera(lr):
+    sc = SCENES["small"]()
+    cam = moved_camera()
+    ref = oracle.render(sc.v, sc.rgba, cam, sc.width, sc.height)
+    got = gpu_render(lr, ctx_for(lr), sc, cam)
+    check_frame(got, ref, "moved camera")
+
+
+@pytest.mark.parametrize("name", ["small", "gauss", "c1", "ragged"])
+def test_unsorted_parity(lr, name):
+    import torch
+    sc = SCENES[name]()
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, unsorted=True, want_order=False)
+    ctx = ctx_for(lr)
+    h = ctx.upload(sc.v, sc.rgba)
+    f32 = torch.zeros((sc.height, sc.width, 4), dtype=torch.float32, device="cuda")
+    out = ctx.render_unsorted(h, sc.camera, sc.width, sc.height, rgba_f32=f32)
+    ctx.release(h)
+    d8 = np.abs(out.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32)).max()
+    df = np.abs(f32.cpu().numpy().astype(np.float64) - ref["rgba_f64"]).max()
+    assert d8 <= 1 and df <= F32_TOL, (d8, df)
+
+
+def test_invariance_over_sorter_depth_and_bins(lr):
+    """Sorter depth, bin size and repetition never change a single bit."""
+    sc = SCENES["gauss"]()
+    base = gpu_render(lr, ctx_for(lr), sc, order=False)
+    b32 = base["rgba_f32"].cpu().numpy()
+    b8 = base["rgba8"].cpu().numpy()
+    flagged = {}
+    for bin_size in (16, 32, 64):
+        for k in (2, 4, 8, 16, 32):
+            got = gpu_render(lr, ctx_for(lr, bin_size, k), sc, order=False)
+            np.testing.assert_array_equal(got["rgba_f32"].cpu().numpy().view(np.uint32), b32.view(np.uint32),
+                                          err_msg=f"bin {bin_size} K {k}")
+            np.testing.assert_array_equal(got["rgba8"].cpu().numpy(), b8)
+            flagged[(bin_size, k)] = int(got["flagged"].cpu().numpy().sum())
+    # a shallower sorter sends more pixels down the exact path
+    assert flagged[(32, 2)] >= flagged[(32, 32)]
+
+
+def test_forced_fallback_is_exact(lr):
+    """K = 2 on a dense cloud: many pixels overflow the sorter and are
+    recomputed; the frame is still exact."""
+    sc = SCENES["gauss"]()
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    got = gpu_render(lr, ctx_for(lr, 32, 2), sc)
+    check_frame(got, ref, "K=2")
+    assert int(got["flagged"].cpu().numpy().sum()) > 0
+
+
+def stacked_block_scene(nq, W=64, H=48, seed=5):
+    """nq small fronto-parallel quads stacked over the same 8x8 block at
+    random depths: the block's list exceeds the on-chip capacity."""
+    rng = np.random.default_rng(seed)
+    quads = []
+    for q in range(nq):
+        x0, y0 = rng.uniform(16.2, 20.0), rng.uniform(8.2, 12.0)
+        w, h = rng.uniform(3, 12, 2)
+        z = float(rng.uniform(1.0, 9.0))
+        corners = [[x0, y0], [x0 + w, y0], [x0 + w, y0 + h], [x0, y0 + h]]
+        quads.append((scenes.screen_quad(corners, z, W, H), int(rng.integers(0, 2**32))))
+    return scenes.from_quads(quads, W, H, name=f"stack{nq}")
+
+
+@pytest.mark.parametrize("nq", [1500, 9000])
+def test_dense_block_paths(lr, nq):
+    sc = stacked_block_scene(nq)
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    ctx = ctx_for(lr)
+    got = gpu_render(lr, ctx, sc)
+    check_frame(got, ref, f"stack {nq}")
+    st = ctx.stats()
+    assert st["dense_blocks"] >= 1
+    assert st["fragments"] == ref["total"]
+
+
+def test_repeat_is_deterministic(lr):
+    sc = SCENES["gauss"]()
+    ctx = ctx_for(lr)
+    h = ctx.upload(sc.v, sc.rgba)
+    a = ctx.render_debug(h, sc.camera, sc.width, sc.height)
+    b = ctx.render_debug(h, sc.camera, sc.width, sc.height)
+    ctx.release(h)
+    for k in ("rgba8", "rgba_f32", "count", "flagged"):
+        assert bool((a[k] == b[k]).all()), k
+
+
+def test_stats_match_oracle(lr):
+    sc = SCENES["small"]()
+    ctx = ctx_for(lr)
+    h = ctx.upload(sc.v, sc.rgba)
+    ctx.render(h, sc.camera, sc.width, sc.height)
+    st = ctx.stats()
+    ctx.release(h)
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False)
+    cc = ref["setup"].cull_counts()
+    assert st["visible"] == cc["visible"]
+    assert st["culled"][1:] == [cc["near"], cc["guard"], cc["degenerate"], cc["no_sample"], cc["edge_on"]]
+    assert st["fragments"] == ref["total"]
+    counts, _, _ = oracle.bins(ref["setup"], sc.width, sc.height, 32)
+    assert st["bin_pairs"] == int(counts.sum())
+
+
+def test_render_batch_matches_single(lr):
+    import torch
+    ctx = ctx_for(lr)
+    frames = [scenes.small(64 + 8 * i, 40 + 4 * i, 500 + 300 * i, 30 + i, side=(2, 16)) for i in range(4)]
+    hs = [ctx.upload(s.v, s.rgba) for s in frames]
+    outs = [ctx.new_image(s.width, s.height) for s in frames]
+    ctx.render_batch([(h, s.camera, s.width, s.height, o, 0, 0) for h, s, o in zip(hs, frames, outs)])
+    for h, s, o in zip(hs, frames, outs):
+        single = ctx.render(h, s.camera, s.width, s.height)
+        assert bool((single == o).all())
+    for h in hs:
+        ctx.release(h)
+
+
+def test_c2_full_frame(lr):
+    sc = scenes.scene("c2")
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    got = gpu_render(lr, ctx_for(lr), sc)
+    check_frame(got, ref, "c2")
+
+
+def test_c3_sampled_pixels(lr):
+    """Full-size dense cloud: the oracle computes sampled pixels one by one
+    (the densest centre region plus random pixels)."""
+    sc = scenes.scene("c3")
+    ctx = ctx_for(lr)
+    got = gpu_render(lr, ctx, sc, order=True)
+    W, H = sc.width, sc.height
+    rng = np.random.default_rng(0)
+    cy, cx = H // 2, W // 2
+    centre = [(cy + dy) * W + (cx + dx) for dy in range(-4, 4) for dx in range(-4, 4)]
+    pix = np.array(centre + list(rng.choice(W * H, 192, replace=False)), np.uint32)
+    ref = oracle.pixels(sc.v, sc.rgba, sc.camera, W, H, pix)
+    cnt = got["count"].cpu().numpy().reshape(-1)[pix].astype(np.uint32)
+    np.testing.assert_array_equal(cnt, ref["count"])
+    f32 = got["rgba_f32"].cpu().numpy().reshape(-1, 4)[pix].astype(np.float64)
+    assert np.abs(f32 - ref["rgba_f64"]).max() <= F32_TOL
+    r8 = got["rgba8"].cpu().numpy().reshape(-1, 4)[pix].astype(np.int32)
+    assert np.abs(r8 - oracle.to_u8(ref["rgba_f64"]).astype(np.int32)).max() <= 1
+    off = got["order_offsets"].cpu().numpy()
+    ids = got["order_ids"].cpu().numpy().astype(np.uint32)
+    for k, p in enumerate(pix):
+        a = ids[int(off[p]):int(off[p + 1])]
+        b = ref["ids"][int(ref["offsets"][k]):int(ref["offsets"][k + 1])]
+        np.testing.assert_array_equal(a, b)
+    assert int(ref["count"].max()) > 200  # the sampled centre is the deep part
