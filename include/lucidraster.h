@@ -86,6 +86,9 @@ typedef struct {
     uint32_t sorter_depth;    /* per-pixel sorter capacity K, 2..32 (default 8) */
     uint32_t flags;           /* LR_FLAG_* */
     uint64_t hbm_budget_bytes;/* serving admission budget (0: arena size) */
+    uint32_t list_cap;        /* entries of a block's on-chip list: 256 (default) or
+                                 1024; blocks with more go to the dense pass */
+    uint32_t reserved;
 } lr_config;
 
 #define LR_FLAG_TIMING 1u     /* record per-stage times (hipEvents) */
@@ -115,6 +118,8 @@ typedef struct {
     uint8_t *out_rgba8;       /* device, width*height*4 bytes */
     uint32_t bin_size;        /* 0: context default */
     uint32_t sorter_depth;    /* 0: context default */
+    uint32_t list_cap;        /* 0: context default */
+    uint32_t reserved;
 } lr_request;
 
 /* Human-readable name of a status code (static storage). */
@@ -177,6 +182,12 @@ lr_status lr_sync(lr_context ctx);
 
 /* Wait, then fill *out with the statistics of the last render. */
 lr_status lr_get_stats(lr_context ctx, lr_stats *out);
+
+/* Per-stage times (microseconds, layout of lr_stats.stage_us) of the last
+ * min(max_frames, frames rendered, 1024) frames, oldest first, into
+ * us[frame][8]; *n_out receives the number of frames.  Needs a context
+ * created with LR_FLAG_TIMING; synchronises. */
+lr_status lr_get_stage_times(lr_context ctx, uint32_t max_frames, float *us, uint32_t *n_out);
 
 /* Parity dump of the setup stage for a render configuration (synchronous).
  * Per quad: X, Y [n][4] snapped vertices; bbox [n][4] (imin, imax, jmin, jmax

@@ -48,17 +48,31 @@ struct alignas(32) QuadXY {
     int32_t Y[4];
 };
 
+// Statistics are accumulated in kStripes copies, one 128-byte line each,
+// picked by workgroup index: device-scope atomics on one address serialize
+// across the XCDs, atomics on different lines do not.  The host sums them.
+constexpr uint32_t kStripes = 256;
+enum Stat { ST_CULL0 = 0, ST_ENTRIES = 6, ST_FRAGMENTS = 7, ST_COUNT = 8 };  // ST_CULL0 + reason
+
+// The queues of dense blocks and of flagged pixels are split the same way
+// into kQueues stripes (by block index), each with its counter in the
+// stripe's line; a stripe holds at most qcap_blocks blocks / 64 x that pixels.
+constexpr uint32_t kQueues = 64;
+
+struct alignas(128) StatStripe {
+    unsigned long long v[ST_COUNT];
+    uint32_t dense_n;   // blocks in dense-queue stripe
+    uint32_t flag_n;    // pixels in flagged-queue stripe
+    uint32_t pad[14];
+};
+static_assert(sizeof(StatStripe) == 128, "one line per stripe");
+
 // Device counters of one frame (zeroed by the first kernel of the frame).
 struct FrameCounters {
-    uint32_t visible;
-    uint32_t cull[6];
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
-    uint32_t flagged;          // pixels queued for the exact per-pixel sort
-    uint32_t dense;            // blocks queued for the dense list path
-    uint32_t pad;
-    unsigned long long entries;    // non-empty (block, quad) pairs
-    unsigned long long fragments;  // covered samples
+    uint32_t pad[30];
+    StatStripe stripe[kStripes];
 };
 
 constexpr uint32_t kErrPairs = 1u;      // bin lists overflowed their capacity
@@ -97,8 +111,10 @@ struct FrameArgs {
     uint32_t match_bits;    // bits needed to hold a bin index
     // raster
     uint32_t nblk_x, nblk_y;  // 8x8 blocks
-    uint32_t *fb_queue;       // flagged pixel indices [W*H]
-    uint32_t *dense_queue;    // dense block indices [nblk_x*nblk_y]
+    uint32_t list_cap;        // per-wave block list entries (256 or 1024)
+    uint32_t qcap_blocks;     // blocks per queue stripe: ceil(nblk_x*nblk_y / kQueues)
+    uint32_t *fb_queue;       // flagged pixels [kQueues][qcap_blocks * 64]
+    uint32_t *dense_queue;    // dense blocks [kQueues][qcap_blocks]
     FrameCounters *ctr;
     uint8_t *out;             // RGBA8
     // debug outputs (may be null)

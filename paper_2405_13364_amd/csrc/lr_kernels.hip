@@ -132,11 +132,16 @@ __device__ __forceinline__ uint32_t pack_rgba8(float R, float G, float B, float 
 
 // ------------------------------------------------------------- frame begin
 
-__global__ void k_frame_begin(FrameCounters *c)
+__global__ __launch_bounds__(256) void k_frame_begin(FrameCounters *c)
 {
-    uint32_t *p = reinterpret_cast<uint32_t *>(c);
-    for (uint32_t i = threadIdx.x; i < sizeof(FrameCounters) / 4; i += blockDim.x)
-        p[i] = 0;
+    uint4 *p = reinterpret_cast<uint4 *>(c);
+    for (uint32_t i = threadIdx.x; i < sizeof(FrameCounters) / 16; i += blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__device__ __forceinline__ void add_stat(FrameCounters *c, uint32_t stat, unsigned long long v)
+{
+    atomicAdd(&c->stripe[blockIdx.x % kStripes].v[stat], v);
 }
 
 // ------------------------------------------------------------------- setup
@@ -302,15 +307,20 @@ __global__ __launch_bounds__(256) void k_setup(FrameArgs a)
         a.bbox[q] = bb;
         a.cull[q] = (uint8_t)reason;
     }
+    // cull statistics: one atomic per workgroup and reason, striped
+    __shared__ uint32_t s_cull[6];
+    if (threadIdx.x < 6)
+        s_cull[threadIdx.x] = 0;
+    __syncthreads();
     const uint32_t lane = lane_id();
     for (uint32_t r = 0; r < 6; r++) {
         uint64_t m = ballot(reason == r);
-        if (m && lane == 0) {
-            if (r == 0)
-                atomicAdd(&a.ctr->visible, (uint32_t)__popcll(m));
-            atomicAdd(&a.ctr->cull[r], (uint32_t)__popcll(m));
-        }
+        if (m && lane == 0)
+            atomicAdd(&s_cull[r], (uint32_t)__popcll(m));
     }
+    __syncthreads();
+    if (threadIdx.x < 6 && s_cull[threadIdx.x])
+        add_stat(a.ctr, ST_CULL0 + threadIdx.x, s_cull[threadIdx.x]);
 }
 
 // ----------------------------------------------------------------- binning
@@ -371,11 +381,18 @@ __global__ __launch_bounds__(64) void k_bin_scan_tiles(FrameArgs a)
         return;
     const uint32_t u0 = tile * 64, u1 = min(u0 + 64, a.nunits);
     uint32_t run = 0;
-    for (uint32_t u = u0; u < u1; u++) {
-        uint32_t *p = a.table + (size_t)u * a.nbins + b;
-        uint32_t v = *p;
-        *p = run;
-        run += v;
+    // loads of a group are issued before its stores so they overlap in flight
+    for (uint32_t g = u0; g < u1; g += 16) {
+        uint32_t v[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            if (g + k < u1)
+                a.table[(size_t)(g + k) * a.nbins + b] = run;
+            run += v[k];
+        }
     }
     a.tile_sums[(size_t)tile * a.nbins + b] = run;
 }
@@ -495,108 +512,40 @@ __global__ __launch_bounds__(64) void k_bin_scatter(FrameArgs a, const uint2 *__
 }
 
 // ------------------------------------------------------------------ raster
+//
+// One workgroup per bin (Stage 3: a workgroup rasterizes a bin, its
+// subgroups work on blocks).  Each wave owns one 8x8 block at a time.  The
+// bin's quad list is read in chunks shared by the workgroup; each wave picks
+// from a chunk, by ballot, the quads whose bbox meets its block and gathers
+// them into batches of 64.  A batch is processed one candidate per lane:
+// gather the quad's record, build its 64-sample coverage mask of the block,
+// keep the non-empty ones.
 
-// Work item -> 8x8 block.  Items are ordered bin by bin (blocks of a bin are
-// consecutive) and split into 8 contiguous ranges, one per XCD: workgroup w
-// is dispatched to XCD w % 8, so the blocks of one bin share that XCD's L2.
-__device__ __forceinline__ bool map_block(const FrameArgs &a, uint32_t w, uint32_t &bxk, uint32_t &byk)
+__device__ __forceinline__ void wave_sync()
 {
-    const uint32_t bpb = 1u << (a.bin_shift - 3);  // blocks per bin side
-    const uint32_t per_bin = bpb * bpb;
-    const uint32_t total = a.nbins * per_bin;
-    const uint32_t per_xcd = (total + 7) / 8;
-    const uint32_t wi = (w & 7) * per_xcd + (w >> 3);
-    if (wi >= total)
-        return false;
-    const uint32_t bin = wi / per_bin, in = wi % per_bin;
-    bxk = (bin % a.nbx) * bpb + in % bpb;
-    byk = (bin / a.nbx) * bpb + in / bpb;
-    return bxk < a.nblk_x && byk < a.nblk_y;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Coverage of one quad over the 64 samples of a block (one bit per lane,
-// lane = 8*ly + lx), exact under the top-left rule.
-__device__ __forceinline__ uint64_t block_coverage(const QuadRec *__restrict__ rec,
-                                                   const QuadXY *__restrict__ xyp, uint32_t q, int px,
-                                                   int py)
+// Exact coverage of the quad's triangle pair at pixel (px, py) with fp64
+// edge functions (all products stay below 2^50).  For quads wider than
+// kNarrowExtent.
+__device__ bool wide_covers(uint32_t flags, const QuadXY &xy, int px, int py)
 {
-    const QuadRec &r = rec[q];
-    const uint32_t flags = r.flags;
-    if (!(flags & kWide)) {
-        const int di = px - (int)(r.bb_i & 0xffffu);
-        const int dj = py - (int)(r.bb_j & 0xffffu);
-        const int *hp = r.hp;
-        int L0 = __mul24(hp[0], di) + __mul24(hp[1], dj);
-        int L1 = __mul24(hp[3], di) + __mul24(hp[4], dj);
-        int L2 = __mul24(hp[6], di) + __mul24(hp[7], dj);
-        int L3 = __mul24(hp[9], di) + __mul24(hp[10], dj);
-        int L4 = __mul24(hp[12], di) + __mul24(hp[13], dj);
-        int L5 = __mul24(hp[15], di) + __mul24(hp[16], dj);
-        uint64_t t0 = ballot(L0 >= hp[2] && L1 >= hp[5] && L2 >= hp[8]);
-        uint64_t t1 = ballot(L3 >= hp[11] && L4 >= hp[14] && L5 >= hp[17]);
-        return t0 | t1;
-    }
-    // wide quad: exact fp64 edge functions (all products below 2^50)
-    const QuadXY xy = xyp[q];
     const double Sx = 256.0 * (double)px + 128.0, Sy = 256.0 * (double)py + 128.0;
     bool in = false;
     for (int T = 0; T < 2; T++) {
         const uint32_t vb = T ? kT1Valid : kT0Valid, sb = T ? kT1Swap : kT0Swap;
         if (!(flags & vb))
             continue;
-        int ia = 0, ib = T ? 2 : 1, ic = T ? 3 : 2;
+        int ib = T ? 2 : 1, ic = T ? 3 : 2;
         if (flags & sb) {
             int t = ib;
             ib = ic;
             ic = t;
         }
-        const int idx[3] = {ia, ib, ic};
-        bool inside = true;
-        for (int e = 0; e < 3; e++) {
-            const int s = idx[e], t = idx[(e + 1) % 3];
-            const double dx = (double)xy.X[t] - (double)xy.X[s];
-            const double dy = (double)xy.Y[t] - (double)xy.Y[s];
-            const double E = dx * (Sy - (double)xy.Y[s]) - dy * (Sx - (double)xy.X[s]);
-            const bool tl = (dy < 0.0) || (dy == 0.0 && dx > 0.0);
-            if (!(E > 0.0 || (E == 0.0 && tl)))
-                inside = false;
-        }
-        in = in || inside;
-    }
-    return ballot(in);
-}
-
-// Single-sample coverage (one lane, one quad), same rule.
-__device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q,
-                                               int px, int py)
-{
-    const uint32_t flags = r.flags;
-    if (!(flags & kWide)) {
-        const int di = px - (int)(r.bb_i & 0xffffu);
-        const int dj = py - (int)(r.bb_j & 0xffffu);
-        const int *hp = r.hp;
-        bool t0 = (__mul24(hp[0], di) + __mul24(hp[1], dj) >= hp[2]) &&
-                  (__mul24(hp[3], di) + __mul24(hp[4], dj) >= hp[5]) &&
-                  (__mul24(hp[6], di) + __mul24(hp[7], dj) >= hp[8]);
-        bool t1 = (__mul24(hp[9], di) + __mul24(hp[10], dj) >= hp[11]) &&
-                  (__mul24(hp[12], di) + __mul24(hp[13], dj) >= hp[14]) &&
-                  (__mul24(hp[15], di) + __mul24(hp[16], dj) >= hp[17]);
-        return t0 || t1;
-    }
-    const QuadXY xy = xyp[q];
-    const double Sx = 256.0 * (double)px + 128.0, Sy = 256.0 * (double)py + 128.0;
-    bool in = false;
-    for (int T = 0; T < 2; T++) {
-        const uint32_t vb = T ? kT1Valid : kT0Valid, sb = T ? kT1Swap : kT0Swap;
-        if (!(flags & vb))
-            continue;
-        int ia = 0, ib = T ? 2 : 1, ic = T ? 3 : 2;
-        if (flags & sb) {
-            int t = ib;
-            ib = ic;
-            ic = t;
-        }
-        const int idx[3] = {ia, ib, ic};
+        const int idx[3] = {0, ib, ic};
         bool inside = true;
         for (int e = 0; e < 3; e++) {
             const int s = idx[e], t = idx[(e + 1) % 3];
@@ -612,8 +561,81 @@ __device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *_
     return in;
 }
 
+// Coverage of one quad over the 64 samples of an 8x8 block, computed by one
+// lane (bit 8*y + x for pixel (px0 + x, py0 + y)), exact under the top-left
+// rule.  Narrow quads step their six integer edge values across the block:
+// sample inside half-plane h iff E_h = a*di + b*dj - t >= 0, and
+// |a*di + b*dj| < 2^30, |t| < 2^30 for narrow quads, so E never overflows.
+__device__ uint64_t lane_block_mask(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q, int px0, int py0)
+{
+    const uint32_t flags = r.flags;
+    if (!(flags & kWide)) {
+        int hp[18];
+#pragma unroll
+        for (int k = 0; k < 18; k++)
+            hp[k] = r.hp[k];
+        const int di = px0 - (int)(r.bb_i & 0xffffu);
+        const int dj = py0 - (int)(r.bb_j & 0xffffu);
+        int row[6];
+#pragma unroll
+        for (int h = 0; h < 6; h++)
+            row[h] = hp[3 * h] * di + hp[3 * h + 1] * dj - hp[3 * h + 2];
+        uint32_t lo = 0, hi = 0;
+#pragma unroll
+        for (int y = 0; y < 8; y++) {
+            int e[6];
+#pragma unroll
+            for (int h = 0; h < 6; h++)
+                e[h] = row[h];
+#pragma unroll
+            for (int x = 0; x < 8; x++) {
+                // covered iff one triangle has all three edge values >= 0
+                const int both = (e[0] | e[1] | e[2]) & (e[3] | e[4] | e[5]);
+                const uint32_t bit = ~(uint32_t)both >> 31;
+                if (y < 4)
+                    lo |= bit << (8 * y + x);
+                else
+                    hi |= bit << (8 * (y - 4) + x);
+#pragma unroll
+                for (int h = 0; h < 6; h++)
+                    e[h] += hp[3 * h];
+            }
+#pragma unroll
+            for (int h = 0; h < 6; h++)
+                row[h] += hp[3 * h + 1];
+        }
+        return (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+    const QuadXY xy = xyp[q];
+    uint64_t m = 0;
+    for (int k = 0; k < 64; k++)
+        if (wide_covers(flags, xy, px0 + (k & 7), py0 + (k >> 3)))
+            m |= 1ull << k;
+    return m;
+}
+
+// Single-sample coverage (one lane, one quad), same rule.
+__device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q,
+                                               int px, int py)
+{
+    if (!(r.flags & kWide)) {
+        const int di = px - (int)(r.bb_i & 0xffffu);
+        const int dj = py - (int)(r.bb_j & 0xffffu);
+        const int *hp = r.hp;
+        const bool t0 = (__mul24(hp[0], di) + __mul24(hp[1], dj) >= hp[2]) &&
+                        (__mul24(hp[3], di) + __mul24(hp[4], dj) >= hp[5]) &&
+                        (__mul24(hp[6], di) + __mul24(hp[7], dj) >= hp[8]);
+        const bool t1 = (__mul24(hp[9], di) + __mul24(hp[10], dj) >= hp[11]) &&
+                        (__mul24(hp[12], di) + __mul24(hp[13], dj) >= hp[14]) &&
+                        (__mul24(hp[15], di) + __mul24(hp[16], dj) >= hp[17]);
+        return t0 || t1;
+    }
+    return wide_covers(r.flags, xyp[q], px, py);
+}
+
 // Block key: the quad's depth at the centroid of its covered samples in the
-// block (Stage 3, phase 2), fp32; smaller key = nearer.
+// block (Stage 3, phase 2), fp32; smaller code = nearer.  A heuristic only:
+// the per-pixel sorter and its exact fallback decide the final order.
 __device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t m, int px0, int py0)
 {
     const float cnt = (float)__popcll(m);
@@ -629,16 +651,18 @@ __device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t 
     return 0x7F800000u - min(__float_as_uint(k), 0x7F800000u);  // < 2^31
 }
 
-// Stable-order bitonic sort of n keys in LDS by one wave (ascending).
+// Ascending bitonic sort of n keys in wave-private LDS by one wave.
 template <typename KeyT>
 __device__ void wave_bitonic_sort(KeyT *keys, uint32_t n, KeyT pad, uint32_t lane)
 {
+    if (n < 2)
+        return;
     uint32_t P = 2;
     while (P < n)
         P <<= 1;
     for (uint32_t i = n + lane; i < P; i += 64)
         keys[i] = pad;
-    __syncthreads();
+    wave_sync();
     for (uint32_t k = 2; k <= P; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
             for (uint32_t t = lane; t < P / 2; t += 64) {
@@ -651,7 +675,7 @@ __device__ void wave_bitonic_sort(KeyT *keys, uint32_t n, KeyT pad, uint32_t lan
                     keys[ixj] = x;
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
     }
 }
@@ -662,13 +686,21 @@ struct Stage {
     uint32_t rgba;
 };
 
+// Per-wave LDS: candidate batch, block entry list, phase-3 staging.
 template <int CAP>
-struct RasterLds {
+struct WaveLds {
+    uint32_t cand[128];
     uint64_t mask[CAP];
     uint32_t id[CAP];
     uint32_t key[CAP];
     Stage stage[64];
     uint32_t sid[64];
+};
+
+template <int NW>
+struct BinChunk {
+    uint32_t q[NW * 64];
+    uint2 bb[NW * 64];
 };
 
 constexpr uint32_t slot_bits(uint32_t cap)
@@ -679,85 +711,153 @@ constexpr uint32_t slot_bits(uint32_t cap)
     return b;
 }
 
-// Queue a pixel for the exact per-pixel sort (wave-aggregated).
-__device__ __forceinline__ void push_flagged(const FrameArgs &a, bool flag, uint32_t pix, uint32_t lane)
+struct BlockGeom {
+    int px0, py0, px1, py1;  // block pixel rect clipped to the screen
+    int px, py;              // this lane's pixel
+    uint32_t blk, pix;
+    uint64_t onmask;
+    bool active, on;
+};
+
+__device__ __forceinline__ BlockGeom block_geom(const FrameArgs &a, uint32_t bxk, uint32_t byk, bool valid,
+                                                uint32_t lane)
+{
+    BlockGeom g;
+    g.active = valid && bxk < a.nblk_x && byk < a.nblk_y;
+    g.px0 = (int)bxk * 8;
+    g.py0 = (int)byk * 8;
+    g.px1 = min(g.px0 + 7, (int)a.W - 1);
+    g.py1 = min(g.py0 + 7, (int)a.H - 1);
+    g.px = g.px0 + (int)(lane & 7);
+    g.py = g.py0 + (int)(lane >> 3);
+    g.on = g.active && g.px < (int)a.W && g.py < (int)a.H;
+    g.onmask = ballot(g.on);
+    g.blk = byk * a.nblk_x + bxk;
+    g.pix = g.on ? (uint32_t)g.py * a.W + (uint32_t)g.px : 0;
+    return g;
+}
+
+// Phase 1 of a block: walks the bin list; every batch of up to 64
+// candidates (quads whose bbox meets the block, in list = ascending quad
+// order) goes to on_batch(m): lane e < m holds cand[e].  All waves of the
+// workgroup call this together (the chunk loads are shared).
+template <int NW, typename Lds, typename F>
+__device__ void scan_bin(const uint2 *__restrict__ bbox, const uint32_t *__restrict__ pairs, BinChunk<NW> &C,
+                         Lds &L, uint32_t start, uint32_t cnt, const BlockGeom &g, F &&on_batch)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    uint32_t nc = 0;
+    for (uint32_t base = 0; base < cnt; base += NW * 64) {
+        const uint32_t t = base + tid;
+        if (t < cnt) {
+            const uint32_t q = pairs[start + t];
+            C.q[tid] = q;
+            C.bb[tid] = bbox[q];
+        }
+        __syncthreads();
+        const uint32_t m = min(cnt - base, (uint32_t)NW * 64);
+        if (g.active) {
+            for (uint32_t c = 0; c < m; c += 64) {
+                const uint32_t e = c + lane;
+                bool ov = false;
+                uint32_t q = 0;
+                if (e < m) {
+                    q = C.q[e];
+                    const uint2 bb = C.bb[e];
+                    ov = (int)(bb.x & 0xffffu) <= g.px1 && (int)(bb.x >> 16) >= g.px0 &&
+                         (int)(bb.y & 0xffffu) <= g.py1 && (int)(bb.y >> 16) >= g.py0;
+                }
+                const uint64_t b = ballot(ov);
+                if (ov)
+                    L.cand[nc + rank_below(b)] = q;
+                nc += (uint32_t)__popcll(b);
+                if (nc >= 64) {
+                    wave_sync();
+                    on_batch(64u);
+                    wave_sync();
+                    // carry the overflow to the front of the batch buffer
+                    if (lane + 64 < nc)
+                        L.cand[lane] = L.cand[lane + 64];
+                    nc -= 64;
+                    wave_sync();
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (g.active && nc) {
+        wave_sync();
+        on_batch(nc);
+        wave_sync();
+    }
+}
+
+// Queue a block's pixels for the exact per-pixel sort (wave-aggregated, on
+// the block's queue stripe).
+__device__ __forceinline__ void push_flagged(const FrameArgs &a, bool flag, const BlockGeom &g, uint32_t lane)
 {
     const uint64_t m = ballot(flag);
     if (!m)
         return;
+    const uint32_t s = g.blk % kQueues;
     uint32_t base = 0;
     if (lane == 0)
-        base = atomicAdd(&a.ctr->flagged, (uint32_t)__popcll(m));
+        base = atomicAdd(&a.ctr->stripe[s].flag_n, (uint32_t)__popcll(m));
     base = lane_value(base, 0);
     if (flag)
-        a.fb_queue[base + rank_below(m)] = pix;
+        a.fb_queue[(size_t)s * a.qcap_blocks * 64 + base + rank_below(m)] = g.pix;
 }
 
-// One 8x8 block, sorted path.  Returns false when the block's list exceeds
-// CAP (nothing written).
-template <int K, int CAP, bool DEBUG>
-__device__ bool raster_sorted_block(const FrameArgs &a, const QuadRec *__restrict__ rec,
-                                    const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
-                                    const uint32_t *__restrict__ pairs, RasterLds<CAP> &L, uint32_t bxk,
-                                    uint32_t byk, bool last_resort)
+__device__ __forceinline__ void push_dense(const FrameArgs &a, const BlockGeom &g, uint32_t lane)
+{
+    if (lane == 0) {
+        const uint32_t s = g.blk % kQueues;
+        const uint32_t slot = atomicAdd(&a.ctr->stripe[s].dense_n, 1u);
+        a.dense_queue[(size_t)s * a.qcap_blocks + slot] = g.blk;
+    }
+}
+
+// Phase-1 batch of the sorted path: masks and block keys of the candidates,
+// non-empty ones appended to the block list (n counts every entry, also
+// past CAP).
+template <int CAP>
+__device__ __forceinline__ void sorted_batch(const QuadRec *__restrict__ rec, const QuadXY *__restrict__ xyp,
+                                             WaveLds<CAP> &L, uint32_t m, const BlockGeom &g, uint32_t lane,
+                                             uint32_t &n)
 {
     constexpr uint32_t SB = slot_bits(CAP);
-    const uint32_t lane = threadIdx.x;
-    const int px0 = (int)bxk * 8, py0 = (int)byk * 8;
-    const int px = px0 + (int)(lane & 7), py = py0 + (int)(lane >> 3);
-    const bool on = px < (int)a.W && py < (int)a.H;
-    const uint64_t onmask = ballot(on);
-    const uint32_t pix = on ? (uint32_t)py * a.W + (uint32_t)px : 0;
-    const int px1 = min(px0 + 7, (int)a.W - 1), py1 = min(py0 + 7, (int)a.H - 1);
-    const uint32_t bin = ((uint32_t)py0 >> a.bin_shift) * a.nbx + ((uint32_t)px0 >> a.bin_shift);
-    const uint32_t start = uniform(a.bin_start[bin]);
-    const uint32_t cnt = uniform(a.bin_count[bin]);
-
-    // ---- phase 1: coverage masks and block keys of the bin's quads
-    uint32_t n = 0;
-    for (uint32_t base = 0; base < cnt; base += 64) {
-        const uint32_t l = base + lane;
-        uint32_t qid = 0;
-        bool ov = false;
-        if (l < cnt) {
-            qid = pairs[start + l];
-            const uint2 bb = bbox[qid];
-            ov = (int)(bb.x & 0xffffu) <= px1 && (int)(bb.x >> 16) >= px0 && (int)(bb.y & 0xffffu) <= py1 &&
-                 (int)(bb.y >> 16) >= py0;
-        }
-        uint64_t cand = ballot(ov);
-        while (cand) {
-            const uint32_t s = (uint32_t)__builtin_ctzll(cand);
-            cand &= cand - 1;
-            const uint32_t q = lane_value(qid, s);
-            const uint64_t m = block_coverage(rec, xyp, q, px, py) & onmask;
-            if (m) {
-                if (n < CAP && lane == 0) {
-                    L.mask[n] = m;
-                    L.id[n] = q;
-                    L.key[n] = ((block_depth_code(rec[q], m, px0, py0) >> (SB - 1)) << SB) | n;
-                }
-                n++;
-            }
-        }
+    uint64_t mk = 0;
+    uint32_t q = 0, code = 0;
+    if (lane < m) {
+        q = L.cand[lane];
+        const QuadRec &r = rec[q];
+        mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
+        if (mk)
+            code = block_depth_code(r, mk, g.px0, g.py0);
     }
-    if (n > CAP) {
-        if (!last_resort)
-            return false;
-        // no list can hold this block: every pixel takes the exact path
-        push_flagged(a, on, pix, lane);
-        if (lane == 0)
-            atomicOr(&a.ctr->error, kErrDense);
-        if (DEBUG && on && a.dbg_flag)
-            a.dbg_flag[pix] = 1;
-        return true;
+    const uint64_t b = ballot(mk != 0);
+    const uint32_t slot = n + rank_below(b);
+    if (mk && slot < CAP) {
+        L.mask[slot] = mk;
+        L.id[slot] = q;
+        L.key[slot] = ((code >> (SB - 1)) << SB) | slot;
     }
-    __syncthreads();
+    n += (uint32_t)__popcll(b);
+}
 
-    // ---- phase 2: depth-sort the block's entries
+// Phases 2 and 3 of a block whose n entries are in L: depth-sort the
+// entries, then one lane per pixel walks them (in 64-entry segments whose
+// coverage masks are transposed to per-pixel bit sets) through a K-deep
+// sorter, blending each fragment the sorter emits.  A pixel whose emitted
+// codes stop strictly increasing is queued for the exact path.
+template <int K, int CAP, bool DEBUG>
+__device__ void finish_sorted(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds<CAP> &L, uint32_t n,
+                              const BlockGeom &g, uint32_t lane)
+{
+    constexpr uint32_t SB = slot_bits(CAP);
+    wave_sync();
     wave_bitonic_sort<uint32_t>(L.key, n, 0xFFFFFFFFu, lane);
 
-    // ---- phase 3: per-pixel K-deep sorter and front-to-back blend
     uint32_t qk[K], qc[K], qi[DEBUG ? K : 1];
 #pragma unroll
     for (int j = 0; j < K; j++) {
@@ -769,14 +869,14 @@ __device__ bool raster_sorted_block(const FrameArgs &a, const QuadRec *__restric
     uint32_t last = 0, nfrag = 0, npop = 0;
     bool flagged = false;
     float T = 1.0f, R = 0.0f, G = 0.0f, B = 0.0f;
-    const uint32_t obase = (DEBUG && on && a.dbg_off) ? a.dbg_off[pix] : 0;
+    const uint32_t obase = (DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0;
 
     auto emit = [&](uint32_t pk, uint32_t pc, uint32_t pi) {
         flagged |= (pk - 1u) < last;  // pops must strictly increase (placeholders excepted)
         last = pk;
         blend_ftb(pc, T, R, G, B);
         if (DEBUG && pk != 0) {
-            if (a.dbg_ids && on && obase + npop < a.dbg_cap)
+            if (a.dbg_ids && g.on && obase + npop < a.dbg_cap)
                 a.dbg_ids[obase + npop] = pi;
             npop++;
         }
@@ -800,15 +900,16 @@ __device__ bool raster_sorted_block(const FrameArgs &a, const QuadRec *__restric
             if (DEBUG)
                 L.sid[lane] = q;
         }
-        __syncthreads();
+        wave_sync();
         uint64_t col = transpose64(m, lane);
-        if (!on || flagged)
+        if (!g.on || flagged)
             col = 0;
         while (col) {
             const uint32_t k = (uint32_t)__builtin_ctzll(col);
             col &= col - 1;
             const Stage st = L.stage[k];
-            const float kf = frag_key(st.A, st.B, st.C0, px - (int)(st.ij & 0xffffu), py - (int)(st.ij >> 16));
+            const float kf =
+                frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
             const uint32_t x = order_code(kf);
             const uint32_t xc = st.rgba;
             const uint32_t xi = DEBUG ? L.sid[k] : 0;
@@ -839,256 +940,285 @@ __device__ bool raster_sorted_block(const FrameArgs &a, const QuadRec *__restric
             if (flagged)
                 col = 0;
         }
-        __syncthreads();
+        wave_sync();
     }
-    if (on && !flagged) {
+    if (g.on && !flagged) {
 #pragma unroll
         for (int j = 0; j < K; j++)
             emit(qk[j], qc[j], DEBUG ? qi[j] : 0);
     }
-    push_flagged(a, on && flagged, pix, lane);
-    if (on && !flagged) {
-        reinterpret_cast<uint32_t *>(a.out)[pix] = pack_rgba8(R, G, B, 1.0f - T);
-        if (DEBUG && a.dbg_rgba) {
-            float4 o = make_float4(R, G, B, 1.0f - T);
-            reinterpret_cast<float4 *>(a.dbg_rgba)[pix] = o;
-        }
+    push_flagged(a, g.on && flagged, g, lane);
+    if (g.on && !flagged) {
+        reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(R, G, B, 1.0f - T);
+        if (DEBUG && a.dbg_rgba)
+            reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(R, G, B, 1.0f - T);
     }
-    if (DEBUG && on) {
+    if (DEBUG && g.on) {
         if (a.dbg_count)
-            a.dbg_count[pix] = nfrag;
+            a.dbg_count[g.pix] = nfrag;
         if (a.dbg_flag)
-            a.dbg_flag[pix] = flagged ? 1 : 0;
+            a.dbg_flag[g.pix] = flagged ? 1 : 0;
     }
     // statistics (flagged pixels are counted by the exact path)
-    uint32_t wsum = (on && !flagged) ? nfrag : 0;
+    uint32_t wsum = (g.on && !flagged) ? nfrag : 0;
     for (int off = 32; off > 0; off >>= 1)
         wsum += shfl_xor(wsum, off);
     if (lane == 0) {
-        atomicAdd(&a.ctr->entries, (unsigned long long)n);
-        atomicAdd(&a.ctr->fragments, (unsigned long long)wsum);
+        add_stat(a.ctr, ST_ENTRIES, n);
+        if (wsum)
+            add_stat(a.ctr, ST_FRAGMENTS, wsum);
     }
-    return true;
 }
 
-template <int K, bool DEBUG>
-__global__ __launch_bounds__(64) void k_raster(FrameArgs a, const QuadRec *__restrict__ rec,
-                                               const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
-                                               const uint32_t *__restrict__ pairs)
+template <int K, int NW, int CAP, bool DEBUG>
+__global__ __launch_bounds__(NW * 64) void k_raster(FrameArgs a, const QuadRec *__restrict__ rec,
+                                                    const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
+                                                    const uint32_t *__restrict__ pairs)
 {
-    __shared__ RasterLds<1024> L;
-    uint32_t bxk, byk;
-    if (!map_block(a, blockIdx.x, bxk, byk))
-        return;
+    __shared__ BinChunk<NW> C;
+    __shared__ WaveLds<CAP> Lw[NW];
     if (a.ctr->error & kErrPairs)
         return;  // bin lists are incomplete: the frame is reported as failed
-    if (!raster_sorted_block<K, 1024, DEBUG>(a, rec, xyp, bbox, pairs, L, bxk, byk, false)) {
-        if (threadIdx.x == 0) {
-            uint32_t slot = atomicAdd(&a.ctr->dense, 1u);
-            a.dense_queue[slot] = byk * a.nblk_x + bxk;
+    const uint32_t bin = blockIdx.x;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t bpb = 1u << (a.bin_shift - 3), nb = bpb * bpb;
+    const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
+    const uint32_t bx_bin = (bin % a.nbx) * bpb, by_bin = (bin / a.nbx) * bpb;
+    WaveLds<CAP> &L = Lw[wave];
+    for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
+        const uint32_t k = r0 + wave;
+        const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
+        uint32_t n = 0;
+        scan_bin<NW>(bbox, pairs, C, L, start, cnt, g,
+                          [&](uint32_t m) { sorted_batch<CAP>(rec, xyp, L, m, g, lane, n); });
+        if (g.active) {
+            if (n > CAP)
+                push_dense(a, g, lane);
+            else
+                finish_sorted<K, CAP, DEBUG>(a, rec, L, n, g, lane);
         }
     }
 }
 
-// Blocks whose list outgrew the on-chip list of k_raster: one wave per
-// block with a list eight times longer.
+// Blocks whose list outgrew the workgroup's per-wave list: one wave per
+// block with a 4096-entry list; deeper blocks send their pixels to the exact
+// per-pixel path.
+constexpr uint32_t kDenseCap = 4096;
+
 template <int K, bool DEBUG>
 __global__ __launch_bounds__(64) void k_raster_dense(FrameArgs a, const QuadRec *__restrict__ rec,
                                                      const QuadXY *__restrict__ xyp,
                                                      const uint2 *__restrict__ bbox,
                                                      const uint32_t *__restrict__ pairs)
 {
-    __shared__ RasterLds<8192> L;
+    __shared__ BinChunk<1> C;
+    __shared__ WaveLds<kDenseCap> L;
     if (a.ctr->error & kErrPairs)
         return;
-    const uint32_t count = uniform(a.ctr->dense);
-    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
-        const uint32_t blk = uniform(a.dense_queue[t]);
-        raster_sorted_block<K, 8192, DEBUG>(a, rec, xyp, bbox, pairs, L, blk % a.nblk_x, blk / a.nblk_x,
-                                            true);
+    const uint32_t lane = threadIdx.x;
+    const uint32_t s = blockIdx.x % kQueues, G = gridDim.x / kQueues;
+    const uint32_t count = uniform(a.ctr->stripe[s].dense_n);
+    for (uint32_t t = blockIdx.x / kQueues; t < count; t += G) {
+        const uint32_t blk = uniform(a.dense_queue[(size_t)s * a.qcap_blocks + t]);
+        const uint32_t bxk = blk % a.nblk_x, byk = blk / a.nblk_x;
+        const BlockGeom g = block_geom(a, bxk, byk, true, lane);
+        const uint32_t bin = (byk * 8 >> a.bin_shift) * a.nbx + (bxk * 8 >> a.bin_shift);
+        const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
+        uint32_t n = 0;
+        scan_bin<1>(bbox, pairs, C, L, start, cnt, g,
+                               [&](uint32_t m) { sorted_batch<kDenseCap>(rec, xyp, L, m, g, lane, n); });
+        if (n > kDenseCap) {
+            // no list holds this block: every pixel takes the exact path
+            push_flagged(a, g.on, g, lane);
+            if (lane == 0)
+                atomicOr(&a.ctr->error, kErrDense);
+            if (DEBUG && g.on && a.dbg_flag)
+                a.dbg_flag[g.pix] = 1;
+        } else {
+            finish_sorted<K, kDenseCap, DEBUG>(a, rec, L, n, g, lane);
+        }
         __syncthreads();
     }
 }
 
 // --------------------------------------------------------- exact per pixel
+//
+// One wave per flagged pixel: every quad of the pixel's bin is tested on the
+// single sample, covering fragments are sorted by their full (code, index)
+// key in LDS and blended in order.  Pixels deeper than the LDS buffer are
+// done in rounds: each round keeps only keys above the last blended key and,
+// when the buffer fills, sorts it and keeps its lower half (raising an upper
+// cut), so a round blends the smallest keys left, at least half a buffer.
 
-constexpr uint32_t kFallbackCap = 4096;
+constexpr uint32_t kFallbackBuf = 4096;
 
 template <bool DEBUG>
 __global__ __launch_bounds__(64) void k_fallback(FrameArgs a, const QuadRec *__restrict__ rec,
                                                  const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
                                                  const uint32_t *__restrict__ pairs)
 {
-    __shared__ unsigned long long s_key[kFallbackCap];
+    __shared__ unsigned long long s_key[kFallbackBuf];
     if (a.ctr->error & kErrPairs)
         return;
     const uint32_t lane = threadIdx.x;
-    const uint32_t count = uniform(a.ctr->flagged);
-    for (uint32_t t = blockIdx.x; t < count; t += gridDim.x) {
-        const uint32_t p = uniform(a.fb_queue[t]);
+    const uint32_t sq = blockIdx.x % kQueues, G = gridDim.x / kQueues;
+    const uint32_t count = uniform(a.ctr->stripe[sq].flag_n);
+    for (uint32_t t = blockIdx.x / kQueues; t < count; t += G) {
+        const uint32_t p = uniform(a.fb_queue[(size_t)sq * a.qcap_blocks * 64 + t]);
         const int i = (int)(p % a.W), j = (int)(p / a.W);
         const uint32_t bin = ((uint32_t)j >> a.bin_shift) * a.nbx + ((uint32_t)i >> a.bin_shift);
         const uint32_t start = uniform(a.bin_start[bin]);
         const uint32_t cnt = uniform(a.bin_count[bin]);
-        uint32_t n = 0;
-        for (uint32_t base = 0; base < cnt; base += 64) {
-            const uint32_t l = base + lane;
-            bool cov = false;
-            unsigned long long key = 0;
-            if (l < cnt) {
-                const uint32_t q = pairs[start + l];
-                const uint2 bb = bbox[q];
-                if ((int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
-                    (int)(bb.y >> 16) >= j) {
-                    const QuadRec &r = rec[q];
-                    if (pixel_coverage(r, xyp, q, i, j)) {
-                        cov = true;
-                        const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
-                                                  j - (int)(r.bb_j & 0xffffu));
-                        key = ((unsigned long long)order_code(kf) << 32) | q;
+        const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
+        float T = 1.0f, R = 0.0f, G2 = 0.0f, B = 0.0f;
+        unsigned long long lo = 0;  // keys <= lo are blended already (real keys are > 0)
+        uint32_t total = 0, done = 0;
+        for (bool more = true; more;) {
+            unsigned long long hi = ~0ull;  // the buffer holds every key in (lo, hi]
+            bool cut = false;
+            uint32_t n = 0, seen = 0;
+            for (uint32_t base = 0; base < cnt; base += 64) {
+                if (n + 64 > kFallbackBuf) {
+                    // keep the lower half of the buffer
+                    wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
+                    n = kFallbackBuf / 2;
+                    hi = s_key[n - 1];
+                    cut = true;
+                    wave_sync();
+                }
+                const uint32_t l = base + lane;
+                bool cov = false;
+                unsigned long long key = 0;
+                if (l < cnt) {
+                    const uint32_t q = pairs[start + l];
+                    const uint2 bb = bbox[q];
+                    if ((int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
+                        (int)(bb.y >> 16) >= j) {
+                        const QuadRec &r = rec[q];
+                        if (pixel_coverage(r, xyp, q, i, j)) {
+                            cov = true;
+                            const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
+                                                      j - (int)(r.bb_j & 0xffffu));
+                            key = ((unsigned long long)order_code(kf) << 32) | q;
+                        }
                     }
                 }
+                seen += (uint32_t)__popcll(ballot(cov));
+                const bool keep = cov && key > lo && key <= hi;
+                const uint64_t m = ballot(keep);
+                if (keep)
+                    s_key[n + rank_below(m)] = key;
+                n += (uint32_t)__popcll(m);
+                wave_sync();
             }
-            const uint64_t m = ballot(cov);
-            const uint32_t pos = n + rank_below(m);
-            if (cov && pos < kFallbackCap)
-                s_key[pos] = key;
-            n += (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-        if (n > kFallbackCap) {
-            if (lane == 0)
-                atomicOr(&a.ctr->error, kErrFallback);
-            __syncthreads();
-            continue;
-        }
-        wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
-        float T = 1.0f, R = 0.0f, G = 0.0f, B = 0.0f;
-        const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
-        for (uint32_t base = 0; base < n; base += 64) {
-            const uint32_t e = base + lane;
-            uint32_t q = 0, c = 0;
-            if (e < n) {
-                q = (uint32_t)(s_key[e] & 0xffffffffu);
-                c = rec[q].rgba;
-                if (DEBUG && a.dbg_ids && obase + e < a.dbg_cap)
-                    a.dbg_ids[obase + e] = q;
+            if (total == 0)
+                total = seen;
+            wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
+            for (uint32_t base = 0; base < n; base += 64) {
+                const uint32_t e = base + lane;
+                uint32_t q = 0, c = 0;
+                if (e < n) {
+                    q = (uint32_t)(s_key[e] & 0xffffffffu);
+                    c = rec[q].rgba;
+                    if (DEBUG && a.dbg_ids && obase + done + e < a.dbg_cap)
+                        a.dbg_ids[obase + done + e] = q;
+                }
+                const uint32_t lim = min(64u, n - base);
+                for (uint32_t s = 0; s < lim; s++)
+                    blend_ftb(lane_value(c, s), T, R, G2, B);
             }
-            const uint32_t lim = min(64u, n - base);
-            for (uint32_t s = 0; s < lim; s++)
-                blend_ftb(lane_value(c, s), T, R, G, B);
+            done += n;
+            if (n)
+                lo = s_key[n - 1];
+            more = cut;
+            wave_sync();
         }
         if (lane == 0) {
-            atomicAdd(&a.ctr->fragments, (unsigned long long)n);
-            reinterpret_cast<uint32_t *>(a.out)[p] = pack_rgba8(R, G, B, 1.0f - T);
+            add_stat(a.ctr, ST_FRAGMENTS, total);
+            reinterpret_cast<uint32_t *>(a.out)[p] = pack_rgba8(R, G2, B, 1.0f - T);
             if (DEBUG) {
                 if (a.dbg_rgba)
-                    reinterpret_cast<float4 *>(a.dbg_rgba)[p] = make_float4(R, G, B, 1.0f - T);
+                    reinterpret_cast<float4 *>(a.dbg_rgba)[p] = make_float4(R, G2, B, 1.0f - T);
                 if (a.dbg_count)
-                    a.dbg_count[p] = n;
+                    a.dbg_count[p] = total;
             }
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
 // ------------------------------------------------------ unsorted baseline
+//
+// Same bins, waves, batches and coverage; each pixel blends its fragments in
+// list (= quad index) order with "over", one transposed batch at a time.
 
-template <bool DEBUG>
-__global__ __launch_bounds__(64) void k_unsorted(FrameArgs a, const QuadRec *__restrict__ rec,
-                                                 const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
-                                                 const uint32_t *__restrict__ pairs)
+struct UnsortedLds {
+    uint32_t cand[128];
+    uint32_t col[64];
+};
+
+template <int NW, bool DEBUG>
+__global__ __launch_bounds__(NW * 64) void k_unsorted(FrameArgs a, const QuadRec *__restrict__ rec,
+                                                      const QuadXY *__restrict__ xyp,
+                                                      const uint2 *__restrict__ bbox,
+                                                      const uint32_t *__restrict__ pairs)
 {
-    __shared__ uint64_t s_mask[64];
-    __shared__ uint32_t s_id[64];
-    __shared__ uint32_t s_col[64];
-    uint32_t bxk, byk;
-    if (!map_block(a, blockIdx.x, bxk, byk))
-        return;
+    __shared__ BinChunk<NW> C;
+    __shared__ UnsortedLds Uw[NW];
     if (a.ctr->error & kErrPairs)
         return;
-    const uint32_t lane = threadIdx.x;
-    const int px0 = (int)bxk * 8, py0 = (int)byk * 8;
-    const int px = px0 + (int)(lane & 7), py = py0 + (int)(lane >> 3);
-    const bool on = px < (int)a.W && py < (int)a.H;
-    const uint64_t onmask = ballot(on);
-    const uint32_t pix = on ? (uint32_t)py * a.W + (uint32_t)px : 0;
-    const int px1 = min(px0 + 7, (int)a.W - 1), py1 = min(py0 + 7, (int)a.H - 1);
-    const uint32_t bin = ((uint32_t)py0 >> a.bin_shift) * a.nbx + ((uint32_t)px0 >> a.bin_shift);
-    const uint32_t start = uniform(a.bin_start[bin]);
-    const uint32_t cnt = uniform(a.bin_count[bin]);
-    float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
-    uint32_t nfrag = 0, ntot = 0, n = 0;
-
-    auto flush = [&]() {
-        __syncthreads();
-        uint64_t m = 0;
-        if (lane < n) {
-            m = s_mask[lane];
-            s_col[lane] = rec[s_id[lane]].rgba;
-        }
-        __syncthreads();
-        uint64_t col = transpose64(m, lane);
-        if (!on)
-            col = 0;
-        while (col) {
-            const uint32_t k = (uint32_t)__builtin_ctzll(col);
-            col &= col - 1;
-            blend_over(s_col[k], R, G, B, Al);
-            nfrag++;
-        }
-        __syncthreads();
-        ntot += n;
-        n = 0;
-    };
-
-    for (uint32_t base = 0; base < cnt; base += 64) {
-        const uint32_t l = base + lane;
-        uint32_t qid = 0;
-        bool ov = false;
-        if (l < cnt) {
-            qid = pairs[start + l];
-            const uint2 bb = bbox[qid];
-            ov = (int)(bb.x & 0xffffu) <= px1 && (int)(bb.x >> 16) >= px0 && (int)(bb.y & 0xffffu) <= py1 &&
-                 (int)(bb.y >> 16) >= py0;
-        }
-        uint64_t cand = ballot(ov);
-        while (cand) {
-            const uint32_t s = (uint32_t)__builtin_ctzll(cand);
-            cand &= cand - 1;
-            const uint32_t q = lane_value(qid, s);
-            const uint64_t m = block_coverage(rec, xyp, q, px, py) & onmask;
-            if (m) {
-                if (lane == 0) {
-                    s_mask[n] = m;
-                    s_id[n] = q;
-                }
-                n++;
-                if (n == 64)
-                    flush();
+    const uint32_t bin = blockIdx.x;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t bpb = 1u << (a.bin_shift - 3), nb = bpb * bpb;
+    const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
+    const uint32_t bx_bin = (bin % a.nbx) * bpb, by_bin = (bin / a.nbx) * bpb;
+    UnsortedLds &U = Uw[wave];
+    for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
+        const uint32_t k = r0 + wave;
+        const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
+        float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
+        uint32_t nfrag = 0, ntot = 0;
+        scan_bin<NW>(bbox, pairs, C, U, start, cnt, g, [&](uint32_t m) {
+            uint64_t mk = 0;
+            if (lane < m) {
+                const uint32_t q = U.cand[lane];
+                const QuadRec &r = rec[q];
+                mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
+                U.col[lane] = r.rgba;
+            }
+            ntot += (uint32_t)__popcll(ballot(mk != 0));
+            wave_sync();
+            uint64_t bits = transpose64(mk, lane);
+            if (!g.on)
+                bits = 0;
+            while (bits) {
+                const uint32_t kk = (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1;
+                blend_over(U.col[kk], R, G, B, Al);
+                nfrag++;
+            }
+            wave_sync();
+        });
+        if (!g.active)
+            continue;
+        if (g.on) {
+            reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(R, G, B, Al);
+            if (DEBUG) {
+                if (a.dbg_rgba)
+                    reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(R, G, B, Al);
+                if (a.dbg_count)
+                    a.dbg_count[g.pix] = nfrag;
             }
         }
-    }
-    if (n)
-        flush();
-    if (on) {
-        reinterpret_cast<uint32_t *>(a.out)[pix] = pack_rgba8(R, G, B, Al);
-        if (DEBUG) {
-            if (a.dbg_rgba)
-                reinterpret_cast<float4 *>(a.dbg_rgba)[pix] = make_float4(R, G, B, Al);
-            if (a.dbg_count)
-                a.dbg_count[pix] = nfrag;
+        uint32_t wsum = nfrag;
+        for (int off = 32; off > 0; off >>= 1)
+            wsum += shfl_xor(wsum, off);
+        if (lane == 0) {
+            add_stat(a.ctr, ST_ENTRIES, ntot);
+            add_stat(a.ctr, ST_FRAGMENTS, wsum);
         }
     }
-    uint32_t wsum = nfrag;
-    for (int off = 32; off > 0; off >>= 1)
-        wsum += shfl_xor(wsum, off);
-    if (lane == 0) {
-        atomicAdd(&a.ctr->entries, (unsigned long long)ntot);
-        atomicAdd(&a.ctr->fragments, (unsigned long long)wsum);
-    }
 }
-
 // ---------------------------------------------------------- scene upload
 
 __global__ __launch_bounds__(256) void k_transpose_scene(const uint32_t *__restrict__ in, uint32_t n,
@@ -1105,40 +1235,22 @@ __global__ __launch_bounds__(256) void k_transpose_scene(const uint32_t *__restr
 
 // ---------------------------------------------------------------- launches
 
-static uint32_t raster_grid(const FrameArgs &a)
-{
-    const uint32_t bpb = 1u << (a.bin_shift - 3);
-    const uint32_t total = a.nbins * bpb * bpb;
-    return ((total + 7) / 8) * 8;
-}
-
 static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEvent_t *ev, bool bins)
 {
-    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(64), 0, s, a.ctr);
-    if (a.n) {
-        hipLaunchKernelGGL(k_setup, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
-    }
+    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(256), 0, s, a.ctr);
+    hipLaunchKernelGGL(k_setup, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
     if (ev)
         (void)hipEventRecord(ev[1], s);
     if (!bins)
         return hipGetLastError();
-    if (a.n) {
-        hipLaunchKernelGGL(k_bin_count, dim3(a.nunits), dim3(64), a.nbins * 4, s, a,
-                           (const uint2 *)a.bbox);
-    } else {
-        // no quads: every bin count is zero
-    }
+    hipLaunchKernelGGL(k_bin_count, dim3(a.nunits), dim3(64), a.nbins * 4, s, a, (const uint2 *)a.bbox);
     if (ev)
         (void)hipEventRecord(ev[2], s);
-    if (a.n) {
-        hipLaunchKernelGGL(k_bin_scan_tiles, dim3((a.nbins + 63) / 64, a.ntiles), dim3(64), 0, s, a);
-    }
+    hipLaunchKernelGGL(k_bin_scan_tiles, dim3((a.nbins + 63) / 64, a.ntiles), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_bin_scan_final, dim3(1), dim3(1024), 0, s, a);
     if (ev)
         (void)hipEventRecord(ev[3], s);
-    if (a.n) {
-        hipLaunchKernelGGL(k_bin_scatter, dim3(a.nunits), dim3(64), a.nbins * 4, s, a, (const uint2 *)a.bbox);
-    }
+    hipLaunchKernelGGL(k_bin_scatter, dim3(a.nunits), dim3(64), a.nbins * 4, s, a, (const uint2 *)a.bbox);
     if (ev)
         (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
@@ -1159,23 +1271,26 @@ bool sorter_depth_supported(int k)
     return k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 24 || k == 32;
 }
 
+// Four waves per bin workgroup (16-pixel bins: one round of 4 blocks;
+// 32-pixel: 4 rounds; 64-pixel: 16), each with a 256- or 1024-entry block
+// list; longer lists go to the dense pass.
 template <int K, bool DEBUG>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
-    const uint32_t g = raster_grid(a);
-    hipLaunchKernelGGL((k_raster<K, DEBUG>), dim3(g), dim3(64), 0, s, a, (const QuadRec *)a.rec,
-                       (const QuadXY *)a.xy, (const uint2 *)a.bbox, (const uint32_t *)a.pairs);
+    const QuadRec *rec = a.rec;
+    const QuadXY *xy = a.xy;
+    const uint2 *bb = a.bbox;
+    const uint32_t *pr = a.pairs;
+    if (a.list_cap > 256)
+        hipLaunchKernelGGL((k_raster<K, 4, 1024, DEBUG>), dim3(a.nbins), dim3(256), 0, s, a, rec, xy, bb, pr);
+    else
+        hipLaunchKernelGGL((k_raster<K, 4, 256, DEBUG>), dim3(a.nbins), dim3(256), 0, s, a, rec, xy, bb, pr);
     if (ev)
         (void)hipEventRecord(ev[5], s);
-    const uint32_t nblk = a.nblk_x * a.nblk_y;
-    hipLaunchKernelGGL((k_raster_dense<K, DEBUG>), dim3(min(nblk, 512u)), dim3(64), 0, s, a,
-                       (const QuadRec *)a.rec, (const QuadXY *)a.xy, (const uint2 *)a.bbox,
-                       (const uint32_t *)a.pairs);
+    hipLaunchKernelGGL((k_raster_dense<K, DEBUG>), dim3(kQueues * 8), dim3(64), 0, s, a, rec, xy, bb, pr);
     if (ev)
         (void)hipEventRecord(ev[6], s);
-    hipLaunchKernelGGL((k_fallback<DEBUG>), dim3(min(a.W * a.H, 2048u)), dim3(64), 0, s, a,
-                       (const QuadRec *)a.rec, (const QuadXY *)a.xy, (const uint2 *)a.bbox,
-                       (const uint32_t *)a.pairs);
+    hipLaunchKernelGGL((k_fallback<DEBUG>), dim3(kQueues * 32), dim3(64), 0, s, a, rec, xy, bb, pr);
     if (ev)
         (void)hipEventRecord(ev[7], s);
 }
@@ -1194,6 +1309,16 @@ static void launch_sorted_k(const FrameArgs &a, int k, hipStream_t s, hipEvent_t
     }
 }
 
+template <bool DEBUG>
+static void launch_unsorted(const FrameArgs &a, hipStream_t s)
+{
+    const QuadRec *rec = a.rec;
+    const QuadXY *xy = a.xy;
+    const uint2 *bb = a.bbox;
+    const uint32_t *pr = a.pairs;
+    hipLaunchKernelGGL((k_unsorted<4, DEBUG>), dim3(a.nbins), dim3(256), 0, s, a, rec, xy, bb, pr);
+}
+
 hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s, hipEvent_t *ev)
 {
     if (ev)
@@ -1203,13 +1328,10 @@ hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipS
         return e;
     const bool dbg = a.dbg_rgba || a.dbg_count || a.dbg_flag || a.dbg_ids;
     if (unsorted) {
-        const uint32_t g = raster_grid(a);
         if (dbg)
-            hipLaunchKernelGGL((k_unsorted<true>), dim3(g), dim3(64), 0, s, a, (const QuadRec *)a.rec,
-                               (const QuadXY *)a.xy, (const uint2 *)a.bbox, (const uint32_t *)a.pairs);
+            launch_unsorted<true>(a, s);
         else
-            hipLaunchKernelGGL((k_unsorted<false>), dim3(g), dim3(64), 0, s, a, (const QuadRec *)a.rec,
-                               (const QuadXY *)a.xy, (const uint2 *)a.bbox, (const uint32_t *)a.pairs);
+            launch_unsorted<false>(a, s);
         if (ev) {
             (void)hipEventRecord(ev[5], s);
             (void)hipEventRecord(ev[6], s);

@@ -103,7 +103,9 @@ struct lr_context_s {
     uint32_t pair_hint = 0;        // capacity learnt from an overflow
     hipStream_t last_stream = nullptr;
     hipEvent_t ws_free = nullptr;  // recorded after each frame that used ws
-    hipEvent_t ev[8] = {};
+    // stage timing: one set of 8 events per frame in a ring
+    std::vector<hipEvent_t> ring;  // kRing * 8
+    uint32_t ring_head = 0, ring_count = 0;
     bool timing = false;
     bool have_frame = false;
     uint64_t last_quads = 0;
@@ -145,7 +147,7 @@ uint32_t log2u(uint32_t x)
 // Byte layout of a frame workspace.
 struct Plan {
     uint32_t n, W, H, bin, shift, nbx, nby, nbins, unit_quads, nunits, ntiles, pair_cap, nblk_x, nblk_y,
-        match_bits;
+        match_bits, qcap_blocks;
     uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_tiles, o_start, o_count, o_pairs, o_fb, o_dense, o_ctr,
         total;
 };
@@ -187,12 +189,16 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t pair_h
     p.o_start = take(((uint64_t)p.nbins + 1) * 4);
     p.o_count = take((uint64_t)p.nbins * 4);
     p.o_pairs = take((uint64_t)p.pair_cap * 4);
-    p.o_fb = take((uint64_t)W * H * 4);
-    p.o_dense = take((uint64_t)p.nblk_x * p.nblk_y * 4);
+    p.qcap_blocks = (p.nblk_x * p.nblk_y + lr::kQueues - 1) / lr::kQueues;
+    p.o_fb = take((uint64_t)lr::kQueues * p.qcap_blocks * 64 * 4);
+    p.o_dense = take((uint64_t)lr::kQueues * p.qcap_blocks * 4);
     p.o_ctr = take(sizeof(lr::FrameCounters));
     p.total = o;
     return p;
 }
+
+// Frames whose stage times are kept when timing is on.
+constexpr uint32_t kRing = 1024;
 
 // The binning kernels keep one 32-bit counter per bin in LDS (64 KiB).
 constexpr uint32_t kMaxBins = 16384;
@@ -291,6 +297,7 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
     a.match_bits = plan.match_bits;
     a.nblk_x = plan.nblk_x;
     a.nblk_y = plan.nblk_y;
+    a.qcap_blocks = plan.qcap_blocks;
     a.fb_queue = reinterpret_cast<uint32_t *>(base + plan.o_fb);
     a.dense_queue = reinterpret_cast<uint32_t *>(base + plan.o_dense);
     a.ctr = reinterpret_cast<lr::FrameCounters *>(base + plan.o_ctr);
@@ -315,8 +322,10 @@ lr_status order_after_previous(lr_context ctx, hipStream_t s)
 
 lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t W, uint32_t H,
                       uint8_t *out, void *stream, int unsorted, const DebugOut *dbg, uint32_t bin,
-                      uint32_t k)
+                      uint32_t k, uint32_t list_cap)
 {
+    if (list_cap != 256 && list_cap != 1024)
+        return fail(ctx, LR_ERR_INVALID_ARG, "list_cap must be 256 or 1024");
     if (!out)
         return fail(ctx, LR_ERR_INVALID_ARG, "output pointer is NULL");
     if (!lr::sorter_depth_supported((int)k))
@@ -326,6 +335,7 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     lr_status st = build_args(ctx, scene, cam, W, H, out, bin, a, plan);
     if (st != LR_OK)
         return st;
+    a.list_cap = list_cap;
     if (dbg) {
         a.dbg_rgba = dbg->rgba;
         a.dbg_count = dbg->count;
@@ -338,7 +348,13 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     st = order_after_previous(ctx, s);
     if (st != LR_OK)
         return st;
-    hipError_t e = lr::launch_frame(a, (int)k, unsorted, s, ctx->timing ? ctx->ev : nullptr);
+    hipEvent_t *ev = nullptr;
+    if (ctx->timing) {
+        ev = &ctx->ring[(size_t)ctx->ring_head * 8];
+        ctx->ring_head = (ctx->ring_head + 1) % kRing;
+        ctx->ring_count = std::min(ctx->ring_count + 1, kRing);
+    }
+    hipError_t e = lr::launch_frame(a, (int)k, unsorted, s, ev);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "kernel launch");
     LR_HIP(ctx, hipEventRecord(ctx->ws_free, s));
@@ -346,6 +362,15 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     ctx->have_frame = true;
     ctx->last_quads = a.n;
     return LR_OK;
+}
+
+void stage_times(lr_context ctx, uint32_t slot, float *us)
+{
+    hipEvent_t *ev = &ctx->ring[(size_t)slot * 8];
+    float ms = 0.0f;
+    for (int i = 0; i < 7; i++)
+        us[i] = hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess ? ms * 1000.0f : 0.0f;
+    us[7] = hipEventElapsedTime(&ms, ev[0], ev[7]) == hipSuccess ? ms * 1000.0f : 0.0f;
 }
 
 lr_status sync_impl(lr_context ctx, bool clear)
@@ -406,6 +431,10 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         c.block_h = 8;
     if (c.sorter_depth == 0)
         c.sorter_depth = 8;
+    if (c.list_cap == 0)
+        c.list_cap = 256;
+    if (c.list_cap != 256 && c.list_cap != 1024)
+        return fail(nullptr, LR_ERR_INVALID_ARG, "list_cap must be 256 or 1024");
     if (!valid_bin(c.bin_size))
         return fail(nullptr, LR_ERR_INVALID_ARG, "bin_size must be 16, 32 or 64");
     if (c.block_h != 8)
@@ -448,8 +477,12 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
     ctx->alloc.init(ctx->arena_bytes);
     ctx->timing = (c.flags & LR_FLAG_TIMING) != 0;
     bool ok = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming) == hipSuccess;
-    for (int i = 0; i < 8 && ok; i++)
-        ok = hipEventCreate(&ctx->ev[i]) == hipSuccess;
+    if (ctx->timing) {
+        ctx->ring.assign((size_t)kRing * 8, nullptr);
+        for (auto &ev : ctx->ring)
+            if (ok)
+                ok = hipEventCreate(&ev) == hipSuccess;
+    }
     ok = ok && hipHostMalloc((void **)&ctx->host_ctr, sizeof(lr::FrameCounters), hipHostMallocDefault) ==
                    hipSuccess;
     if (!ok) {
@@ -468,7 +501,7 @@ lr_status lr_destroy(lr_context ctx)
     (void)hipDeviceSynchronize();
     if (ctx->ws_free)
         (void)hipEventDestroy(ctx->ws_free);
-    for (auto &e : ctx->ev)
+    for (auto &e : ctx->ring)
         if (e)
             (void)hipEventDestroy(e);
     if (ctx->host_ctr)
@@ -545,7 +578,7 @@ lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32
     if (!lock.owns_lock())
         return fail(ctx, LR_ERR_BUSY, "context in use by another thread");
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, ctx->cfg.bin_size,
-                       ctx->cfg.sorter_depth);
+                       ctx->cfg.sorter_depth, ctx->cfg.list_cap);
 }
 
 lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -569,9 +602,9 @@ lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, 
     d.cap = order_cap;
     if (!rgba_f32 && !counts && !flagged && !order_ids)
         return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, ctx->cfg.bin_size,
-                           ctx->cfg.sorter_depth);
+                           ctx->cfg.sorter_depth, ctx->cfg.list_cap);
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, &d, ctx->cfg.bin_size,
-                       ctx->cfg.sorter_depth);
+                       ctx->cfg.sorter_depth, ctx->cfg.list_cap);
 }
 
 lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -585,7 +618,7 @@ lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *ca
     DebugOut d;
     d.rgba = rgba_f32;
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 1, rgba_f32 ? &d : nullptr,
-                       ctx->cfg.bin_size, ctx->cfg.sorter_depth);
+                       ctx->cfg.bin_size, ctx->cfg.sorter_depth, ctx->cfg.list_cap);
 }
 
 lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, void *stream)
@@ -599,8 +632,9 @@ lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, vo
         const lr_request &r = reqs[i];
         uint32_t bin = r.bin_size ? r.bin_size : ctx->cfg.bin_size;
         uint32_t k = r.sorter_depth ? r.sorter_depth : ctx->cfg.sorter_depth;
+        uint32_t lc = r.list_cap ? r.list_cap : ctx->cfg.list_cap;
         lr_status st = render_impl(ctx, r.scene, &r.camera, r.width, r.height, r.out_rgba8, stream, 0, nullptr,
-                                   bin, k);
+                                   bin, k, lc);
         if (st != LR_OK)
             return st;
     }
@@ -625,26 +659,45 @@ lr_status lr_get_stats(lr_context ctx, lr_stats *out)
     if (!ctx->have_frame)
         return st;
     const lr::FrameCounters &c = *ctx->host_ctr;
+    unsigned long long sum[lr::ST_COUNT] = {};
+    for (uint32_t k = 0; k < lr::kStripes; k++)
+        for (uint32_t i = 0; i < lr::ST_COUNT; i++)
+            sum[i] += c.stripe[k].v[i];
     out->quads = ctx->last_quads;
-    out->visible = c.visible;
+    out->visible = sum[lr::ST_CULL0 + lr::VISIBLE];
     for (int r = 1; r < 6; r++)
-        out->culled[r] = c.cull[r];
+        out->culled[r] = sum[lr::ST_CULL0 + r];
     out->bin_pairs = c.pairs_total;
-    out->block_entries = c.entries;
-    out->fragments = c.fragments;
-    out->flagged_pixels = c.flagged;
-    out->dense_blocks = c.dense;
+    out->block_entries = sum[lr::ST_ENTRIES];
+    out->fragments = sum[lr::ST_FRAGMENTS];
+    for (uint32_t k = 0; k < lr::kQueues; k++) {
+        out->flagged_pixels += c.stripe[k].flag_n;
+        out->dense_blocks += c.stripe[k].dense_n;
+    }
     out->error_word = c.error;
-    if (ctx->timing) {
-        float ms = 0.0f;
-        for (int i = 0; i < 7; i++) {
-            if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess)
-                out->stage_us[i] = ms * 1000.0f;
-        }
-        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[7]) == hipSuccess)
-            out->stage_us[7] = ms * 1000.0f;
+    if (ctx->timing && ctx->ring_count) {
+        const uint32_t last = (ctx->ring_head + kRing - 1) % kRing;
+        stage_times(ctx, last, out->stage_us);
     }
     return st;
+}
+
+lr_status lr_get_stage_times(lr_context ctx, uint32_t max_frames, float *us, uint32_t *n_out)
+{
+    if (!ctx || !n_out || (max_frames && !us))
+        return fail(ctx, LR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    *n_out = 0;
+    if (!ctx->timing)
+        return fail(ctx, LR_ERR_INVALID_ARG, "the context was created without LR_FLAG_TIMING");
+    LR_HIP(ctx, hipDeviceSynchronize());
+    const uint32_t n = std::min(max_frames, ctx->ring_count);
+    for (uint32_t f = 0; f < n; f++) {
+        const uint32_t slot = (ctx->ring_head + kRing - n + f) % kRing;
+        stage_times(ctx, slot, us + 8 * (size_t)f);
+    }
+    *n_out = n;
+    return LR_OK;
 }
 
 lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,

@@ -45,7 +45,8 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
                 ("arena_bytes", ctypes.c_uint64), ("bin_size", ctypes.c_uint32),
                 ("block_h", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("list_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -60,12 +61,14 @@ class Stats(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_uint64), ("camera", Camera), ("width", ctypes.c_uint32),
                 ("height", ctypes.c_uint32), ("out_rgba8", ctypes.c_void_p),
-                ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32)]
+                ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
+                ("list_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 EXPORTS = ["lr_status_string", "lr_last_error", "lr_create", "lr_destroy", "lr_upload_scene",
            "lr_release_scene", "lr_render", "lr_render_debug", "lr_render_unsorted",
-           "lr_render_batch", "lr_sync", "lr_get_stats", "lr_debug_setup", "lr_debug_bins"]
+           "lr_render_batch", "lr_sync", "lr_get_stats", "lr_get_stage_times", "lr_debug_setup",
+           "lr_debug_bins"]
 
 _lib = None
 
@@ -95,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "lr_render_batch": [CTX, ctypes.POINTER(Request), U32, P],
         "lr_sync": [CTX],
         "lr_get_stats": [CTX, ctypes.POINTER(Stats)],
+        "lr_get_stage_times": [CTX, U32, P, ctypes.POINTER(U32)],
         "lr_debug_setup": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P, P, P, P],
         "lr_debug_bins": [CTX, U64, ctypes.POINTER(Camera), U32, U32, U32, P, P, U64,
                           ctypes.POINTER(U64)],
@@ -131,7 +135,7 @@ class Context:
     """A rendering context on one GPU with a torch-owned device arena."""
 
     def __init__(self, arena_bytes: int = 1 << 30, device: int = 0, bin_size: int = 32,
-                 sorter_depth: int = 8, timing: bool = False, stream=None):
+                 sorter_depth: int = 8, timing: bool = False, stream=None, list_cap: int = 256):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -143,8 +147,8 @@ class Context:
         cfg = Config(device=device, stream=None if stream is None else int(stream.cuda_stream),
                      arena=self.arena.data_ptr(), arena_bytes=int(arena_bytes), bin_size=bin_size,
                      block_h=8, sorter_depth=sorter_depth, flags=LR_FLAG_TIMING if timing else 0,
-                     hbm_budget_bytes=0)
-        self.bin_size, self.sorter_depth = bin_size, sorter_depth
+                     hbm_budget_bytes=0, list_cap=list_cap)
+        self.bin_size, self.sorter_depth, self.list_cap = bin_size, sorter_depth, list_cap
         h = ctypes.c_void_p()
         self._check(self.lib.lr_create(ctypes.byref(cfg), ctypes.byref(h)), None)
         self.h = h
@@ -268,9 +272,11 @@ class Context:
         return res
 
     def render_batch(self, reqs, stream=None, check: bool = True):
-        """reqs: list of (scene, cam, W, H, out, bin_size, sorter_depth)."""
+        """reqs: list of (scene, cam, W, H, out, bin_size, sorter_depth[, list_cap])."""
         arr = (Request * len(reqs))()
-        for k, (scene, cam, W, H, out, bs, kd) in enumerate(reqs):
+        for k, req in enumerate(reqs):
+            scene, cam, W, H, out, bs, kd = req[:7]
+            arr[k].list_cap = req[7] if len(req) > 7 and req[7] else 0
             arr[k].scene = scene
             arr[k].camera = camera_struct(cam)
             arr[k].width, arr[k].height = W, H
@@ -291,6 +297,14 @@ class Context:
                 "bin_pairs": s.bin_pairs, "block_entries": s.block_entries, "fragments": s.fragments,
                 "flagged_pixels": s.flagged_pixels, "dense_blocks": s.dense_blocks,
                 "error_word": s.error_word, "stage_us": dict(zip(STAGES, list(s.stage_us)))}
+
+    def stage_times(self, max_frames: int = 1024) -> np.ndarray:
+        """Per-frame stage times in microseconds, [frames, 8] (see STAGES)."""
+        buf = np.zeros((max_frames, 8), np.float32)
+        n = ctypes.c_uint32()
+        self._check(self.lib.lr_get_stage_times(self.h, max_frames, buf.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.byref(n)), self.h)
+        return buf[:n.value]
 
     # -- parity dumps
     def debug_setup(self, scene: int, cam, W: int, H: int, n: int) -> Dict[str, np.ndarray]:
