@@ -35,8 +35,7 @@ WORKLOADS = {
 }
 
 KERNELS = {"setup": "k_setup", "bin_count": "k_bin_count", "bin_scan": "k_bin_scan_tiles+k_bin_scan_final",
-           "bin_scatter": "k_bin_scatter", "raster": "k_raster", "raster_dense": "k_raster_dense",
-           "fallback": "k_fallback"}
+           "bin_scatter": "k_bin_scatter", "raster": "k_raster", "fallback": "k_fallback"}
 
 
 def log(msg):
@@ -145,7 +144,7 @@ def main():
     ctx.render(h, sc.camera, W, H, out=out)
     st = ctx.stats()
     log(f"frame: {st['fragments']} fragments, {st['bin_pairs']} bin pairs, {st['block_entries']} block "
-        f"entries, {st['flagged_pixels']} flagged pixels, {st['dense_blocks']} dense blocks")
+        f"entries, {st['flagged_pixels']} flagged pixels, {st['dense_blocks']} blocks in depth slices")
 
     log(f"timing sorted render: {args.warmup} warmup + {args.steps} steps")
     total_ms, per = time_steps(torch, lambda: ctx.render(h, sc.camera, W, H, out=out, check=False),
@@ -165,7 +164,7 @@ def main():
 
     # dominant kernel of the sorted frame
     names = lucidraster.STAGES[:7]
-    avg_us = {nm: float(stage[:, i].mean()) for i, nm in enumerate(names)}
+    avg_us = {nm: float(stage[:, i].mean()) for i, nm in enumerate(names) if nm != "unused"}
     dom = max(avg_us, key=avg_us.get)
     if algorithmic_bytes(dom, sc.n, st["visible"], st["bin_pairs"], W, H) is None:
         dom = "raster"
@@ -205,7 +204,7 @@ def main():
         "paper_sw_over_hw": 3.30,
         "stage_us": {k: round(v, 3) for k, v in avg_us.items()},
         "flagged_pixels": int(st["flagged_pixels"]),
-        "dense_blocks": int(st["dense_blocks"]),
+        "sliced_blocks": int(st["dense_blocks"]),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

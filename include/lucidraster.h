@@ -86,9 +86,6 @@ typedef struct {
     uint32_t sorter_depth;    /* per-pixel sorter capacity K, 2..32 (default 8) */
     uint32_t flags;           /* LR_FLAG_* */
     uint64_t hbm_budget_bytes;/* serving admission budget (0: arena size) */
-    uint32_t list_cap;        /* entries of a block's on-chip list: 256 (default) or
-                                 1024; blocks with more go to the dense pass */
-    uint32_t reserved;
 } lr_config;
 
 #define LR_FLAG_TIMING 1u     /* record per-stage times (hipEvents) */
@@ -103,11 +100,12 @@ typedef struct {
     uint64_t block_entries;   /* non-empty (block, quad) pairs */
     uint64_t fragments;       /* covered (pixel, quad) pairs */
     uint64_t flagged_pixels;  /* pixels recomputed by the exact per-pixel sort */
-    uint64_t dense_blocks;    /* blocks whose lists exceeded the on-chip list */
+    uint64_t dense_blocks;    /* blocks with more entries than one on-chip sort
+                                 (1024), processed in depth slices */
     uint32_t error_word;      /* device error bits (0: none) */
     uint32_t reserved;
     float stage_us[8];        /* setup, bin count, bin scan, bin scatter,
-                                 raster, dense raster, fallback, total */
+                                 raster, (unused), exact per-pixel pass, total */
 } lr_stats;
 
 /* A request for lr_render_batch. */
@@ -118,8 +116,6 @@ typedef struct {
     uint8_t *out_rgba8;       /* device, width*height*4 bytes */
     uint32_t bin_size;        /* 0: context default */
     uint32_t sorter_depth;    /* 0: context default */
-    uint32_t list_cap;        /* 0: context default */
-    uint32_t reserved;
 } lr_request;
 
 /* Human-readable name of a status code (static storage). */

@@ -41,6 +41,13 @@ constexpr uint32_t kT0Valid = 2u;    // triangle (P0, P1, P2) has non-zero area
 constexpr uint32_t kT0Swap = 4u;     // ... and is stored as (P0, P2, P1)
 constexpr uint32_t kT1Valid = 8u;    // triangle (P0, P2, P3)
 constexpr uint32_t kT1Swap = 16u;
+// Strictly convex quad with consistent winding: hp[0..11] hold its four
+// outer edges (P0P1, P1P2, P2P3, P3P0, oriented to positive area) and a
+// sample is covered iff it is inside all four.  This equals the union of
+// the two triangles under the top-left rule: both triangles then have the
+// quad's orientation, and a sample moved by the rule's infinitesimal shift
+// (eps, eps^2) never lies on the shared diagonal.
+constexpr uint32_t kConvex = 32u;
 
 // Snapped vertices (sub-pixel units) of a quad.
 struct alignas(32) QuadXY {
@@ -54,14 +61,14 @@ struct alignas(32) QuadXY {
 constexpr uint32_t kStripes = 256;
 enum Stat { ST_CULL0 = 0, ST_ENTRIES = 6, ST_FRAGMENTS = 7, ST_COUNT = 8 };  // ST_CULL0 + reason
 
-// The queues of dense blocks and of flagged pixels are split the same way
-// into kQueues stripes (by block index), each with its counter in the
-// stripe's line; a stripe holds at most qcap_blocks blocks / 64 x that pixels.
+// The queue of flagged pixels is split the same way into kQueues stripes (by
+// block index), each with its counter in the stripe's line; a stripe holds at
+// most 64 x qcap_blocks pixels.  dense_n counts blocks done in depth slices.
 constexpr uint32_t kQueues = 64;
 
 struct alignas(128) StatStripe {
     unsigned long long v[ST_COUNT];
-    uint32_t dense_n;   // blocks in dense-queue stripe
+    uint32_t dense_n;   // blocks processed in depth slices
     uint32_t flag_n;    // pixels in flagged-queue stripe
     uint32_t pad[14];
 };
@@ -77,7 +84,10 @@ struct FrameCounters {
 
 constexpr uint32_t kErrPairs = 1u;      // bin lists overflowed their capacity
 constexpr uint32_t kErrFallback = 2u;   // a pixel had more fragments than the exact sort holds
-constexpr uint32_t kErrDense = 4u;      // a dense block overflowed the dense list (pixels sent to the exact sort)
+constexpr uint32_t kErrDense = 4u;      // a block could not be sliced to fit its list (pixels sent to the exact sort)
+
+// Waves per raster workgroup (one bin, one 8x8 block per wave at a time).
+constexpr uint32_t kRasterWaves = 4;
 
 // Everything one frame's kernels need (passed by value).
 struct FrameArgs {
@@ -111,10 +121,13 @@ struct FrameArgs {
     uint32_t match_bits;    // bits needed to hold a bin index
     // raster
     uint32_t nblk_x, nblk_y;  // 8x8 blocks
-    uint32_t list_cap;        // per-wave block list entries (256 or 1024)
     uint32_t qcap_blocks;     // blocks per queue stripe: ceil(nblk_x*nblk_y / kQueues)
     uint32_t *fb_queue;       // flagged pixels [kQueues][qcap_blocks * 64]
-    uint32_t *dense_queue;    // dense blocks [kQueues][qcap_blocks]
+    // block entries of the raster stage, per (bin, wave) region of the bin's
+    // length at entry (kRasterWaves * bin_start[bin] + wave * bin_count[bin])
+    uint32_t *ent_code;       // block depth code
+    unsigned long long *ent_mask;  // 64-sample coverage mask
+    uint32_t *ent_id;         // quad index
     FrameCounters *ctr;
     uint8_t *out;             // RGBA8
     // debug outputs (may be null)

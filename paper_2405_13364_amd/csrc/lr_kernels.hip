@@ -189,6 +189,42 @@ __device__ void tri_halfplanes(const int32_t *X, const int32_t *Y, int ia, int i
     }
 }
 
+// A strictly convex quad (all four corner turns of one sign) gets its four
+// outer edges, oriented to positive area, in hp[0..11] and kConvex.
+__device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, int64_t Rx, int64_t Ry, int32_t *hp,
+                                  uint32_t &flags)
+{
+    int sgn[4];
+    for (int k = 0; k < 4; k++) {
+        const int p = k, q = (k + 1) & 3, r = (k + 2) & 3;
+        const int64_t t = edge_fn(X[p], Y[p], X[q], Y[q], X[r], Y[r]);
+        sgn[k] = (t > 0) - (t < 0);
+    }
+    const bool pos = sgn[0] > 0 && sgn[1] > 0 && sgn[2] > 0 && sgn[3] > 0;
+    const bool neg = sgn[0] < 0 && sgn[1] < 0 && sgn[2] < 0 && sgn[3] < 0;
+    if (!pos && !neg)
+        return;
+    int32_t h[12];
+    for (int e = 0; e < 4; e++) {
+        // positive orientation: P0 P1 P2 P3, or reversed P0 P3 P2 P1
+        const int s0 = pos ? e : (4 - e) & 3;
+        const int s1 = pos ? (e + 1) & 3 : (3 - e) & 3;
+        const int64_t sx = X[s0], sy = Y[s0], dx = (int64_t)X[s1] - sx, dy = (int64_t)Y[s1] - sy;
+        const bool top_left = (dy < 0) || (dy == 0 && dx > 0);
+        const int64_t er = dx * (Ry - sy) - dy * (Rx - sx);
+        const int64_t num = (top_left ? 0 : 1) - er;
+        int64_t t = -((-num) >> 8);  // ceil(num / 256)
+        if (t > INT32_MAX) t = INT32_MAX;
+        if (t < INT32_MIN) t = INT32_MIN;
+        h[3 * e] = (int32_t)(-dy);
+        h[3 * e + 1] = (int32_t)dx;
+        h[3 * e + 2] = (int32_t)t;
+    }
+    for (int k = 0; k < 12; k++)
+        hp[k] = h[k];
+    flags |= kConvex;
+}
+
 __global__ __launch_bounds__(256) void k_setup(FrameArgs a)
 {
     const uint32_t q = blockIdx.x * 256 + threadIdx.x;
@@ -286,6 +322,8 @@ __global__ __launch_bounds__(256) void k_setup(FrameArgs a)
                             tri_halfplanes(xy.X, xy.Y, 0, 1, 2, Rx, Ry, r.hp, flags, kT0Valid, kT0Swap);
                             tri_halfplanes(xy.X, xy.Y, 0, 2, 3, Rx, Ry, r.hp + 9, flags, kT1Valid,
                                            kT1Swap);
+                            if (!(flags & kWide))
+                                convex_halfplanes(xy.X, xy.Y, Rx, Ry, r.hp, flags);
                             r.bb_i = (uint32_t)imin | ((uint32_t)imax << 16);
                             r.bb_j = (uint32_t)jmin | ((uint32_t)jmax << 16);
                             r.rgba = a.rgba_in[q];
@@ -561,76 +599,127 @@ __device__ bool wide_covers(uint32_t flags, const QuadXY &xy, int px, int py)
     return in;
 }
 
-// Coverage of one quad over the 64 samples of an 8x8 block, computed by one
-// lane (bit 8*y + x for pixel (px0 + x, py0 + y)), exact under the top-left
-// rule.  Narrow quads step their six integer edge values across the block:
-// sample inside half-plane h iff E_h = a*di + b*dj - t >= 0, and
-// |a*di + b*dj| < 2^30, |t| < 2^30 for narrow quads, so E never overflows.
-__device__ uint64_t lane_block_mask(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q, int px0, int py0)
+// The same for a wide quad (rare): per sample, out of line.
+__device__ __noinline__ uint64_t wide_block_mask(uint32_t flags, QuadXY xy, int px0, int py0)
 {
-    const uint32_t flags = r.flags;
-    if (!(flags & kWide)) {
-        int hp[18];
-#pragma unroll
-        for (int k = 0; k < 18; k++)
-            hp[k] = r.hp[k];
-        const int di = px0 - (int)(r.bb_i & 0xffffu);
-        const int dj = py0 - (int)(r.bb_j & 0xffffu);
-        int row[6];
-#pragma unroll
-        for (int h = 0; h < 6; h++)
-            row[h] = hp[3 * h] * di + hp[3 * h + 1] * dj - hp[3 * h + 2];
-        uint32_t lo = 0, hi = 0;
-#pragma unroll
-        for (int y = 0; y < 8; y++) {
-            int e[6];
-#pragma unroll
-            for (int h = 0; h < 6; h++)
-                e[h] = row[h];
-#pragma unroll
-            for (int x = 0; x < 8; x++) {
-                // covered iff one triangle has all three edge values >= 0
-                const int both = (e[0] | e[1] | e[2]) & (e[3] | e[4] | e[5]);
-                const uint32_t bit = ~(uint32_t)both >> 31;
-                if (y < 4)
-                    lo |= bit << (8 * y + x);
-                else
-                    hi |= bit << (8 * (y - 4) + x);
-#pragma unroll
-                for (int h = 0; h < 6; h++)
-                    e[h] += hp[3 * h];
-            }
-#pragma unroll
-            for (int h = 0; h < 6; h++)
-                row[h] += hp[3 * h + 1];
-        }
-        return (uint64_t)lo | ((uint64_t)hi << 32);
-    }
-    const QuadXY xy = xyp[q];
     uint64_t m = 0;
+#pragma unroll 1
     for (int k = 0; k < 64; k++)
         if (wide_covers(flags, xy, px0 + (k & 7), py0 + (k >> 3)))
             m |= 1ull << k;
     return m;
 }
 
+// Sign bits of edge values shifted into an accumulator: (acc << 1) | (v >> 31).
+__device__ __forceinline__ uint32_t shift_in_sign(uint32_t acc, int v)
+{
+    return __builtin_amdgcn_alignbit(acc, (uint32_t)v, 31);
+}
+
+// Coverage of one quad over the 64 samples of an 8x8 block, computed by one
+// lane (bit 8*y + x for pixel (px0 + x, py0 + y)), exact under the top-left
+// rule.  Narrow quads step their integer edge values E = a*di + b*dj - t
+// across the block (sample inside an edge iff E >= 0; |a*di + b*dj| < 2^30
+// and |t| < 2^30 for narrow quads, so E never overflows): four edges for a
+// convex quad, the two triangles' six otherwise.  Each row is walked from
+// x = 7 down so the sign bits land in order.
+__device__ uint64_t lane_block_mask(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q, int px0, int py0)
+{
+    const uint32_t flags = r.flags;
+    if (flags & kWide)
+        return wide_block_mask(flags, xyp[q], px0, py0);
+    const int di = px0 - (int)(r.bb_i & 0xffffu);
+    const int dj = py0 - (int)(r.bb_j & 0xffffu);
+    uint32_t lo = 0, hi = 0;
+    if (flags & kConvex) {
+        int a[4], b[4], row[4];
+#pragma unroll
+        for (int h = 0; h < 4; h++) {
+            a[h] = r.hp[3 * h];
+            b[h] = r.hp[3 * h + 1];
+            row[h] = a[h] * (di + 7) + b[h] * dj - r.hp[3 * h + 2];  // value at x = 7
+        }
+#pragma unroll 1
+        for (int y = 0; y < 8; y++) {
+            int e0 = row[0], e1 = row[1], e2 = row[2], e3 = row[3];
+            uint32_t bits = 0;
+#pragma unroll
+            for (int x = 0; x < 8; x++) {
+                bits = shift_in_sign(bits, e0 | e1 | e2 | e3);  // 1: outside some edge
+                e0 -= a[0];
+                e1 -= a[1];
+                e2 -= a[2];
+                e3 -= a[3];
+                asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3));
+            }
+            bits = ~bits & 0xffu;
+            if (y < 4)
+                lo |= bits << (8 * y);
+            else
+                hi |= bits << (8 * (y - 4));
+#pragma unroll
+            for (int h = 0; h < 4; h++)
+                row[h] += b[h];
+        }
+    } else {
+        int a[6], b[6], row[6];
+#pragma unroll
+        for (int h = 0; h < 6; h++) {
+            a[h] = r.hp[3 * h];
+            b[h] = r.hp[3 * h + 1];
+            row[h] = a[h] * (di + 7) + b[h] * dj - r.hp[3 * h + 2];
+        }
+#pragma unroll 1
+        for (int y = 0; y < 8; y++) {
+            int e0 = row[0], e1 = row[1], e2 = row[2], e3 = row[3], e4 = row[4], e5 = row[5];
+            uint32_t bits = 0;
+#pragma unroll
+            for (int x = 0; x < 8; x++) {
+                // outside iff both triangles have a negative edge value
+                bits = shift_in_sign(bits, (e0 | e1 | e2) & (e3 | e4 | e5));
+                e0 -= a[0];
+                e1 -= a[1];
+                e2 -= a[2];
+                e3 -= a[3];
+                e4 -= a[4];
+                e5 -= a[5];
+                asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3), "+v"(e4), "+v"(e5));
+            }
+            bits = ~bits & 0xffu;
+            if (y < 4)
+                lo |= bits << (8 * y);
+            else
+                hi |= bits << (8 * (y - 4));
+#pragma unroll
+            for (int h = 0; h < 6; h++)
+                row[h] += b[h];
+        }
+    }
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
 // Single-sample coverage (one lane, one quad), same rule.
 __device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q,
                                                int px, int py)
 {
-    if (!(r.flags & kWide)) {
-        const int di = px - (int)(r.bb_i & 0xffffu);
-        const int dj = py - (int)(r.bb_j & 0xffffu);
-        const int *hp = r.hp;
-        const bool t0 = (__mul24(hp[0], di) + __mul24(hp[1], dj) >= hp[2]) &&
-                        (__mul24(hp[3], di) + __mul24(hp[4], dj) >= hp[5]) &&
-                        (__mul24(hp[6], di) + __mul24(hp[7], dj) >= hp[8]);
-        const bool t1 = (__mul24(hp[9], di) + __mul24(hp[10], dj) >= hp[11]) &&
-                        (__mul24(hp[12], di) + __mul24(hp[13], dj) >= hp[14]) &&
-                        (__mul24(hp[15], di) + __mul24(hp[16], dj) >= hp[17]);
-        return t0 || t1;
+    if (r.flags & kWide)
+        return wide_covers(r.flags, xyp[q], px, py);
+    const int di = px - (int)(r.bb_i & 0xffffu);
+    const int dj = py - (int)(r.bb_j & 0xffffu);
+    const int *hp = r.hp;
+    if (r.flags & kConvex) {
+        bool in = true;
+        for (int h = 0; h < 4; h++)
+            in = in && (__mul24(hp[3 * h], di) + __mul24(hp[3 * h + 1], dj) >= hp[3 * h + 2]);
+        return in;
     }
-    return wide_covers(r.flags, xyp[q], px, py);
+    const bool t0 = (__mul24(hp[0], di) + __mul24(hp[1], dj) >= hp[2]) &&
+                    (__mul24(hp[3], di) + __mul24(hp[4], dj) >= hp[5]) &&
+                    (__mul24(hp[6], di) + __mul24(hp[7], dj) >= hp[8]);
+    const bool t1 = (__mul24(hp[9], di) + __mul24(hp[10], dj) >= hp[11]) &&
+                    (__mul24(hp[12], di) + __mul24(hp[13], dj) >= hp[14]) &&
+                    (__mul24(hp[15], di) + __mul24(hp[16], dj) >= hp[17]);
+    return t0 || t1;
 }
 
 // Block key: the quad's depth at the centroid of its covered samples in the
@@ -686,13 +775,14 @@ struct Stage {
     uint32_t rgba;
 };
 
-// Per-wave LDS: candidate batch, block entry list, phase-3 staging.
-template <int CAP>
+// Entries one on-chip sort takes; longer block lists are cut into slices.
+constexpr uint32_t kSortCap = 1024;
+
+// Per-wave LDS of the sorted raster: candidate batch, sort keys of the
+// current slice (also the slicing histogram), phase-3 staging.
 struct WaveLds {
     uint32_t cand[128];
-    uint64_t mask[CAP];
-    uint32_t id[CAP];
-    uint32_t key[CAP];
+    uint32_t key[kSortCap];
     Stage stage[64];
     uint32_t sid[64];
 };
@@ -702,14 +792,6 @@ struct BinChunk {
     uint32_t q[NW * 64];
     uint2 bb[NW * 64];
 };
-
-constexpr uint32_t slot_bits(uint32_t cap)
-{
-    uint32_t b = 0;
-    while ((1u << b) < cap)
-        b++;
-    return b;
-}
 
 struct BlockGeom {
     int px0, py0, px1, py1;  // block pixel rect clipped to the screen
@@ -808,24 +890,90 @@ __device__ __forceinline__ void push_flagged(const FrameArgs &a, bool flag, cons
         a.fb_queue[(size_t)s * a.qcap_blocks * 64 + base + rank_below(m)] = g.pix;
 }
 
-__device__ __forceinline__ void push_dense(const FrameArgs &a, const BlockGeom &g, uint32_t lane)
-{
-    if (lane == 0) {
-        const uint32_t s = g.blk % kQueues;
-        const uint32_t slot = atomicAdd(&a.ctr->stripe[s].dense_n, 1u);
-        a.dense_queue[(size_t)s * a.qcap_blocks + slot] = g.blk;
-    }
-}
+// Per-pixel state of phase 3: the K-deep sorter (codes ascending, filled
+// with placeholder code 0 that is emitted first and blends nothing), the
+// last emitted code, and the front-to-back blend.
+template <int K, bool DEBUG>
+struct PixelSorter {
+    uint32_t qk[K], qc[K], qi[DEBUG ? K : 1];
+    uint32_t last, nfrag, npop, obase;
+    bool flagged;
+    float T, R, G, B;
 
-// Phase-1 batch of the sorted path: masks and block keys of the candidates,
-// non-empty ones appended to the block list (n counts every entry, also
-// past CAP).
-template <int CAP>
-__device__ __forceinline__ void sorted_batch(const QuadRec *__restrict__ rec, const QuadXY *__restrict__ xyp,
-                                             WaveLds<CAP> &L, uint32_t m, const BlockGeom &g, uint32_t lane,
-                                             uint32_t &n)
+    __device__ __forceinline__ void init(uint32_t ob)
+    {
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            qk[j] = 0;
+            qc[j] = 0;
+            if (DEBUG)
+                qi[j] = 0;
+        }
+        last = nfrag = npop = 0;
+        obase = ob;
+        flagged = false;
+        T = 1.0f;
+        R = G = B = 0.0f;
+    }
+
+    __device__ __forceinline__ void emit(const FrameArgs &a, bool on, uint32_t pk, uint32_t pc, uint32_t pi)
+    {
+        flagged |= (pk - 1u) < last;  // emitted codes must strictly increase (placeholders excepted)
+        last = pk;
+        blend_ftb(pc, T, R, G, B);
+        if (DEBUG && pk != 0) {
+            if (a.dbg_ids && on && obase + npop < a.dbg_cap)
+                a.dbg_ids[obase + npop] = pi;
+            npop++;
+        }
+    }
+
+    // insert x and emit the smallest of queue + x
+    __device__ __forceinline__ void push(const FrameArgs &a, bool on, uint32_t x, uint32_t xc, uint32_t xi)
+    {
+        nfrag++;
+        flagged |= (x == 0xFFFFFFFFu);  // zero key: leave it to the exact path
+        bool lt[K];
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            lt[j] = x < qk[j];
+        const uint32_t pk = lt[0] ? x : qk[0];
+        const uint32_t pc = lt[0] ? xc : qc[0];
+        uint32_t pi = 0;
+        if (DEBUG)
+            pi = lt[0] ? xi : qi[0];
+#pragma unroll
+        for (int j = 0; j < K - 1; j++) {
+            qk[j] = lt[j + 1] ? (lt[j] ? qk[j] : x) : qk[j + 1];
+            qc[j] = lt[j + 1] ? (lt[j] ? qc[j] : xc) : qc[j + 1];
+            if (DEBUG)
+                qi[j] = lt[j + 1] ? (lt[j] ? qi[j] : xi) : qi[j + 1];
+        }
+        qk[K - 1] = lt[K - 1] ? qk[K - 1] : x;
+        qc[K - 1] = lt[K - 1] ? qc[K - 1] : xc;
+        if (DEBUG)
+            qi[K - 1] = lt[K - 1] ? qi[K - 1] : xi;
+        emit(a, on, pk, pc, pi);
+    }
+
+    __device__ __forceinline__ void flush(const FrameArgs &a, bool on)
+    {
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            emit(a, on, qk[j], qc[j], DEBUG ? qi[j] : 0);
+    }
+};
+
+// Phase 1 of the sorted path for one batch: each lane takes a candidate,
+// builds its coverage mask of the block and, if not empty, its block key;
+// non-empty entries go to the wave's global entry region at slot n + rank,
+// and the first kSortCap also to the LDS sort keys (key bits above the slot
+// index).  kmin / kmax track the key range.
+__device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *__restrict__ rec,
+                                             const QuadXY *__restrict__ xyp, WaveLds &L, uint32_t m,
+                                             const BlockGeom &g, uint32_t lane, uint32_t ebase, uint32_t sb,
+                                             uint32_t &n, uint32_t &kmin, uint32_t &kmax)
 {
-    constexpr uint32_t SB = slot_bits(CAP);
     uint64_t mk = 0;
     uint32_t q = 0, code = 0;
     if (lane < m) {
@@ -837,58 +985,40 @@ __device__ __forceinline__ void sorted_batch(const QuadRec *__restrict__ rec, co
     }
     const uint64_t b = ballot(mk != 0);
     const uint32_t slot = n + rank_below(b);
-    if (mk && slot < CAP) {
-        L.mask[slot] = mk;
-        L.id[slot] = q;
-        L.key[slot] = ((code >> (SB - 1)) << SB) | slot;
+    if (mk) {
+        a.ent_code[ebase + slot] = code;
+        a.ent_mask[ebase + slot] = mk;
+        a.ent_id[ebase + slot] = q;
+        if (slot < kSortCap)
+            L.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
     }
+    uint32_t mn = mk ? code : 0xFFFFFFFFu, mx = mk ? code : 0u;
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, shfl_xor(mn, off));
+        mx = max(mx, shfl_xor(mx, off));
+    }
+    kmin = min(kmin, mn);
+    kmax = max(kmax, mx);
     n += (uint32_t)__popcll(b);
 }
 
-// Phases 2 and 3 of a block whose n entries are in L: depth-sort the
-// entries, then one lane per pixel walks them (in 64-entry segments whose
-// coverage masks are transposed to per-pixel bit sets) through a K-deep
-// sorter, blending each fragment the sorter emits.  A pixel whose emitted
-// codes stop strictly increasing is queued for the exact path.
-template <int K, int CAP, bool DEBUG>
-__device__ void finish_sorted(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds<CAP> &L, uint32_t n,
-                              const BlockGeom &g, uint32_t lane)
+// Phases 2 and 3 for n sorted-key entries in L.key (entry = low sb bits,
+// an index into the wave's global entry region): depth-sort them, then one
+// lane per pixel walks them in 64-entry segments whose coverage masks are
+// transposed to per-pixel bit sets, feeding each pixel's sorter.
+template <int K, bool DEBUG>
+__device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds &L, uint32_t n,
+                             uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
 {
-    constexpr uint32_t SB = slot_bits(CAP);
     wave_sync();
     wave_bitonic_sort<uint32_t>(L.key, n, 0xFFFFFFFFu, lane);
-
-    uint32_t qk[K], qc[K], qi[DEBUG ? K : 1];
-#pragma unroll
-    for (int j = 0; j < K; j++) {
-        qk[j] = 0;  // "already emitted" placeholders: popped first, blend nothing
-        qc[j] = 0;
-        if (DEBUG)
-            qi[j] = 0;
-    }
-    uint32_t last = 0, nfrag = 0, npop = 0;
-    bool flagged = false;
-    float T = 1.0f, R = 0.0f, G = 0.0f, B = 0.0f;
-    const uint32_t obase = (DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0;
-
-    auto emit = [&](uint32_t pk, uint32_t pc, uint32_t pi) {
-        flagged |= (pk - 1u) < last;  // pops must strictly increase (placeholders excepted)
-        last = pk;
-        blend_ftb(pc, T, R, G, B);
-        if (DEBUG && pk != 0) {
-            if (a.dbg_ids && g.on && obase + npop < a.dbg_cap)
-                a.dbg_ids[obase + npop] = pi;
-            npop++;
-        }
-    };
-
     for (uint32_t seg = 0; seg < n; seg += 64) {
         const uint32_t e = seg + lane;
         uint64_t m = 0;
         if (e < n) {
-            const uint32_t slot = L.key[e] & ((1u << SB) - 1);
-            m = L.mask[slot];
-            const uint32_t q = L.id[slot];
+            const uint32_t slot = ebase + (L.key[e] & ((1u << sb) - 1));
+            m = a.ent_mask[slot];
+            const uint32_t q = a.ent_id[slot];
             const QuadRec &r = rec[q];
             Stage st;
             st.A = r.A;
@@ -902,7 +1032,7 @@ __device__ void finish_sorted(const FrameArgs &a, const QuadRec *__restrict__ re
         }
         wave_sync();
         uint64_t col = transpose64(m, lane);
-        if (!g.on || flagged)
+        if (!g.on || ps.flagged)
             col = 0;
         while (col) {
             const uint32_t k = (uint32_t)__builtin_ctzll(col);
@@ -910,73 +1040,122 @@ __device__ void finish_sorted(const FrameArgs &a, const QuadRec *__restrict__ re
             const Stage st = L.stage[k];
             const float kf =
                 frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
-            const uint32_t x = order_code(kf);
-            const uint32_t xc = st.rgba;
-            const uint32_t xi = DEBUG ? L.sid[k] : 0;
-            nfrag++;
-            flagged |= (x == 0xFFFFFFFFu);  // zero key: leave it to the exact path
-            // insert x and emit the smallest of queue + x
-            bool lt[K];
-#pragma unroll
-            for (int j = 0; j < K; j++)
-                lt[j] = x < qk[j];
-            const uint32_t pk = lt[0] ? x : qk[0];
-            const uint32_t pc = lt[0] ? xc : qc[0];
-            uint32_t pi = 0;
-            if (DEBUG)
-                pi = lt[0] ? xi : qi[0];
-#pragma unroll
-            for (int j = 0; j < K - 1; j++) {
-                qk[j] = lt[j + 1] ? (lt[j] ? qk[j] : x) : qk[j + 1];
-                qc[j] = lt[j + 1] ? (lt[j] ? qc[j] : xc) : qc[j + 1];
-                if (DEBUG)
-                    qi[j] = lt[j + 1] ? (lt[j] ? qi[j] : xi) : qi[j + 1];
-            }
-            qk[K - 1] = lt[K - 1] ? qk[K - 1] : x;
-            qc[K - 1] = lt[K - 1] ? qc[K - 1] : xc;
-            if (DEBUG)
-                qi[K - 1] = lt[K - 1] ? qi[K - 1] : xi;
-            emit(pk, pc, pi);
-            if (flagged)
+            ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.sid[k] : 0);
+            if (ps.flagged)
                 col = 0;
         }
         wave_sync();
     }
-    if (g.on && !flagged) {
-#pragma unroll
-        for (int j = 0; j < K; j++)
-            emit(qk[j], qc[j], DEBUG ? qi[j] : 0);
+}
+
+// A block with n > kSortCap entries: a 256-bucket histogram of its block
+// keys over [kmin, kmax] splits the key range into slices of at most
+// kSortCap entries (whole buckets, nearest first); each slice is gathered
+// from the global entry region into the LDS keys and walked.  The pixel
+// sorters carry over from slice to slice, so they see the same entry order
+// as one sort of the whole list.  Returns false when one bucket alone holds
+// more than kSortCap entries.
+template <int K, bool DEBUG>
+__device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds &L, uint32_t n,
+                            uint32_t ebase, uint32_t sb, uint32_t kmin, uint32_t kmax, const BlockGeom &g,
+                            uint32_t lane, PixelSorter<K, DEBUG> &ps)
+{
+    const uint32_t span = kmax - kmin;  // < 2^31
+    const uint32_t bits = span ? 32 - __builtin_clz(span) : 1;
+    const uint32_t hs = bits > 8 ? bits - 8 : 0;  // bucket = (code - kmin) >> hs, in [0, 256)
+    uint32_t *hist = L.key;  // reused: 256 counters, then the slice keys
+    for (uint32_t b = lane; b < 256; b += 64)
+        hist[b] = 0;
+    wave_sync();
+    for (uint32_t e = lane; e < n; e += 64)
+        atomicAdd(&hist[(a.ent_code[ebase + e] - kmin) >> hs], 1u);
+    wave_sync();
+    uint32_t counts[4];
+    for (int k = 0; k < 4; k++)
+        counts[k] = hist[lane * 4 + k];  // lane holds buckets 4*lane .. 4*lane+3
+    wave_sync();
+    // code resolution inside a slice: 32 - sb bits for the (code - lo) part
+    const uint32_t room = 32 - sb;
+    uint32_t b0 = 0;
+    while (b0 < 256) {
+        // greedy: the longest run of buckets from b0 holding at most kSortCap entries
+        uint32_t take = 0, sum = 0;
+        for (uint32_t b = b0; b < 256; b++) {
+            const uint32_t c = lane_value(counts[b & 3], b >> 2);
+            if (sum + c > kSortCap)
+                break;
+            sum += c;
+            take++;
+        }
+        if (take == 0)
+            return false;
+        const uint32_t b1 = b0 + take;
+        const uint32_t lo = kmin + (b0 << hs);
+        const uint32_t hi = (b1 >= 256) ? kmax + 1 : kmin + (b1 << hs);
+        const uint32_t w = hi - lo - 1;
+        const uint32_t wb = w ? 32 - __builtin_clz(w) : 1;
+        const uint32_t sh = wb > room ? wb - room : 0;
+        uint32_t ns = 0;
+        for (uint32_t base = 0; base < n; base += 64) {
+            const uint32_t e = base + lane;
+            uint32_t code = 0;
+            bool in = false;
+            if (e < n) {
+                code = a.ent_code[ebase + e];
+                in = code >= lo && code < hi;
+            }
+            const uint64_t bm = ballot(in);
+            if (in)
+                L.key[ns + rank_below(bm)] = (((code - lo) >> sh) << sb) | e;
+            ns += (uint32_t)__popcll(bm);
+        }
+        walk_entries<K, DEBUG>(a, rec, L, ns, ebase, sb, g, lane, ps);
+        b0 = b1;
     }
-    push_flagged(a, g.on && flagged, g, lane);
-    if (g.on && !flagged) {
-        reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(R, G, B, 1.0f - T);
+    return true;
+}
+
+// Outputs of a finished block.
+template <int K, bool DEBUG>
+__device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps,
+                             uint32_t entries)
+{
+    if (g.on && !ps.flagged)
+        ps.flush(a, g.on);
+    push_flagged(a, g.on && ps.flagged, g, lane);
+    if (g.on && !ps.flagged) {
+        reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(ps.R, ps.G, ps.B, 1.0f - ps.T);
         if (DEBUG && a.dbg_rgba)
-            reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(R, G, B, 1.0f - T);
+            reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(ps.R, ps.G, ps.B, 1.0f - ps.T);
     }
     if (DEBUG && g.on) {
         if (a.dbg_count)
-            a.dbg_count[g.pix] = nfrag;
+            a.dbg_count[g.pix] = ps.nfrag;
         if (a.dbg_flag)
-            a.dbg_flag[g.pix] = flagged ? 1 : 0;
+            a.dbg_flag[g.pix] = ps.flagged ? 1 : 0;
     }
     // statistics (flagged pixels are counted by the exact path)
-    uint32_t wsum = (g.on && !flagged) ? nfrag : 0;
+    uint32_t wsum = (g.on && !ps.flagged) ? ps.nfrag : 0;
     for (int off = 32; off > 0; off >>= 1)
         wsum += shfl_xor(wsum, off);
     if (lane == 0) {
-        add_stat(a.ctr, ST_ENTRIES, n);
+        add_stat(a.ctr, ST_ENTRIES, entries);
         if (wsum)
             add_stat(a.ctr, ST_FRAGMENTS, wsum);
     }
 }
 
-template <int K, int NW, int CAP, bool DEBUG>
-__global__ __launch_bounds__(NW * 64) void k_raster(FrameArgs a, const QuadRec *__restrict__ rec,
-                                                    const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
-                                                    const uint32_t *__restrict__ pairs)
+// Sorted raster: one workgroup of kRasterWaves waves per bin, one 8x8 block
+// per wave per round (16-pixel bins: 1 round; 32: 4; 64: 16).
+template <int K, bool DEBUG>
+__global__ __launch_bounds__(kRasterWaves * 64) void k_raster(FrameArgs a, const QuadRec *__restrict__ rec,
+                                                              const QuadXY *__restrict__ xyp,
+                                                              const uint2 *__restrict__ bbox,
+                                                              const uint32_t *__restrict__ pairs)
 {
+    constexpr uint32_t NW = kRasterWaves;
     __shared__ BinChunk<NW> C;
-    __shared__ WaveLds<CAP> Lw[NW];
+    __shared__ WaveLds Lw[NW];
     if (a.ctr->error & kErrPairs)
         return;  // bin lists are incomplete: the frame is reported as failed
     const uint32_t bin = blockIdx.x;
@@ -984,60 +1163,36 @@ __global__ __launch_bounds__(NW * 64) void k_raster(FrameArgs a, const QuadRec *
     const uint32_t bpb = 1u << (a.bin_shift - 3), nb = bpb * bpb;
     const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
     const uint32_t bx_bin = (bin % a.nbx) * bpb, by_bin = (bin / a.nbx) * bpb;
-    WaveLds<CAP> &L = Lw[wave];
+    const uint32_t ebase = NW * start + wave * cnt;  // this wave's entry region (cnt entries)
+    // entry index bits in a sort key: enough for kSortCap and for cnt
+    const uint32_t sb = max(10u, cnt > 1 ? 32 - __builtin_clz(cnt - 1) : 1u);
+    WaveLds &L = Lw[wave];
     for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
         const uint32_t k = r0 + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
-        uint32_t n = 0;
-        scan_bin<NW>(bbox, pairs, C, L, start, cnt, g,
-                          [&](uint32_t m) { sorted_batch<CAP>(rec, xyp, L, m, g, lane, n); });
-        if (g.active) {
-            if (n > CAP)
-                push_dense(a, g, lane);
-            else
-                finish_sorted<K, CAP, DEBUG>(a, rec, L, n, g, lane);
-        }
-    }
-}
-
-// Blocks whose list outgrew the workgroup's per-wave list: one wave per
-// block with a 4096-entry list; deeper blocks send their pixels to the exact
-// per-pixel path.
-constexpr uint32_t kDenseCap = 4096;
-
-template <int K, bool DEBUG>
-__global__ __launch_bounds__(64) void k_raster_dense(FrameArgs a, const QuadRec *__restrict__ rec,
-                                                     const QuadXY *__restrict__ xyp,
-                                                     const uint2 *__restrict__ bbox,
-                                                     const uint32_t *__restrict__ pairs)
-{
-    __shared__ BinChunk<1> C;
-    __shared__ WaveLds<kDenseCap> L;
-    if (a.ctr->error & kErrPairs)
-        return;
-    const uint32_t lane = threadIdx.x;
-    const uint32_t s = blockIdx.x % kQueues, G = gridDim.x / kQueues;
-    const uint32_t count = uniform(a.ctr->stripe[s].dense_n);
-    for (uint32_t t = blockIdx.x / kQueues; t < count; t += G) {
-        const uint32_t blk = uniform(a.dense_queue[(size_t)s * a.qcap_blocks + t]);
-        const uint32_t bxk = blk % a.nblk_x, byk = blk / a.nblk_x;
-        const BlockGeom g = block_geom(a, bxk, byk, true, lane);
-        const uint32_t bin = (byk * 8 >> a.bin_shift) * a.nbx + (bxk * 8 >> a.bin_shift);
-        const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
-        uint32_t n = 0;
-        scan_bin<1>(bbox, pairs, C, L, start, cnt, g,
-                               [&](uint32_t m) { sorted_batch<kDenseCap>(rec, xyp, L, m, g, lane, n); });
-        if (n > kDenseCap) {
-            // no list holds this block: every pixel takes the exact path
-            push_flagged(a, g.on, g, lane);
-            if (lane == 0)
-                atomicOr(&a.ctr->error, kErrDense);
-            if (DEBUG && g.on && a.dbg_flag)
-                a.dbg_flag[g.pix] = 1;
+        uint32_t n = 0, kmin = 0xFFFFFFFFu, kmax = 0;
+        scan_bin<NW>(bbox, pairs, C, L, start, cnt, g, [&](uint32_t m) {
+            sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, n, kmin, kmax);
+        });
+        if (!g.active)
+            continue;
+        // entries written by other lanes of this wave are read back below
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        PixelSorter<K, DEBUG> ps;
+        ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
+        if (n <= kSortCap) {
+            walk_entries<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps);
         } else {
-            finish_sorted<K, kDenseCap, DEBUG>(a, rec, L, n, g, lane);
+            if (lane == 0)
+                atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
+            if (!walk_sliced<K, DEBUG>(a, rec, L, n, ebase, sb, kmin, kmax, g, lane, ps)) {
+                // no slice fits: the exact path takes the block
+                ps.flagged = true;
+                if (lane == 0)
+                    atomicOr(&a.ctr->error, kErrDense);
+            }
         }
-        __syncthreads();
+        finish_block<K, DEBUG>(a, g, lane, ps, n);
     }
 }
 
@@ -1271,9 +1426,7 @@ bool sorter_depth_supported(int k)
     return k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 24 || k == 32;
 }
 
-// Four waves per bin workgroup (16-pixel bins: one round of 4 blocks;
-// 32-pixel: 4 rounds; 64-pixel: 16), each with a 256- or 1024-entry block
-// list; longer lists go to the dense pass.
+// One workgroup of kRasterWaves waves per bin.
 template <int K, bool DEBUG>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
@@ -1281,15 +1434,11 @@ static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
     const QuadXY *xy = a.xy;
     const uint2 *bb = a.bbox;
     const uint32_t *pr = a.pairs;
-    if (a.list_cap > 256)
-        hipLaunchKernelGGL((k_raster<K, 4, 1024, DEBUG>), dim3(a.nbins), dim3(256), 0, s, a, rec, xy, bb, pr);
-    else
-        hipLaunchKernelGGL((k_raster<K, 4, 256, DEBUG>), dim3(a.nbins), dim3(256), 0, s, a, rec, xy, bb, pr);
-    if (ev)
+    hipLaunchKernelGGL((k_raster<K, DEBUG>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s, a, rec, xy, bb, pr);
+    if (ev) {
         (void)hipEventRecord(ev[5], s);
-    hipLaunchKernelGGL((k_raster_dense<K, DEBUG>), dim3(kQueues * 8), dim3(64), 0, s, a, rec, xy, bb, pr);
-    if (ev)
         (void)hipEventRecord(ev[6], s);
+    }
     hipLaunchKernelGGL((k_fallback<DEBUG>), dim3(kQueues * 32), dim3(64), 0, s, a, rec, xy, bb, pr);
     if (ev)
         (void)hipEventRecord(ev[7], s);
@@ -1316,7 +1465,8 @@ static void launch_unsorted(const FrameArgs &a, hipStream_t s)
     const QuadXY *xy = a.xy;
     const uint2 *bb = a.bbox;
     const uint32_t *pr = a.pairs;
-    hipLaunchKernelGGL((k_unsorted<4, DEBUG>), dim3(a.nbins), dim3(256), 0, s, a, rec, xy, bb, pr);
+    hipLaunchKernelGGL((k_unsorted<kRasterWaves, DEBUG>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s, a, rec,
+                       xy, bb, pr);
 }
 
 hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s, hipEvent_t *ev)

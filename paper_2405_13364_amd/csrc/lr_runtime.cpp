@@ -148,7 +148,7 @@ uint32_t log2u(uint32_t x)
 struct Plan {
     uint32_t n, W, H, bin, shift, nbx, nby, nbins, unit_quads, nunits, ntiles, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks;
-    uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_tiles, o_start, o_count, o_pairs, o_fb, o_dense, o_ctr,
+    uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_tiles, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
         total;
 };
 
@@ -168,7 +168,8 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t pair_h
     p.unit_quads = uq;
     p.nunits = std::max<uint32_t>(1, (n + uq - 1) / uq);
     p.ntiles = (p.nunits + 63) / 64;
-    uint64_t cap = 4ull * n + 4ull * p.nbins + 65536;
+    // first guess; an overflow is reported and the next frame is planned larger
+    uint64_t cap = 5ull * n / 2 + 4ull * p.nbins + 65536;
     cap = std::max<uint64_t>(cap, pair_hint);
     p.pair_cap = (uint32_t)std::min<uint64_t>(cap, 0xF0000000ull);
     p.nblk_x = (W + 7) / 8;
@@ -191,7 +192,9 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t pair_h
     p.o_pairs = take((uint64_t)p.pair_cap * 4);
     p.qcap_blocks = (p.nblk_x * p.nblk_y + lr::kQueues - 1) / lr::kQueues;
     p.o_fb = take((uint64_t)lr::kQueues * p.qcap_blocks * 64 * 4);
-    p.o_dense = take((uint64_t)lr::kQueues * p.qcap_blocks * 4);
+    p.o_ecode = take((uint64_t)lr::kRasterWaves * p.pair_cap * 4);
+    p.o_emask = take((uint64_t)lr::kRasterWaves * p.pair_cap * 8);
+    p.o_eid = take((uint64_t)lr::kRasterWaves * p.pair_cap * 4);
     p.o_ctr = take(sizeof(lr::FrameCounters));
     p.total = o;
     return p;
@@ -299,7 +302,9 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
     a.nblk_y = plan.nblk_y;
     a.qcap_blocks = plan.qcap_blocks;
     a.fb_queue = reinterpret_cast<uint32_t *>(base + plan.o_fb);
-    a.dense_queue = reinterpret_cast<uint32_t *>(base + plan.o_dense);
+    a.ent_code = reinterpret_cast<uint32_t *>(base + plan.o_ecode);
+    a.ent_mask = reinterpret_cast<unsigned long long *>(base + plan.o_emask);
+    a.ent_id = reinterpret_cast<uint32_t *>(base + plan.o_eid);
     a.ctr = reinterpret_cast<lr::FrameCounters *>(base + plan.o_ctr);
     a.out = out;
     ctx->ws_ctr_off = ctx->ws.off + plan.o_ctr;
@@ -322,10 +327,8 @@ lr_status order_after_previous(lr_context ctx, hipStream_t s)
 
 lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t W, uint32_t H,
                       uint8_t *out, void *stream, int unsorted, const DebugOut *dbg, uint32_t bin,
-                      uint32_t k, uint32_t list_cap)
+                      uint32_t k)
 {
-    if (list_cap != 256 && list_cap != 1024)
-        return fail(ctx, LR_ERR_INVALID_ARG, "list_cap must be 256 or 1024");
     if (!out)
         return fail(ctx, LR_ERR_INVALID_ARG, "output pointer is NULL");
     if (!lr::sorter_depth_supported((int)k))
@@ -335,7 +338,6 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     lr_status st = build_args(ctx, scene, cam, W, H, out, bin, a, plan);
     if (st != LR_OK)
         return st;
-    a.list_cap = list_cap;
     if (dbg) {
         a.dbg_rgba = dbg->rgba;
         a.dbg_count = dbg->count;
@@ -431,10 +433,6 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         c.block_h = 8;
     if (c.sorter_depth == 0)
         c.sorter_depth = 8;
-    if (c.list_cap == 0)
-        c.list_cap = 256;
-    if (c.list_cap != 256 && c.list_cap != 1024)
-        return fail(nullptr, LR_ERR_INVALID_ARG, "list_cap must be 256 or 1024");
     if (!valid_bin(c.bin_size))
         return fail(nullptr, LR_ERR_INVALID_ARG, "bin_size must be 16, 32 or 64");
     if (c.block_h != 8)
@@ -578,7 +576,7 @@ lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32
     if (!lock.owns_lock())
         return fail(ctx, LR_ERR_BUSY, "context in use by another thread");
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, ctx->cfg.bin_size,
-                       ctx->cfg.sorter_depth, ctx->cfg.list_cap);
+                       ctx->cfg.sorter_depth);
 }
 
 lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -602,9 +600,9 @@ lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, 
     d.cap = order_cap;
     if (!rgba_f32 && !counts && !flagged && !order_ids)
         return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, ctx->cfg.bin_size,
-                           ctx->cfg.sorter_depth, ctx->cfg.list_cap);
+                           ctx->cfg.sorter_depth);
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, &d, ctx->cfg.bin_size,
-                       ctx->cfg.sorter_depth, ctx->cfg.list_cap);
+                       ctx->cfg.sorter_depth);
 }
 
 lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -618,7 +616,7 @@ lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *ca
     DebugOut d;
     d.rgba = rgba_f32;
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 1, rgba_f32 ? &d : nullptr,
-                       ctx->cfg.bin_size, ctx->cfg.sorter_depth, ctx->cfg.list_cap);
+                       ctx->cfg.bin_size, ctx->cfg.sorter_depth);
 }
 
 lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, void *stream)
@@ -632,9 +630,8 @@ lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, vo
         const lr_request &r = reqs[i];
         uint32_t bin = r.bin_size ? r.bin_size : ctx->cfg.bin_size;
         uint32_t k = r.sorter_depth ? r.sorter_depth : ctx->cfg.sorter_depth;
-        uint32_t lc = r.list_cap ? r.list_cap : ctx->cfg.list_cap;
         lr_status st = render_impl(ctx, r.scene, &r.camera, r.width, r.height, r.out_rgba8, stream, 0, nullptr,
-                                   bin, k, lc);
+                                   bin, k);
         if (st != LR_OK)
             return st;
     }

@@ -27,7 +27,7 @@ LR_FLAG_TIMING = 1
 
 SORTER_DEPTHS = (2, 4, 8, 12, 16, 24, 32)
 BIN_SIZES = (16, 32, 64)
-STAGES = ("setup", "bin_count", "bin_scan", "bin_scatter", "raster", "raster_dense", "fallback", "total")
+STAGES = ("setup", "bin_count", "bin_scan", "bin_scatter", "raster", "unused", "fallback", "total")
 
 
 class LRError(RuntimeError):
@@ -45,8 +45,7 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
                 ("arena_bytes", ctypes.c_uint64), ("bin_size", ctypes.c_uint32),
                 ("block_h", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
-                ("list_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64)]
 
 
 class Stats(ctypes.Structure):
@@ -61,8 +60,7 @@ class Stats(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_uint64), ("camera", Camera), ("width", ctypes.c_uint32),
                 ("height", ctypes.c_uint32), ("out_rgba8", ctypes.c_void_p),
-                ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
-                ("list_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32)]
 
 
 EXPORTS = ["lr_status_string", "lr_last_error", "lr_create", "lr_destroy", "lr_upload_scene",
@@ -135,7 +133,7 @@ class Context:
     """A rendering context on one GPU with a torch-owned device arena."""
 
     def __init__(self, arena_bytes: int = 1 << 30, device: int = 0, bin_size: int = 32,
-                 sorter_depth: int = 8, timing: bool = False, stream=None, list_cap: int = 256):
+                 sorter_depth: int = 8, timing: bool = False, stream=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -147,8 +145,8 @@ class Context:
         cfg = Config(device=device, stream=None if stream is None else int(stream.cuda_stream),
                      arena=self.arena.data_ptr(), arena_bytes=int(arena_bytes), bin_size=bin_size,
                      block_h=8, sorter_depth=sorter_depth, flags=LR_FLAG_TIMING if timing else 0,
-                     hbm_budget_bytes=0, list_cap=list_cap)
-        self.bin_size, self.sorter_depth, self.list_cap = bin_size, sorter_depth, list_cap
+                     hbm_budget_bytes=0)
+        self.bin_size, self.sorter_depth = bin_size, sorter_depth
         h = ctypes.c_void_p()
         self._check(self.lib.lr_create(ctypes.byref(cfg), ctypes.byref(h)), None)
         self.h = h
@@ -272,11 +270,10 @@ class Context:
         return res
 
     def render_batch(self, reqs, stream=None, check: bool = True):
-        """reqs: list of (scene, cam, W, H, out, bin_size, sorter_depth[, list_cap])."""
+        """reqs: list of (scene, cam, W, H, out, bin_size, sorter_depth)."""
         arr = (Request * len(reqs))()
         for k, req in enumerate(reqs):
             scene, cam, W, H, out, bs, kd = req[:7]
-            arr[k].list_cap = req[7] if len(req) > 7 and req[7] else 0
             arr[k].scene = scene
             arr[k].camera = camera_struct(cam)
             arr[k].width, arr[k].height = W, H

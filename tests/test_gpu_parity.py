@@ -30,10 +30,10 @@ def lr():
 _ctx_cache = {}
 
 
-def ctx_for(lr, bin_size=32, k=8):
-    key = (bin_size, k)
+def ctx_for(lr, bin_size=32, k=8, arena=512 << 20):
+    key = (bin_size, k, arena)
     if key not in _ctx_cache:
-        _ctx_cache[key] = lr.Context(arena_bytes=512 << 20, bin_size=bin_size, sorter_depth=k)
+        _ctx_cache[key] = lr.Context(arena_bytes=arena, bin_size=bin_size, sorter_depth=k)
     return _ctx_cache[key]
 
 
@@ -260,7 +260,7 @@ def test_c3_sampled_pixels(lr):
     """Full-size dense cloud: the oracle computes sampled pixels one by one
     (the densest centre region plus random pixels)."""
     sc = scenes.scene("c3")
-    ctx = ctx_for(lr)
+    ctx = ctx_for(lr, arena=1 << 30)
     got = gpu_render(lr, ctx, sc, order=True)
     W, H = sc.width, sc.height
     rng = np.random.default_rng(0)
