@@ -128,6 +128,123 @@ def calibrate_copy(mib):
           flush=True)
 
 
+def mixed_batch_leg(torch, lucidraster, scenes, rules, reps, log):
+    """64 frames of uneven size, count and shape (seeds 1000..1063): one
+    batched call (graph replay, and direct launches) against 64 sequential
+    renders with the same tuning."""
+    frames = [scenes.mixed_scene(1000 + i) for i in range(64)]
+    res = {"frames": 64, "quads": int(sum(s.n for s in frames)), "tuning": "autotuned" if rules else "default",
+           "workload": "64 frames, seeds 1000-1063: size from {256x256, 640x480, 1280x720, 1920x1080}, "
+                       "quads log-uniform 1k-500k, shape of the 256x256, 1280x720 or 1920x1080 workload"}
+    arena = 24 << 30
+    ctxs = {"graph": lucidraster.Context(arena_bytes=arena, tuning=rules, graphs=True),
+            "direct": lucidraster.Context(arena_bytes=arena, tuning=rules, graphs=False)}
+    outs_seq = None
+    for mode, ctx in ctxs.items():
+        hs = [ctx.upload(s.v, s.rgba) for s in frames]
+        outs = [ctx.new_image(s.width, s.height) for s in frames]
+        reqs = [(h, s.camera, s.width, s.height, o) for h, s, o in zip(hs, frames, outs)]
+        ctx.render_batch(reqs)  # plans capacities, captures the graph
+        ctx.render_batch(reqs)
+        frags = ctx.stats()["fragments"]
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            ctx.render_batch(reqs, check=False)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        ctx.sync()
+        ms = float(np.median(ts))
+        res[f"batch_{mode}"] = {"ms": round(ms, 4), "frames_per_s": round(64e3 / ms, 2),
+                                "Mfrags_per_s": round(frags / (ms * 1e-3) / 1e6, 3)}
+        if mode == "graph":
+            # the same 64 frames rendered one at a time
+            seq = [ctx.new_image(s.width, s.height) for s in frames]
+            for h, s, o in zip(hs, frames, seq):
+                ctx.render(h, s.camera, s.width, s.height, out=o)
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for h, s, o in zip(hs, frames, seq):
+                    ctx.render(h, s.camera, s.width, s.height, out=o, check=False)
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            ctx.sync()
+            ms_s = float(np.median(ts))
+            res["sequential"] = {"ms": round(ms_s, 4), "frames_per_s": round(64e3 / ms_s, 2),
+                                 "Mfrags_per_s": round(frags / (ms_s * 1e-3) / 1e6, 3)}
+            res["batch_equals_single"] = all(bool((o == q).all()) for o, q in zip(outs, seq))
+            res["fragments"] = int(frags)
+        log(f"batch {mode}: {ms:.3f} ms for 64 frames")
+        ctx.close()
+    res["batch_over_sequential"] = round(res["sequential"]["ms"] / res["batch_graph"]["ms"], 3)
+    return res
+
+
+def serving_leg(torch, lucidraster, scenes, rules, n_scenes, n_req, log):
+    """Poisson arrivals over resident mixed scenes: continuous batching on two
+    stream slots vs one-at-a-time, at fractions of the one-at-a-time capacity."""
+    from paper_2405_13364_amd import serving
+    ctx = lucidraster.Context(arena_bytes=40 << 30, tuning=rules, graphs=False, batch_slots=2)
+    meta = []
+    for s in range(n_scenes):
+        sc = scenes.mixed_scene(2000 + s)
+        meta.append((ctx.upload(sc.v, sc.rgba), sc.width, sc.height))
+    cam = scenes.Camera()
+    for h, W, H in meta:  # warm-up and capacity planning
+        ctx.render(h, cam, W, H)
+    # one-at-a-time service time: every scene once, back to back
+    outs = {(W, H): ctx.new_image(W, H) for _, W, H in meta}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h, W, H in meta:
+        ctx.render(h, cam, W, H, out=outs[(W, H)], check=False)
+    torch.cuda.synchronize()
+    service_ms = (time.perf_counter() - t0) * 1e3 / len(meta)
+    cap = 1e3 / service_ms
+    res = {"scenes": n_scenes, "requests_per_rate": n_req, "service_ms_alone": round(service_ms, 4),
+           "capacity_frames_per_s": round(cap, 2), "budget_bytes": 8 << 30,
+           "workload": f"{n_scenes} resident scenes (seeds 2000+), Poisson arrivals (seed 3000), camera "
+                       "yaw/pitch jitter U[-2, 2] deg"}
+    modes = {"one_at_a_time": (1, 1), "continuous": (2, 16)}
+    for mode, (slots, mb) in modes.items():
+        rows = []
+        for frac in (0.5, 0.8, 0.95, 1.1):
+            trace = serving.poisson_trace(frac * cap, n_req, meta, seed=3000)
+            be = serving.GpuBackend(ctx, slots, keep_every=97 if mode == "continuous" and frac == 0.95 else 0)
+            srv = serving.Server(be, 8 << 30, slots=slots, max_batch=mb)
+            be.start_clock()
+            done = srv.run(trace)
+            ctx.sync()
+            row = {"rate_frac": frac, "offered_per_s": round(frac * cap, 2)}
+            row.update(serving.summarize(done))
+            rows.append(row)
+            if be.outputs:
+                ok = True
+                for r in trace:
+                    if r.rid in be.outputs:
+                        alone = ctx.render(r.scene, r.camera, r.width, r.height)
+                        ok = ok and bool((alone == be.outputs[r.rid]).all())
+                res["served_equal_alone"] = {"checked": len(be.outputs), "equal": ok}
+            log(f"serving {mode} at {frac:.2f} x capacity: {row['frames_per_s']} frames/s, "
+                f"p50 {row['p50_ms']} ms, p99 {row['p99_ms']} ms, {row['batches']} batches")
+        # saturation: every request present at t = 0
+        trace = serving.poisson_trace(1e9, n_req, meta, seed=3001)
+        be = serving.GpuBackend(ctx, slots)
+        be.start_clock()
+        done = serving.Server(be, 8 << 30, slots=slots, max_batch=mb).run(trace)
+        ctx.sync()
+        res[mode] = {"rates": rows, "saturated": serving.summarize(done)}
+    res["saturated_speedup"] = round(res["continuous"]["saturated"]["frames_per_s"] /
+                                     res["one_at_a_time"]["saturated"]["frames_per_s"], 3)
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +255,11 @@ def main():
     ap.add_argument("--sorter-depth", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame mixed batch")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--serve-scenes", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -235,6 +357,14 @@ def main():
     else:
         res["cpu_baseline"] = None
     ctx.close()
+    from paper_2405_13364_amd import autotune
+    rules = autotune.load_rules()
+    if not args.no_batch:
+        log("64-frame mixed batch")
+        res["batch"] = mixed_batch_leg(torch, lucidraster, scenes, rules, args.batch_reps, log)
+    if not args.no_serving:
+        log("serving loop")
+        res["serving"] = serving_leg(torch, lucidraster, scenes, rules, args.serve_scenes, args.serve_requests, log)
     print(json.dumps(res), flush=True)
 
 

@@ -82,15 +82,25 @@ typedef struct {
     uint64_t arena_bytes;     /* arena size; with arena == NULL the library
                                  allocates this much once (default 1 GiB) */
     uint32_t bin_size;        /* 16, 32 (default) or 64 pixels */
-    uint32_t block_h;         /* 8: 8x8 blocks (default); 4: 8x4 half-blocks */
-    uint32_t sorter_depth;    /* per-pixel sorter capacity K, 2..32 (default 8) */
+    uint32_t block_h;         /* depth-sort granularity: 8 for 8x8 blocks
+                                 (default), 4 for 8x4 half-blocks (Stage 3,
+                                 Phase 2); images are identical either way */
+    uint32_t sorter_depth;    /* per-pixel sorter capacity K: 2, 4, 8
+                                 (default), 12, 16, 24 or 32 */
     uint32_t flags;           /* LR_FLAG_* */
     uint64_t hbm_budget_bytes;/* serving admission budget (0: arena size) */
+    uint32_t batch_slots;     /* batch workspaces that may be in flight at
+                                 once, on different streams (default 2, at
+                                 most 8) */
+    uint32_t reserved;
 } lr_config;
 
 #define LR_FLAG_TIMING 1u     /* record per-stage times (hipEvents) */
+#define LR_FLAG_NO_GRAPH 2u   /* lr_render_batch launches directly instead
+                                 of replaying captured hipGraphs */
 
-/* Statistics of the last completed render on the context. */
+/* Statistics of the last render call on the context (for a batch, summed over
+ * its frames; error_word is the OR of theirs). */
 typedef struct {
     uint64_t quads;           /* input quads */
     uint64_t visible;         /* quads that passed setup */
@@ -108,15 +118,29 @@ typedef struct {
                                  raster, (unused), exact per-pixel pass, total */
 } lr_stats;
 
-/* A request for lr_render_batch. */
+/* A request for lr_render_batch.  A zero tuning field takes the first
+ * matching rule set by lr_set_tuning, else the context default. */
 typedef struct {
     lr_scene scene;
     lr_camera camera;
     uint32_t width, height;
     uint8_t *out_rgba8;       /* device, width*height*4 bytes */
-    uint32_t bin_size;        /* 0: context default */
-    uint32_t sorter_depth;    /* 0: context default */
+    uint32_t bin_size;        /* 16, 32, 64 or 0 */
+    uint32_t sorter_depth;    /* as lr_config.sorter_depth, or 0 */
+    uint32_t block_h;         /* 4, 8 or 0 */
+    uint32_t reserved;
 } lr_request;
+
+/* A tuning rule: applies to frames of at most max_pixels pixels with at most
+ * max_quads_per_pixel quads per pixel (resident quads / (width*height)).
+ * The autotuner writes these from a sweep of frame shapes (the paper's
+ * Section 4 suggests adapting the bin size to the scene). */
+typedef struct {
+    uint32_t max_pixels;
+    float max_quads_per_pixel;
+    uint32_t bin_size, block_h, sorter_depth;
+    uint32_t reserved;
+} lr_tune_rule;
 
 /* Human-readable name of a status code (static storage). */
 const char *lr_status_string(lr_status s);
@@ -145,7 +169,10 @@ lr_status lr_release_scene(lr_context ctx, lr_scene scene);
 
 /* Render a scene into out_rgba8 (device, width*height*4 bytes, row-major, top
  * row first, premultiplied RGBA8).  1 <= width, height <= 16384.  Runs on
- * stream (NULL: the context stream) and returns without waiting. */
+ * stream (NULL: the context stream) and returns without waiting.  The bin
+ * size, block shape and sorter depth come from the first matching tuning rule
+ * (lr_set_tuning), else from the context configuration; the image does not
+ * depend on them. */
 lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                     uint32_t height, uint8_t *out_rgba8, void *stream);
 
@@ -168,9 +195,24 @@ lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, 
 lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                              uint32_t height, uint8_t *out_rgba8, void *stream, float *rgba_f32);
 
-/* Render n requests back to back on one stream (uneven sizes allowed);
- * every output is bit-identical to the corresponding lr_render. */
+/* Render n requests (uneven sizes and tunings allowed) on one stream.  Each
+ * stage runs as one launch over up to 64 frames at a time (one per distinct
+ * sorter depth for the raster stage), so small frames share the GPU; the
+ * launch sequence is captured once per batch shape into a hipGraph and
+ * replayed (unless LR_FLAG_NO_GRAPH).  Every output is bit-identical to
+ * lr_render of the same request with the same tuning.  The batch uses one of
+ * the context's batch workspaces: batches on different streams run
+ * concurrently, up to lr_config.batch_slots at a time.  Returns
+ * LR_ERR_OUT_OF_MEMORY when one frame alone does not fit the arena. */
 lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, void *stream);
+
+/* Replace the tuning rules (copied; n = 0 clears them).  Rules are tried in
+ * order; max_pixels must be non-zero and the tuning values valid. */
+lr_status lr_set_tuning(lr_context ctx, const lr_tune_rule *rules, uint32_t n);
+
+/* Device memory one request needs while in flight (its frame workspace,
+ * after tuning), for admission control.  Does not allocate. */
+lr_status lr_request_bytes(lr_context ctx, const lr_request *req, uint64_t *bytes);
 
 /* Wait for all work the context issued; report a latched kernel error
  * (LR_ERR_CAPACITY) and clear it. */

@@ -1,0 +1,116 @@
+"""Autotuner: per-frame-shape choice of bin size, block shape and sorter depth.
+
+The sweep renders sample frames of every class (frame size x quads-per-pixel
+bucket), each drawn from the three base workload shapes, under every tuning
+(bin 16/32/64 x 8x8 or 8x4 blocks x sorter depth 8..32), and keeps for each
+class the tuning with the least total GPU time.  The result is a list of
+``lr_tune_rule`` records (first match wins), written as JSON beside this
+module; ``Context(tuning=load_rules())`` installs it.
+
+Every tuning gives the same image (the renderer is exact), so the sweep only
+measures time.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+RULES_PATH = os.path.join(HERE, "tuning.json")
+
+BINS = (16, 32, 64)
+BLOCKS = (8, 4)
+DEPTHS = (8, 12, 16, 24, 32)
+# quads-per-pixel bucket upper bounds and the value sampled in each bucket
+QPP_BUCKETS = ((0.01, 0.005), (0.05, 0.022), (0.2, 0.1), (1.0, 0.45), (1e9, 2.0))
+
+
+def tunings():
+    return list(itertools.product(BINS, DEPTHS, BLOCKS))
+
+
+def sample_frames(W: int, H: int, qpp: float, seed: int):
+    """One frame per base workload shape at this size and density."""
+    from . import scenes
+    n = int(min(500_000, max(1_000, round(qpp * W * H))))
+    out = []
+    for k, base in enumerate(("c1", "c2", "c3")):
+        b = scenes.RECIPES[base]
+        rc = scenes.Recipe(W, H, n, seed + k, b.gaussian, b.sigma, b.z, b.side, b.alpha)
+        out.append(scenes.generate(rc, f"tune-{base}-{W}x{H}-{n}"))
+    return out
+
+
+def time_frame(ctx, h, sc, tune, reps: int) -> float:
+    """Median GPU milliseconds of one frame rendered as a one-frame batch."""
+    import torch
+    out = ctx.new_image(sc.width, sc.height)
+    req = [(h, sc.camera, sc.width, sc.height, out) + tuple(tune)]
+    ctx.render_batch(req)  # warm-up (and capacity planning)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ctx.render_batch(req, check=False)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ctx.sync()
+    return float(np.median(ts))
+
+
+def sweep(resolutions=None, reps: int = 5, log=print) -> Dict[str, object]:
+    from . import lucidraster, scenes
+    resolutions = resolutions or scenes.RESOLUTIONS
+    ctx = lucidraster.Context(arena_bytes=8 << 30, graphs=False)
+    rules, table = [], []
+    t0 = time.perf_counter()
+    for W, H in sorted(resolutions, key=lambda r: r[0] * r[1]):
+        for qmax, qpp in QPP_BUCKETS:
+            frames = sample_frames(W, H, qpp, seed=4000 + W + H)
+            hs = [ctx.upload(s.v, s.rgba) for s in frames]
+            cost = {}
+            for tune in tunings():
+                cost[tune] = sum(time_frame(ctx, h, s, tune, reps) for h, s in zip(hs, frames))
+            for h in hs:
+                ctx.release(h)
+            best = min(cost, key=cost.get)
+            default = cost[(32, 8, 8)]
+            table.append({"width": W, "height": H, "qpp": qpp, "quads": frames[0].n,
+                          "best": list(best), "best_ms": round(cost[best], 4),
+                          "default_ms": round(default, 4),
+                          "all_ms": {f"{b}/{k}/{bh}": round(v, 4) for (b, k, bh), v in cost.items()}})
+            rules.append({"max_pixels": W * H, "max_quads_per_pixel": qmax, "bin_size": best[0],
+                          "sorter_depth": best[1], "block_h": best[2]})
+            log(f"[autotune] {W}x{H} qpp {qpp}: best bin {best[0]} K {best[1]} block 8x{best[2]} "
+                f"{cost[best]:.3f} ms (bin 32 K 8 8x8: {default:.3f} ms)")
+    ctx.close()
+    return {"rules": rules, "sweep": table, "reps": reps, "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def load_rules(path: str = RULES_PATH) -> Optional[List[dict]]:
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)["rules"]
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="sweep tunings on the GPU and write the rule table")
+    ap.add_argument("--out", default=RULES_PATH)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    res = sweep(reps=args.reps)
+    with open(args.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(f"wrote {args.out}: {len(res['rules'])} rules in {res['seconds']} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -83,8 +83,20 @@ struct FrameCounters {
 };
 
 constexpr uint32_t kErrPairs = 1u;      // bin lists overflowed their capacity
-constexpr uint32_t kErrFallback = 2u;   // a pixel had more fragments than the exact sort holds
 constexpr uint32_t kErrDense = 4u;      // a block could not be sliced to fit its list (pixels sent to the exact sort)
+
+// Context-wide log of frames whose bin lists overflowed, kept until the host
+// reads and clears it (frame workspaces, and their counters, are reused by
+// later frames before the host looks).
+constexpr uint32_t kErrLogCap = 480;
+struct ErrLog {
+    uint32_t n;          // overflows logged (may exceed kErrLogCap)
+    uint32_t pad[31];
+    struct Entry {
+        uint32_t tag;    // FrameArgs::tag of the frame
+        uint32_t pairs;  // pairs the frame needed
+    } e[kErrLogCap];
+};
 
 // Waves per raster workgroup (one bin, one 8x8 block per wave at a time).
 constexpr uint32_t kRasterWaves = 4;
@@ -120,15 +132,20 @@ struct FrameArgs {
     uint32_t pair_cap;
     uint32_t match_bits;    // bits needed to hold a bin index
     // raster
+    uint32_t half_blocks;     // 1: block lists are sorted per 8x4 half-block
+    uint32_t fb_groups;       // exact-pass workgroups per flagged-queue stripe
     uint32_t nblk_x, nblk_y;  // 8x8 blocks
     uint32_t qcap_blocks;     // blocks per queue stripe: ceil(nblk_x*nblk_y / kQueues)
     uint32_t *fb_queue;       // flagged pixels [kQueues][qcap_blocks * 64]
     // block entries of the raster stage, per (bin, wave) region of the bin's
     // length at entry (kRasterWaves * bin_start[bin] + wave * bin_count[bin])
+    // ((1 + half_blocks) times those sizes with half-blocks)
     uint32_t *ent_code;       // block depth code
     unsigned long long *ent_mask;  // 64-sample coverage mask
     uint32_t *ent_id;         // quad index
     FrameCounters *ctr;
+    ErrLog *elog;
+    uint32_t tag;             // host-assigned frame tag for the error log
     uint8_t *out;             // RGBA8
     // debug outputs (may be null)
     float *dbg_rgba;
@@ -139,6 +156,23 @@ struct FrameArgs {
     uint32_t dbg_cap;
 };
 
+// Frames per batched launch: the frame map travels in the kernel arguments.
+constexpr uint32_t kMaxBatch = 64;
+
+// Source of a workgroup's frame.  OneFrame: a single frame, its arguments by
+// value.  FrameMap: frames of a batch whose arguments sit in device memory;
+// for one launch, wg0[f] is the first workgroup of frame f and wg0[nf] the
+// grid size (a frame with no work in the launch has wg0[f] == wg0[f + 1]).
+struct OneFrame {
+    FrameArgs a;
+};
+
+struct FrameMap {
+    const FrameArgs *tab;
+    uint32_t nf;
+    uint32_t wg0[kMaxBatch + 1];
+};
+
 // Kernel launches (lr_kernels.hip).
 hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s,
                         hipEvent_t *ev /* 8 events or null */);
@@ -147,5 +181,15 @@ hipError_t launch_binning_only(const FrameArgs &a, hipStream_t s);
 hipError_t launch_transpose_scene(const void *quads_dev, uint32_t n, float *v, uint32_t *rgba,
                                   hipStream_t s);
 bool sorter_depth_supported(int k);
+
+// A batch of nf <= kMaxBatch frames: host copies of their arguments (for the
+// launch geometry), the same arguments already in device memory (dev), and
+// each frame's sorter depth.  One launch per stage covers every frame (one
+// per distinct sorter depth for the raster stage).
+hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *sorter_depth, uint32_t nf,
+                        hipStream_t s);
+
+// Workgroups the exact per-pixel pass uses per flagged-queue stripe.
+uint32_t fallback_groups(uint32_t nblocks);
 
 }  // namespace lr

@@ -19,6 +19,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace lr {
 
 // ------------------------------------------------------------------ helpers
@@ -130,11 +132,41 @@ __device__ __forceinline__ uint32_t pack_rgba8(float R, float G, float B, float 
     return to_u8(R) | (to_u8(G) << 8) | (to_u8(B) << 16) | (to_u8(A) << 24);
 }
 
+// ------------------------------------------------------- frame resolution
+//
+// Every kernel runs either for one frame (arguments by value) or for a batch
+// of frames (one grid covering all of them): frame_of gives the workgroup's
+// frame and its workgroup index within that frame.
+
+__device__ __forceinline__ const FrameArgs *frame_of(const OneFrame &src, uint32_t &blk)
+{
+    blk = blockIdx.x;
+    return &src.a;
+}
+
+__device__ __forceinline__ const FrameArgs *frame_of(const FrameMap &m, uint32_t &blk)
+{
+    const uint32_t b = blockIdx.x;
+    uint32_t lo = 0, hi = m.nf;  // wg0[lo] <= b < wg0[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (m.wg0[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    blk = b - m.wg0[lo];
+    return m.tab + lo;
+}
+
 // ------------------------------------------------------------- frame begin
 
-__global__ __launch_bounds__(256) void k_frame_begin(FrameCounters *c)
+template <class Src>
+__global__ __launch_bounds__(256) void k_frame_begin(Src src)
 {
-    uint4 *p = reinterpret_cast<uint4 *>(c);
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    uint4 *p = reinterpret_cast<uint4 *>(a.ctr);
     for (uint32_t i = threadIdx.x; i < sizeof(FrameCounters) / 16; i += blockDim.x)
         p[i] = make_uint4(0, 0, 0, 0);
 }
@@ -225,9 +257,12 @@ __device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, int64_t Rx
     flags |= kConvex;
 }
 
-__global__ __launch_bounds__(256) void k_setup(FrameArgs a)
+template <class Src>
+__global__ __launch_bounds__(256) void k_setup(Src src)
 {
-    const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const uint32_t q = blk * 256 + threadIdx.x;
     uint32_t reason = 0xff;
     if (q < a.n) {
         const uint32_t n = a.n;
@@ -385,10 +420,14 @@ __device__ __forceinline__ bool quad_bins(uint2 bb, uint32_t shift, uint32_t &bx
     return true;
 }
 
-__global__ __launch_bounds__(64) void k_bin_count(FrameArgs a, const uint2 *__restrict__ bbox)
+template <class Src>
+__global__ __launch_bounds__(64) void k_bin_count(Src src)
 {
     extern __shared__ uint32_t s_hist[];
-    const uint32_t lane = threadIdx.x, u = blockIdx.x;
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t lane = threadIdx.x, u = blk;
     for (uint32_t b = lane; b < a.nbins; b += 64)
         s_hist[b] = 0;
     __syncthreads();
@@ -411,10 +450,17 @@ __global__ __launch_bounds__(64) void k_bin_count(FrameArgs a, const uint2 *__re
         row[b] = s_hist[b];
 }
 
+// Workgroups of the tile scan: ceil(nbins / 64) per tile of 64 units.
+__host__ __device__ __forceinline__ uint32_t scan_groups_x(uint32_t nbins) { return (nbins + 63) / 64; }
+
 // table[u][b] -> exclusive prefix over the units of one tile; tile totals.
-__global__ __launch_bounds__(64) void k_bin_scan_tiles(FrameArgs a)
+template <class Src>
+__global__ __launch_bounds__(64) void k_bin_scan_tiles(Src src)
 {
-    const uint32_t b = blockIdx.x * 64 + threadIdx.x, tile = blockIdx.y;
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const uint32_t gx = scan_groups_x(a.nbins);
+    const uint32_t b = (blk % gx) * 64 + threadIdx.x, tile = blk / gx;
     if (b >= a.nbins)
         return;
     const uint32_t u0 = tile * 64, u1 = min(u0 + 64, a.nunits);
@@ -436,9 +482,12 @@ __global__ __launch_bounds__(64) void k_bin_scan_tiles(FrameArgs a)
 }
 
 // Per bin: prefix over tiles and the bin total; then the prefix over bins.
-__global__ __launch_bounds__(1024) void k_bin_scan_final(FrameArgs a)
+template <class Src>
+__global__ __launch_bounds__(1024) void k_bin_scan_final(Src src)
 {
     __shared__ uint32_t s_part[1024];
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
     const uint32_t t = threadIdx.x;
     const uint32_t per = (a.nbins + 1023) / 1024;
     const uint32_t b0 = min(t * per, a.nbins), b1 = min(b0 + per, a.nbins);
@@ -472,17 +521,27 @@ __global__ __launch_bounds__(1024) void k_bin_scan_final(FrameArgs a)
         uint32_t total = s_part[1023];
         a.bin_start[a.nbins] = total;
         a.ctr->pairs_total = total;
-        if (total > a.pair_cap)
+        if (total > a.pair_cap) {
             a.ctr->error |= kErrPairs;
+            const uint32_t i = atomicAdd(&a.elog->n, 1u);
+            if (i < kErrLogCap) {
+                a.elog->e[i].tag = a.tag;
+                a.elog->e[i].pairs = total;
+            }
+        }
     }
 }
 
-__global__ __launch_bounds__(64) void k_bin_scatter(FrameArgs a, const uint2 *__restrict__ bbox)
+template <class Src>
+__global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 {
     extern __shared__ uint32_t s_off[];
     __shared__ uint32_t s_pref[64];
     __shared__ uint32_t s_rect[64][3];
-    const uint32_t lane = threadIdx.x, u = blockIdx.x;
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t lane = threadIdx.x, u = blk;
     const uint32_t *row = a.table + (size_t)u * a.nbins;
     const uint32_t *tsum = a.tile_sums + (size_t)(u >> 6) * a.nbins;
     for (uint32_t b = lane; b < a.nbins; b += 64)
@@ -969,37 +1028,54 @@ struct PixelSorter {
 // non-empty entries go to the wave's global entry region at slot n + rank,
 // and the first kSortCap also to the LDS sort keys (key bits above the slot
 // index).  kmin / kmax track the key range.
+//
+// With half-blocks, the rows 0-3 and 4-7 of a mask become separate entries,
+// each keyed at the centroid of its own samples: one sort then orders both
+// 8x4 halves, and a pixel only sees the entries of its half.
+__device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32_t ebase, uint32_t sb,
+                                          uint32_t slot, uint32_t code, uint64_t mask, uint32_t q)
+{
+    a.ent_code[ebase + slot] = code;
+    a.ent_mask[ebase + slot] = mask;
+    a.ent_id[ebase + slot] = q;
+    if (slot < kSortCap)
+        L.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
+}
+
 __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *__restrict__ rec,
                                              const QuadXY *__restrict__ xyp, WaveLds &L, uint32_t m,
                                              const BlockGeom &g, uint32_t lane, uint32_t ebase, uint32_t sb,
-                                             uint32_t &n, uint32_t &kmin, uint32_t &kmax)
+                                             bool half, uint32_t &n, uint32_t &kmin, uint32_t &kmax)
 {
-    uint64_t mk = 0;
-    uint32_t q = 0, code = 0;
+    uint64_t m0 = 0, m1 = 0;  // entries: m0 (whole block, or rows 0-3), m1 (rows 4-7)
+    uint32_t q = 0, c0 = 0, c1 = 0;
     if (lane < m) {
         q = L.cand[lane];
         const QuadRec &r = rec[q];
-        mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
-        if (mk)
-            code = block_depth_code(r, mk, g.px0, g.py0);
+        const uint64_t mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
+        m0 = half ? (mk & 0xFFFFFFFFull) : mk;
+        m1 = half ? (mk & ~0xFFFFFFFFull) : 0;
+        if (m0)
+            c0 = block_depth_code(r, m0, g.px0, g.py0);
+        if (m1)
+            c1 = block_depth_code(r, m1, g.px0, g.py0);
     }
-    const uint64_t b = ballot(mk != 0);
-    const uint32_t slot = n + rank_below(b);
-    if (mk) {
-        a.ent_code[ebase + slot] = code;
-        a.ent_mask[ebase + slot] = mk;
-        a.ent_id[ebase + slot] = q;
-        if (slot < kSortCap)
-            L.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
-    }
-    uint32_t mn = mk ? code : 0xFFFFFFFFu, mx = mk ? code : 0u;
+    const uint64_t b0 = ballot(m0 != 0);
+    const uint64_t b1 = half ? ballot(m1 != 0) : 0;
+    const uint32_t n0 = (uint32_t)__popcll(b0);
+    if (m0)
+        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q);
+    if (m1)
+        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q);
+    uint32_t mn = min(m0 ? c0 : 0xFFFFFFFFu, m1 ? c1 : 0xFFFFFFFFu);
+    uint32_t mx = max(m0 ? c0 : 0u, m1 ? c1 : 0u);
     for (int off = 32; off > 0; off >>= 1) {
         mn = min(mn, shfl_xor(mn, off));
         mx = max(mx, shfl_xor(mx, off));
     }
     kmin = min(kmin, mn);
     kmax = max(kmax, mx);
-    n += (uint32_t)__popcll(b);
+    n += n0 + (uint32_t)__popcll(b1);
 }
 
 // Phases 2 and 3 for n sorted-key entries in L.key (entry = low sb bits,
@@ -1147,32 +1223,37 @@ __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t la
 
 // Sorted raster: one workgroup of kRasterWaves waves per bin, one 8x8 block
 // per wave per round (16-pixel bins: 1 round; 32: 4; 64: 16).
-template <int K, bool DEBUG>
-__global__ __launch_bounds__(kRasterWaves * 64) void k_raster(FrameArgs a, const QuadRec *__restrict__ rec,
-                                                              const QuadXY *__restrict__ xyp,
-                                                              const uint2 *__restrict__ bbox,
-                                                              const uint32_t *__restrict__ pairs)
+template <int K, bool DEBUG, class Src>
+__global__ __launch_bounds__(kRasterWaves * 64) void k_raster(Src src)
 {
     constexpr uint32_t NW = kRasterWaves;
     __shared__ BinChunk<NW> C;
     __shared__ WaveLds Lw[NW];
+    uint32_t bin;
+    const FrameArgs &a = *frame_of(src, bin);
+    const QuadRec *__restrict__ rec = a.rec;
+    const QuadXY *__restrict__ xyp = a.xy;
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t *__restrict__ pairs = a.pairs;
     if (a.ctr->error & kErrPairs)
         return;  // bin lists are incomplete: the frame is reported as failed
-    const uint32_t bin = blockIdx.x;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t bpb = 1u << (a.bin_shift - 3), nb = bpb * bpb;
     const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
     const uint32_t bx_bin = (bin % a.nbx) * bpb, by_bin = (bin / a.nbx) * bpb;
-    const uint32_t ebase = NW * start + wave * cnt;  // this wave's entry region (cnt entries)
-    // entry index bits in a sort key: enough for kSortCap and for cnt
-    const uint32_t sb = max(10u, cnt > 1 ? 32 - __builtin_clz(cnt - 1) : 1u);
+    // this wave's entry region: cnt entries per block, twice that with half-blocks
+    const bool half = a.half_blocks != 0;
+    const uint32_t ecap = half ? 2 * cnt : cnt;
+    const uint32_t ebase = NW * (half ? 2 * start : start) + wave * ecap;
+    // entry index bits in a sort key: enough for kSortCap and for ecap
+    const uint32_t sb = max(10u, ecap > 1 ? 32 - __builtin_clz(ecap - 1) : 1u);
     WaveLds &L = Lw[wave];
     for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
         const uint32_t k = r0 + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         uint32_t n = 0, kmin = 0xFFFFFFFFu, kmax = 0;
         scan_bin<NW>(bbox, pairs, C, L, start, cnt, g, [&](uint32_t m) {
-            sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, n, kmin, kmax);
+            sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, half, n, kmin, kmax);
         });
         if (!g.active)
             continue;
@@ -1207,18 +1288,22 @@ __global__ __launch_bounds__(kRasterWaves * 64) void k_raster(FrameArgs a, const
 
 constexpr uint32_t kFallbackBuf = 4096;
 
-template <bool DEBUG>
-__global__ __launch_bounds__(64) void k_fallback(FrameArgs a, const QuadRec *__restrict__ rec,
-                                                 const QuadXY *__restrict__ xyp, const uint2 *__restrict__ bbox,
-                                                 const uint32_t *__restrict__ pairs)
+template <bool DEBUG, class Src>
+__global__ __launch_bounds__(64) void k_fallback(Src src)
 {
     __shared__ unsigned long long s_key[kFallbackBuf];
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const QuadRec *__restrict__ rec = a.rec;
+    const QuadXY *__restrict__ xyp = a.xy;
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t *__restrict__ pairs = a.pairs;
     if (a.ctr->error & kErrPairs)
         return;
     const uint32_t lane = threadIdx.x;
-    const uint32_t sq = blockIdx.x % kQueues, G = gridDim.x / kQueues;
+    const uint32_t sq = blk % kQueues, G = a.fb_groups;
     const uint32_t count = uniform(a.ctr->stripe[sq].flag_n);
-    for (uint32_t t = blockIdx.x / kQueues; t < count; t += G) {
+    for (uint32_t t = blk / kQueues; t < count; t += G) {
         const uint32_t p = uniform(a.fb_queue[(size_t)sq * a.qcap_blocks * 64 + t]);
         const int i = (int)(p % a.W), j = (int)(p / a.W);
         const uint32_t bin = ((uint32_t)j >> a.bin_shift) * a.nbx + ((uint32_t)i >> a.bin_shift);
@@ -1312,17 +1397,19 @@ struct UnsortedLds {
     uint32_t col[64];
 };
 
-template <int NW, bool DEBUG>
-__global__ __launch_bounds__(NW * 64) void k_unsorted(FrameArgs a, const QuadRec *__restrict__ rec,
-                                                      const QuadXY *__restrict__ xyp,
-                                                      const uint2 *__restrict__ bbox,
-                                                      const uint32_t *__restrict__ pairs)
+template <int NW, bool DEBUG, class Src>
+__global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
 {
     __shared__ BinChunk<NW> C;
     __shared__ UnsortedLds Uw[NW];
+    uint32_t bin;
+    const FrameArgs &a = *frame_of(src, bin);
+    const QuadRec *__restrict__ rec = a.rec;
+    const QuadXY *__restrict__ xyp = a.xy;
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t *__restrict__ pairs = a.pairs;
     if (a.ctr->error & kErrPairs)
         return;
-    const uint32_t bin = blockIdx.x;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t bpb = 1u << (a.bin_shift - 3), nb = bpb * bpb;
     const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
@@ -1390,22 +1477,28 @@ __global__ __launch_bounds__(256) void k_transpose_scene(const uint32_t *__restr
 
 // ---------------------------------------------------------------- launches
 
+uint32_t fallback_groups(uint32_t nblocks)
+{
+    return std::min<uint32_t>(32, std::max<uint32_t>(2, (nblocks + 255) / 256));
+}
+
 static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEvent_t *ev, bool bins)
 {
-    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(256), 0, s, a.ctr);
-    hipLaunchKernelGGL(k_setup, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+    const OneFrame f{a};
+    hipLaunchKernelGGL(k_frame_begin<OneFrame>, dim3(1), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_setup<OneFrame>, dim3((a.n + 255) / 256), dim3(256), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[1], s);
     if (!bins)
         return hipGetLastError();
-    hipLaunchKernelGGL(k_bin_count, dim3(a.nunits), dim3(64), a.nbins * 4, s, a, (const uint2 *)a.bbox);
+    hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
         (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_bin_scan_tiles, dim3((a.nbins + 63) / 64, a.ntiles), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_bin_scan_final, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_bin_scan_tiles<OneFrame>, dim3(scan_groups_x(a.nbins) * a.ntiles), dim3(64), 0, s, f);
+    hipLaunchKernelGGL(k_bin_scan_final<OneFrame>, dim3(1), dim3(1024), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(a.nunits), dim3(64), a.nbins * 4, s, a, (const uint2 *)a.bbox);
+    hipLaunchKernelGGL(k_bin_scatter<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
         (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
@@ -1426,20 +1519,17 @@ bool sorter_depth_supported(int k)
     return k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 24 || k == 32;
 }
 
-// One workgroup of kRasterWaves waves per bin.
+// Raster (one workgroup of kRasterWaves waves per bin), then the exact pass.
 template <int K, bool DEBUG>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
-    const QuadRec *rec = a.rec;
-    const QuadXY *xy = a.xy;
-    const uint2 *bb = a.bbox;
-    const uint32_t *pr = a.pairs;
-    hipLaunchKernelGGL((k_raster<K, DEBUG>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s, a, rec, xy, bb, pr);
+    const OneFrame f{a};
+    hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s, f);
     if (ev) {
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
     }
-    hipLaunchKernelGGL((k_fallback<DEBUG>), dim3(kQueues * 32), dim3(64), 0, s, a, rec, xy, bb, pr);
+    hipLaunchKernelGGL((k_fallback<DEBUG, OneFrame>), dim3(kQueues * a.fb_groups), dim3(64), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[7], s);
 }
@@ -1461,12 +1551,9 @@ static void launch_sorted_k(const FrameArgs &a, int k, hipStream_t s, hipEvent_t
 template <bool DEBUG>
 static void launch_unsorted(const FrameArgs &a, hipStream_t s)
 {
-    const QuadRec *rec = a.rec;
-    const QuadXY *xy = a.xy;
-    const uint2 *bb = a.bbox;
-    const uint32_t *pr = a.pairs;
-    hipLaunchKernelGGL((k_unsorted<kRasterWaves, DEBUG>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s, a, rec,
-                       xy, bb, pr);
+    const OneFrame f{a};
+    hipLaunchKernelGGL((k_unsorted<kRasterWaves, DEBUG, OneFrame>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s,
+                       f);
 }
 
 hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s, hipEvent_t *ev)
@@ -1492,6 +1579,75 @@ hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipS
     } else {
         launch_sorted_k<false>(a, sorter_depth, s, ev);
     }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- batched launches
+
+// A frame map for one stage: wg(f) workgroups for frame f (0 to skip it).
+template <typename F>
+static FrameMap stage_map(const FrameArgs *dev, uint32_t nf, F &&wg)
+{
+    FrameMap m{};
+    m.tab = dev;
+    m.nf = nf;
+    uint32_t t = 0;
+    for (uint32_t f = 0; f < nf; f++) {
+        m.wg0[f] = t;
+        t += wg(f);
+    }
+    m.wg0[nf] = t;
+    return m;
+}
+
+template <int K>
+static void launch_raster_group(const FrameMap &m, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_raster<K, false, FrameMap>), dim3(m.wg0[m.nf]), dim3(kRasterWaves * 64), 0, s, m);
+}
+
+hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *sorter_depth, uint32_t nf,
+                        hipStream_t s)
+{
+    if (nf == 0)
+        return hipSuccess;
+    if (nf > kMaxBatch)
+        return hipErrorInvalidValue;
+    uint32_t max_bins = 0;
+    for (uint32_t f = 0; f < nf; f++)
+        max_bins = std::max(max_bins, host[f].nbins);
+    const FrameMap one = stage_map(dev, nf, [](uint32_t) { return 1u; });
+    hipLaunchKernelGGL(k_frame_begin<FrameMap>, dim3(nf), dim3(256), 0, s, one);
+    const FrameMap ms = stage_map(dev, nf, [&](uint32_t f) { return (host[f].n + 255) / 256; });
+    hipLaunchKernelGGL(k_setup<FrameMap>, dim3(ms.wg0[nf]), dim3(256), 0, s, ms);
+    const FrameMap mu = stage_map(dev, nf, [&](uint32_t f) { return host[f].nunits; });
+    hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
+    const FrameMap mt =
+        stage_map(dev, nf, [&](uint32_t f) { return scan_groups_x(host[f].nbins) * host[f].ntiles; });
+    hipLaunchKernelGGL(k_bin_scan_tiles<FrameMap>, dim3(mt.wg0[nf]), dim3(64), 0, s, mt);
+    hipLaunchKernelGGL(k_bin_scan_final<FrameMap>, dim3(nf), dim3(1024), 0, s, one);
+    hipLaunchKernelGGL(k_bin_scatter<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
+    static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
+    for (int K : kDepths) {
+        bool any = false;
+        for (uint32_t f = 0; f < nf; f++)
+            any = any || sorter_depth[f] == K;
+        if (!any)
+            continue;
+        const FrameMap mr =
+            stage_map(dev, nf, [&](uint32_t f) { return sorter_depth[f] == K ? host[f].nbins : 0u; });
+        switch (K) {
+        case 2: launch_raster_group<2>(mr, s); break;
+        case 4: launch_raster_group<4>(mr, s); break;
+        case 8: launch_raster_group<8>(mr, s); break;
+        case 12: launch_raster_group<12>(mr, s); break;
+        case 16: launch_raster_group<16>(mr, s); break;
+        case 24: launch_raster_group<24>(mr, s); break;
+        default: launch_raster_group<32>(mr, s); break;
+        }
+    }
+    const FrameMap mf = stage_map(dev, nf, [&](uint32_t f) { return kQueues * host[f].fb_groups; });
+    hipLaunchKernelGGL((k_fallback<false, FrameMap>), dim3(mf.wg0[nf]), dim3(64), 0, s, mf);
     return hipGetLastError();
 }
 

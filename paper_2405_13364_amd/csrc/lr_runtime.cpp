@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lr_internal.h"
@@ -86,6 +87,40 @@ struct Workspace {
     bool valid = false;
 };
 
+// A batch workspace: frame table + per-frame workspaces of one launch group.
+struct BatchSlot {
+    uint64_t off = 0, bytes = 0;
+    bool valid = false, used = false;
+    hipEvent_t done = nullptr;   // recorded after the last group that used it
+    hipStream_t last = nullptr;
+    uint64_t stamp = 0;
+};
+
+// A frame of the last render call (for statistics).
+struct FrameRef {
+    uint64_t ctr_off;
+    uint64_t quads;
+    int slot;  // batch slot holding its counters, -1: the context workspace
+};
+
+// Frame tags remembered for the error log (tag % kTagRing).
+constexpr uint32_t kTagRing = 4096;
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint64_t stamp = 0;
+};
+
+// Resolved tuning of one frame.
+struct Tune {
+    uint32_t bin, half, k;
+};
+
+using HintKey = std::tuple<lr_scene, uint32_t, uint32_t, uint32_t>;  // scene, W, H, bin
+
+// Pinned frame-table buffers in flight at once (host side of the batch table).
+constexpr uint32_t kTabRing = 8;
+
 }  // namespace
 
 struct lr_context_s {
@@ -99,8 +134,26 @@ struct lr_context_s {
     std::map<lr_scene, SceneRec> scenes;
     lr_scene next_scene = 1;
     Workspace ws;
-    uint64_t ws_ctr_off = 0;       // FrameCounters of the last frame (inside ws)
-    uint32_t pair_hint = 0;        // capacity learnt from an overflow
+    std::map<HintKey, uint32_t> pair_hints;  // bin-list capacity learnt from overflows
+    std::vector<FrameRef> last_frames;       // frames of the last render call
+    lr_stats acc{};                          // stats of its frames whose counters were reused
+    lr::ErrLog *elog = nullptr;              // device, in the arena
+    uint64_t elog_off = 0;
+    uint32_t next_tag = 0;
+    std::vector<HintKey> tag_keys;           // kTagRing
+    std::vector<lr_tune_rule> rules;
+    // batches
+    std::vector<BatchSlot> slots;
+    uint32_t max_slots = 2;
+    uint64_t slot_stamp = 0;
+    lr::FrameArgs *host_tab = nullptr;       // pinned, kTabRing x kMaxBatch
+    hipEvent_t tab_ev[kTabRing] = {};
+    bool tab_used[kTabRing] = {};
+    uint32_t tab_head = 0;
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
+    std::map<std::vector<uint64_t>, GraphEntry> graphs;
+    uint64_t graph_stamp = 0;
     hipStream_t last_stream = nullptr;
     hipEvent_t ws_free = nullptr;  // recorded after each frame that used ws
     // stage timing: one set of 8 events per frame in a ring
@@ -108,7 +161,6 @@ struct lr_context_s {
     uint32_t ring_head = 0, ring_count = 0;
     bool timing = false;
     bool have_frame = false;
-    uint64_t last_quads = 0;
     std::string err;
     std::mutex mu;
     lr::FrameCounters *host_ctr = nullptr;  // pinned
@@ -146,19 +198,20 @@ uint32_t log2u(uint32_t x)
 
 // Byte layout of a frame workspace.
 struct Plan {
-    uint32_t n, W, H, bin, shift, nbx, nby, nbins, unit_quads, nunits, ntiles, pair_cap, nblk_x, nblk_y,
-        match_bits, qcap_blocks;
+    uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, ntiles, pair_cap, nblk_x, nblk_y,
+        match_bits, qcap_blocks, fb_groups;
     uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_tiles, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
         total;
 };
 
-Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t pair_hint)
+Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, uint32_t pair_hint)
 {
     Plan p{};
     p.n = n;
     p.W = W;
     p.H = H;
     p.bin = bin;
+    p.half = half;
     p.shift = log2u(bin);
     p.nbx = (W + bin - 1) / bin;
     p.nby = (H + bin - 1) / bin;
@@ -191,10 +244,14 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t pair_h
     p.o_count = take((uint64_t)p.nbins * 4);
     p.o_pairs = take((uint64_t)p.pair_cap * 4);
     p.qcap_blocks = (p.nblk_x * p.nblk_y + lr::kQueues - 1) / lr::kQueues;
+    p.fb_groups = lr::fallback_groups(p.nblk_x * p.nblk_y);
     p.o_fb = take((uint64_t)lr::kQueues * p.qcap_blocks * 64 * 4);
-    p.o_ecode = take((uint64_t)lr::kRasterWaves * p.pair_cap * 4);
-    p.o_emask = take((uint64_t)lr::kRasterWaves * p.pair_cap * 8);
-    p.o_eid = take((uint64_t)lr::kRasterWaves * p.pair_cap * 4);
+    // block entries: a region per (bin, wave) as long as the bin list, twice
+    // that with half-blocks
+    const uint64_t ents = (uint64_t)lr::kRasterWaves * p.pair_cap * (half ? 2 : 1);
+    p.o_ecode = take(ents * 4);
+    p.o_emask = take(ents * 8);
+    p.o_eid = take(ents * 4);
     p.o_ctr = take(sizeof(lr::FrameCounters));
     p.total = o;
     return p;
@@ -241,8 +298,18 @@ struct DebugOut {
     uint32_t cap = 0;
 };
 
-lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t W, uint32_t H,
-                     uint8_t *out, uint32_t bin, lr::FrameArgs &a, Plan &plan)
+uint32_t pair_hint(lr_context ctx, lr_scene scene, uint32_t W, uint32_t H, uint32_t bin)
+{
+    auto it = ctx->pair_hints.find(HintKey(scene, W, H, bin));
+    return it == ctx->pair_hints.end() ? 0u : it->second;
+}
+
+bool valid_k(uint32_t k) { return lr::sorter_depth_supported((int)k); }
+bool valid_block_h(uint32_t b) { return b == 4 || b == 8; }
+
+// Checks shared by every render entry point; fills the plan.
+lr_status check_frame(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t W, uint32_t H,
+                      const Tune &t, Plan &plan)
 {
     auto it = ctx->scenes.find(scene);
     if (it == ctx->scenes.end())
@@ -251,19 +318,23 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
         return fail(ctx, LR_ERR_INVALID_ARG, "camera is NULL");
     if (W < 1 || H < 1 || W > 16384 || H > 16384)
         return fail(ctx, LR_ERR_INVALID_ARG, "width and height must be in [1, 16384]");
-    if (!valid_bin(bin))
+    if (!valid_bin(t.bin))
         return fail(ctx, LR_ERR_INVALID_ARG, "bin size must be 16, 32 or 64");
+    if (!valid_k(t.k))
+        return fail(ctx, LR_ERR_INVALID_ARG, "sorter depth must be one of 2, 4, 8, 12, 16, 24, 32");
     if (!std::isfinite(cam->fov_y) || !(cam->fov_y > 0.0f) || !(cam->fov_y < 3.14159f))
         return fail(ctx, LR_ERR_INVALID_ARG, "fov_y must be in (0, pi)");
-    const SceneRec &sc = it->second;
-    plan = make_plan(sc.n, W, H, bin, ctx->pair_hint);
+    plan = make_plan(it->second.n, W, H, t.bin, t.half, pair_hint(ctx, scene, W, H, t.bin));
     if (plan.nbins > kMaxBins)
         return fail(ctx, LR_ERR_INVALID_ARG,
                     "too many bins for this frame size (at most 16384; use a larger bin size)");
-    lr_status st = ensure_workspace(ctx, plan.total);
-    if (st != LR_OK)
-        return st;
-    char *base = ctx->arena + ctx->ws.off;
+    return LR_OK;
+}
+
+// Frame arguments for a planned frame whose workspace starts at base.
+void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t *out, const Plan &plan,
+               char *base, lr::FrameArgs &a)
+{
     std::memset(&a, 0, sizeof(a));
     a.v = reinterpret_cast<const float *>(ctx->arena + sc.off);
     a.rgba_in = reinterpret_cast<const uint32_t *>(ctx->arena + sc.off + 48ull * sc.n);
@@ -275,11 +346,11 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
             a.rot[3 * r + c] = cam->rot[r][c];
     a.z_near = cam->z_near;
     // focal length in pixels, on the host
-    a.f = (0.5 * (double)H) / std::tan(0.5 * (double)cam->fov_y);
-    a.cx = 0.5 * (double)W;
-    a.cy = 0.5 * (double)H;
-    a.W = W;
-    a.H = H;
+    a.f = (0.5 * (double)plan.H) / std::tan(0.5 * (double)cam->fov_y);
+    a.cx = 0.5 * (double)plan.W;
+    a.cy = 0.5 * (double)plan.H;
+    a.W = plan.W;
+    a.H = plan.H;
     a.rec = reinterpret_cast<lr::QuadRec *>(base + plan.o_rec);
     a.xy = reinterpret_cast<lr::QuadXY *>(base + plan.o_xy);
     a.bbox = reinterpret_cast<uint2 *>(base + plan.o_bbox);
@@ -298,6 +369,8 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
     a.pairs = reinterpret_cast<uint32_t *>(base + plan.o_pairs);
     a.pair_cap = plan.pair_cap;
     a.match_bits = plan.match_bits;
+    a.half_blocks = plan.half;
+    a.fb_groups = plan.fb_groups;
     a.nblk_x = plan.nblk_x;
     a.nblk_y = plan.nblk_y;
     a.qcap_blocks = plan.qcap_blocks;
@@ -306,9 +379,71 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
     a.ent_mask = reinterpret_cast<unsigned long long *>(base + plan.o_emask);
     a.ent_id = reinterpret_cast<uint32_t *>(base + plan.o_eid);
     a.ctr = reinterpret_cast<lr::FrameCounters *>(base + plan.o_ctr);
+    a.elog = ctx->elog;
     a.out = out;
-    ctx->ws_ctr_off = ctx->ws.off + plan.o_ctr;
+}
+
+// Tags a frame for the error log.
+void tag_frame(lr_context ctx, lr_scene scene, const Plan &plan, lr::FrameArgs &a)
+{
+    a.tag = ctx->next_tag++;
+    ctx->tag_keys[a.tag % kTagRing] = HintKey(scene, plan.W, plan.H, plan.bin);
+}
+
+// A single frame in the context workspace.
+lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t W, uint32_t H,
+                     uint8_t *out, const Tune &t, lr::FrameArgs &a, Plan &plan)
+{
+    lr_status st = check_frame(ctx, scene, cam, W, H, t, plan);
+    if (st != LR_OK)
+        return st;
+    st = ensure_workspace(ctx, plan.total);
+    if (st != LR_OK)
+        return st;
+    fill_args(ctx, ctx->scenes[scene], cam, out, plan, ctx->arena + ctx->ws.off, a);
+    tag_frame(ctx, scene, plan, a);
     return LR_OK;
+}
+
+Tune default_tune(lr_context ctx)
+{
+    return Tune{ctx->cfg.bin_size, ctx->cfg.block_h == 4 ? 1u : 0u, ctx->cfg.sorter_depth};
+}
+
+// Tuning of a request: its own fields, else the first matching rule, else
+// the context defaults.
+Tune resolve_tune(lr_context ctx, const lr_request &r)
+{
+    Tune t = default_tune(ctx);
+    auto sc = ctx->scenes.find(r.scene);
+    const uint64_t px = (uint64_t)r.width * r.height;
+    if (sc != ctx->scenes.end() && px) {
+        const double qpp = (double)sc->second.n / (double)px;
+        for (const lr_tune_rule &u : ctx->rules) {
+            if (px <= u.max_pixels && qpp <= (double)u.max_quads_per_pixel) {
+                t = Tune{u.bin_size, u.block_h == 4 ? 1u : 0u, u.sorter_depth};
+                break;
+            }
+        }
+    }
+    if (r.bin_size)
+        t.bin = r.bin_size;
+    if (r.sorter_depth)
+        t.k = r.sorter_depth;
+    if (r.block_h)
+        t.half = r.block_h == 4 ? 1u : (r.block_h == 8 ? 0u : 2u);  // 2: invalid
+    return t;
+}
+
+// Tuning of a single render: the first matching rule, else the defaults.
+Tune frame_tune(lr_context ctx, lr_scene scene, uint32_t W, uint32_t H)
+{
+    lr_request r;
+    std::memset(&r, 0, sizeof(r));
+    r.scene = scene;
+    r.width = W;
+    r.height = H;
+    return resolve_tune(ctx, r);
 }
 
 hipStream_t pick_stream(lr_context ctx, void *stream)
@@ -326,16 +461,13 @@ lr_status order_after_previous(lr_context ctx, hipStream_t s)
 }
 
 lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t W, uint32_t H,
-                      uint8_t *out, void *stream, int unsorted, const DebugOut *dbg, uint32_t bin,
-                      uint32_t k)
+                      uint8_t *out, void *stream, int unsorted, const DebugOut *dbg, const Tune &t)
 {
     if (!out)
         return fail(ctx, LR_ERR_INVALID_ARG, "output pointer is NULL");
-    if (!lr::sorter_depth_supported((int)k))
-        return fail(ctx, LR_ERR_INVALID_ARG, "sorter depth must be one of 2, 4, 8, 12, 16, 24, 32");
     lr::FrameArgs a;
     Plan plan;
-    lr_status st = build_args(ctx, scene, cam, W, H, out, bin, a, plan);
+    lr_status st = build_args(ctx, scene, cam, W, H, out, t, a, plan);
     if (st != LR_OK)
         return st;
     if (dbg) {
@@ -356,13 +488,14 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
         ctx->ring_head = (ctx->ring_head + 1) % kRing;
         ctx->ring_count = std::min(ctx->ring_count + 1, kRing);
     }
-    hipError_t e = lr::launch_frame(a, (int)k, unsorted, s, ev);
+    hipError_t e = lr::launch_frame(a, (int)t.k, unsorted, s, ev);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "kernel launch");
     LR_HIP(ctx, hipEventRecord(ctx->ws_free, s));
     ctx->last_stream = s;
     ctx->have_frame = true;
-    ctx->last_quads = a.n;
+    ctx->last_frames.assign(1, FrameRef{ctx->ws.off + plan.o_ctr, a.n, -1});
+    std::memset(&ctx->acc, 0, sizeof(ctx->acc));
     return LR_OK;
 }
 
@@ -375,25 +508,261 @@ void stage_times(lr_context ctx, uint32_t slot, float *us)
     us[7] = hipEventElapsedTime(&ms, ev[0], ev[7]) == hipSuccess ? ms * 1000.0f : 0.0f;
 }
 
+// Adds one frame's counters to *sum.
+lr_status add_frame_stats(lr_context ctx, const FrameRef &fr, lr_stats *sum)
+{
+    LR_HIP(ctx, hipMemcpy(ctx->host_ctr, ctx->arena + fr.ctr_off, sizeof(lr::FrameCounters),
+                          hipMemcpyDeviceToHost));
+    const lr::FrameCounters &c = *ctx->host_ctr;
+    unsigned long long v[lr::ST_COUNT] = {};
+    for (uint32_t k = 0; k < lr::kStripes; k++)
+        for (uint32_t i = 0; i < lr::ST_COUNT; i++)
+            v[i] += c.stripe[k].v[i];
+    sum->quads += fr.quads;
+    sum->visible += v[lr::ST_CULL0 + lr::VISIBLE];
+    for (int r = 1; r < 6; r++)
+        sum->culled[r] += v[lr::ST_CULL0 + r];
+    sum->bin_pairs += c.pairs_total;
+    sum->block_entries += v[lr::ST_ENTRIES];
+    sum->fragments += v[lr::ST_FRAGMENTS];
+    for (uint32_t k = 0; k < lr::kQueues; k++) {
+        sum->flagged_pixels += c.stripe[k].flag_n;
+        sum->dense_blocks += c.stripe[k].dense_n;
+    }
+    sum->error_word |= c.error;
+    return LR_OK;
+}
+
+// Waits for the device and reads the error log: every frame since the last
+// clear whose bin lists overflowed raises its capacity hint, and the call
+// reports LR_ERR_CAPACITY.  clear empties the log.
 lr_status sync_impl(lr_context ctx, bool clear)
 {
     LR_HIP(ctx, hipDeviceSynchronize());
-    if (!ctx->have_frame)
+    uint32_t n = 0;
+    LR_HIP(ctx, hipMemcpy(&n, ctx->elog, sizeof(n), hipMemcpyDeviceToHost));
+    if (n == 0)
         return LR_OK;
-    LR_HIP(ctx, hipMemcpy(ctx->host_ctr, ctx->arena + ctx->ws_ctr_off, sizeof(lr::FrameCounters),
-                          hipMemcpyDeviceToHost));
-    const uint32_t err = ctx->host_ctr->error;
-    if (err & lr::kErrPairs) {
-        uint64_t want = (uint64_t)ctx->host_ctr->pairs_total + ctx->host_ctr->pairs_total / 4 + 1024;
-        ctx->pair_hint = (uint32_t)std::min<uint64_t>(want, 0xF0000000ull);
-        if (clear)
-            ctx->host_ctr->error &= ~lr::kErrPairs;
-        return fail(ctx, LR_ERR_CAPACITY,
-                    "bin lists overflowed (" + std::to_string(ctx->host_ctr->pairs_total) +
-                        " pairs); capacity raised, render again");
+    const uint32_t m = std::min(n, lr::kErrLogCap);
+    std::vector<lr::ErrLog::Entry> e(m);
+    LR_HIP(ctx, hipMemcpy(e.data(), ctx->elog->e, m * sizeof(lr::ErrLog::Entry), hipMemcpyDeviceToHost));
+    uint32_t worst = 0;
+    for (const auto &x : e) {
+        const uint64_t want = (uint64_t)x.pairs + x.pairs / 4 + 1024;
+        uint32_t &h = ctx->pair_hints[ctx->tag_keys[x.tag % kTagRing]];
+        h = std::max<uint32_t>(h, (uint32_t)std::min<uint64_t>(want, 0xF0000000ull));
+        worst = std::max(worst, x.pairs);
     }
-    if (err & lr::kErrFallback)
-        return fail(ctx, LR_ERR_CAPACITY, "a pixel had more fragments than the exact per-pixel sort holds");
+    if (clear)
+        LR_HIP(ctx, hipMemset(ctx->elog, 0, sizeof(uint32_t)));
+    return fail(ctx, LR_ERR_CAPACITY,
+                std::to_string(n) + " frame(s) overflowed their bin lists (up to " + std::to_string(worst) +
+                    " pairs); capacity raised, render again");
+}
+
+// ------------------------------------------------------------------ batches
+
+// A slot for a launch group of `bytes` on stream s; the stream is ordered
+// after the slot's previous group.  Sets *slot_out, or fails with
+// LR_ERR_OUT_OF_MEMORY when no slot of that size can be had.
+lr_status acquire_slot(lr_context ctx, hipStream_t s, uint64_t bytes, BatchSlot **slot_out,
+                       std::vector<FrameRef> &call_frames)
+{
+    BatchSlot *pick = nullptr;
+    for (auto &sl : ctx->slots)
+        if (sl.used && sl.last == s)
+            pick = &sl;
+    if (!pick)
+        for (auto &sl : ctx->slots)
+            if (!sl.used || hipEventQuery(sl.done) == hipSuccess) {
+                pick = &sl;
+                break;
+            }
+    if (!pick && ctx->slots.size() < ctx->max_slots) {
+        BatchSlot ns;
+        LR_HIP(ctx, hipEventCreateWithFlags(&ns.done, hipEventDisableTiming));
+        ctx->slots.push_back(ns);
+        pick = &ctx->slots.back();
+    }
+    if (!pick) {
+        pick = &ctx->slots[0];
+        for (auto &sl : ctx->slots)
+            if (sl.stamp < pick->stamp)
+                pick = &sl;
+    }
+    // frames of this call still counted in the slot: fold their statistics in
+    // before the slot is overwritten
+    const int idx = (int)(pick - ctx->slots.data());
+    bool waited = false;
+    for (size_t i = 0; i < call_frames.size();) {
+        if (call_frames[i].slot == idx) {
+            if (!waited)
+                LR_HIP(ctx, hipEventSynchronize(pick->done));
+            waited = true;
+            lr_status st = add_frame_stats(ctx, call_frames[i], &ctx->acc);
+            if (st != LR_OK)
+                return st;
+            call_frames.erase(call_frames.begin() + (long)i);
+        } else {
+            i++;
+        }
+    }
+    if (!pick->valid || pick->bytes < bytes) {
+        if (pick->valid) {
+            if (pick->used)
+                LR_HIP(ctx, hipEventSynchronize(pick->done));
+            ctx->alloc.release(pick->off);
+            pick->valid = false;
+        }
+        uint64_t want = bytes + bytes / 4, off;
+        if (!ctx->alloc.alloc(want, off)) {
+            want = bytes;
+            if (!ctx->alloc.alloc(want, off))
+                return LR_ERR_OUT_OF_MEMORY;
+        }
+        pick->off = off;
+        pick->bytes = want;
+        pick->valid = true;
+    }
+    if (pick->used && pick->last != s)
+        LR_HIP(ctx, hipStreamWaitEvent(s, pick->done, 0));
+    *slot_out = pick;
+    return LR_OK;
+}
+
+constexpr uint64_t kTableBytes = ((uint64_t)lr::kMaxBatch * sizeof(lr::FrameArgs) + 255) & ~uint64_t(255);
+
+uint64_t group_bytes(const std::vector<Plan> &plans, uint32_t i0, uint32_t i1)
+{
+    uint64_t b = kTableBytes;
+    for (uint32_t i = i0; i < i1; i++)
+        b += (plans[i].total + 255) & ~uint64_t(255);
+    return b;
+}
+
+// Launches one group through a cached hipGraph (captured on first use of
+// this launch geometry), or directly.
+lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::FrameArgs *dev, const int *ks,
+                       uint32_t nf, hipStream_t s)
+{
+    if (!ctx->use_graphs) {
+        hipError_t e = lr::launch_batch(host, dev, ks, nf, s);
+        return e == hipSuccess ? LR_OK : hip_fail(ctx, e, "batch launch");
+    }
+    // everything else the kernels read comes from the frame table
+    std::vector<uint64_t> key;
+    key.reserve(2 + 6 * (size_t)nf);
+    key.push_back(reinterpret_cast<uint64_t>(dev));
+    key.push_back(nf);
+    for (uint32_t f = 0; f < nf; f++) {
+        key.push_back(host[f].n);
+        key.push_back(host[f].nunits);
+        key.push_back(host[f].nbins);
+        key.push_back(host[f].ntiles);
+        key.push_back(host[f].fb_groups);
+        key.push_back((uint64_t)ks[f]);
+    }
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 64) {
+            // evict the least recently used; wait so no replay of it is pending
+            auto old = ctx->graphs.begin();
+            for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
+                if (g->second.stamp < old->second.stamp)
+                    old = g;
+            LR_HIP(ctx, hipDeviceSynchronize());
+            (void)hipGraphExecDestroy(old->second.exec);
+            ctx->graphs.erase(old);
+        }
+        hipGraph_t g = nullptr;
+        LR_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = lr::launch_batch(host, dev, ks, nf, ctx->capture_stream);
+        hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return hip_fail(ctx, e != hipSuccess ? e : e2, "batch graph capture");
+        }
+        GraphEntry ge;
+        e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "hipGraphInstantiate");
+        it = ctx->graphs.emplace(key, ge).first;
+    }
+    it->second.stamp = ++ctx->graph_stamp;
+    LR_HIP(ctx, hipGraphLaunch(it->second.exec, s));
+    return LR_OK;
+}
+
+lr_status batch_impl(lr_context ctx, const lr_request *reqs, uint32_t n, hipStream_t s)
+{
+    std::vector<Plan> plans(n);
+    std::vector<Tune> tunes(n);
+    for (uint32_t i = 0; i < n; i++) {
+        const lr_request &r = reqs[i];
+        tunes[i] = resolve_tune(ctx, r);
+        if (tunes[i].half > 1)
+            return fail(ctx, LR_ERR_INVALID_ARG, "block_h must be 4 or 8");
+        if (!r.out_rgba8)
+            return fail(ctx, LR_ERR_INVALID_ARG, "output pointer is NULL");
+        lr_status st = check_frame(ctx, r.scene, &r.camera, r.width, r.height, tunes[i], plans[i]);
+        if (st != LR_OK)
+            return st;
+    }
+    std::vector<FrameRef> frames;
+    frames.reserve(n);
+    std::memset(&ctx->acc, 0, sizeof(ctx->acc));
+    std::vector<int> ks(lr::kMaxBatch);
+    uint32_t i0 = 0;
+    while (i0 < n) {
+        uint32_t i1 = std::min<uint32_t>(n, i0 + lr::kMaxBatch);
+        BatchSlot *slot = nullptr;
+        for (;;) {
+            lr_status st = acquire_slot(ctx, s, group_bytes(plans, i0, i1), &slot, frames);
+            if (st == LR_OK)
+                break;
+            if (st != LR_ERR_OUT_OF_MEMORY)
+                return st;
+            if (i1 - i0 == 1)
+                return fail(ctx, LR_ERR_OUT_OF_MEMORY,
+                            "arena too small for one frame of the batch (" +
+                                std::to_string(group_bytes(plans, i0, i1)) + " bytes)");
+            i1 = i0 + (i1 - i0) / 2;
+        }
+        const uint32_t nf = i1 - i0;
+        // host frame table (pinned ring; waits only if its previous copy is pending)
+        const uint32_t h = ctx->tab_head;
+        ctx->tab_head = (h + 1) % kTabRing;
+        if (ctx->tab_used[h])
+            LR_HIP(ctx, hipEventSynchronize(ctx->tab_ev[h]));
+        lr::FrameArgs *host = ctx->host_tab + (size_t)h * lr::kMaxBatch;
+        char *base = ctx->arena + slot->off;
+        lr::FrameArgs *dev = reinterpret_cast<lr::FrameArgs *>(base);
+        uint64_t o = kTableBytes;
+        for (uint32_t f = 0; f < nf; f++) {
+            const lr_request &r = reqs[i0 + f];
+            const Plan &pl = plans[i0 + f];
+            fill_args(ctx, ctx->scenes[r.scene], &r.camera, r.out_rgba8, pl, base + o, host[f]);
+            tag_frame(ctx, r.scene, pl, host[f]);
+            ks[f] = (int)tunes[i0 + f].k;
+            frames.push_back(FrameRef{slot->off + o + pl.o_ctr, pl.n, (int)(slot - ctx->slots.data())});
+            o += (pl.total + 255) & ~uint64_t(255);
+        }
+        LR_HIP(ctx, hipMemcpyAsync(dev, host, nf * sizeof(lr::FrameArgs), hipMemcpyHostToDevice, s));
+        LR_HIP(ctx, hipEventRecord(ctx->tab_ev[h], s));
+        ctx->tab_used[h] = true;
+        lr_status st = launch_group(ctx, host, dev, ks.data(), nf, s);
+        if (st != LR_OK)
+            return st;
+        LR_HIP(ctx, hipEventRecord(slot->done, s));
+        slot->used = true;
+        slot->last = s;
+        slot->stamp = ++ctx->slot_stamp;
+        i0 = i1;
+    }
+    ctx->last_frames = std::move(frames);
+    ctx->have_frame = n > 0;
     return LR_OK;
 }
 
@@ -435,8 +804,12 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         c.sorter_depth = 8;
     if (!valid_bin(c.bin_size))
         return fail(nullptr, LR_ERR_INVALID_ARG, "bin_size must be 16, 32 or 64");
-    if (c.block_h != 8)
-        return fail(nullptr, LR_ERR_INVALID_ARG, "block_h must be 8 (8x8 blocks)");
+    if (!valid_block_h(c.block_h))
+        return fail(nullptr, LR_ERR_INVALID_ARG, "block_h must be 4 (8x4 half-blocks) or 8 (8x8 blocks)");
+    if (c.batch_slots == 0)
+        c.batch_slots = 2;
+    if (c.batch_slots > 8)
+        return fail(nullptr, LR_ERR_INVALID_ARG, "batch_slots must be at most 8");
     if (!lr::sorter_depth_supported((int)c.sorter_depth))
         return fail(nullptr, LR_ERR_INVALID_ARG, "sorter_depth must be one of 2, 4, 8, 12, 16, 24, 32");
     if (c.arena && c.arena_bytes < (1u << 20))
@@ -474,7 +847,14 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
     }
     ctx->alloc.init(ctx->arena_bytes);
     ctx->timing = (c.flags & LR_FLAG_TIMING) != 0;
+    ctx->use_graphs = (c.flags & LR_FLAG_NO_GRAPH) == 0;
+    ctx->max_slots = c.batch_slots;
     bool ok = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming) == hipSuccess;
+    for (uint32_t i = 0; i < kTabRing; i++)
+        ok = ok && hipEventCreateWithFlags(&ctx->tab_ev[i], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&ctx->host_tab, sizeof(lr::FrameArgs) * lr::kMaxBatch * kTabRing,
+                             hipHostMallocDefault) == hipSuccess;
     if (ctx->timing) {
         ctx->ring.assign((size_t)kRing * 8, nullptr);
         for (auto &ev : ctx->ring)
@@ -487,6 +867,16 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         lr_destroy(ctx);
         return fail(nullptr, LR_ERR_DEVICE, "HIP event or pinned allocation failed");
     }
+    ctx->tag_keys.assign(kTagRing, HintKey(0, 0, 0, 0));
+    if (!ctx->alloc.alloc(sizeof(lr::ErrLog), ctx->elog_off)) {
+        lr_destroy(ctx);
+        return fail(nullptr, LR_ERR_OUT_OF_MEMORY, "arena too small");
+    }
+    ctx->elog = reinterpret_cast<lr::ErrLog *>(ctx->arena + ctx->elog_off);
+    if (hipMemset(ctx->elog, 0, sizeof(lr::ErrLog)) != hipSuccess) {
+        lr_destroy(ctx);
+        return fail(nullptr, LR_ERR_DEVICE, "hipMemset of the error log failed");
+    }
     std::memset(ctx->host_ctr, 0, sizeof(lr::FrameCounters));
     *out = ctx;
     return LR_OK;
@@ -497,6 +887,18 @@ lr_status lr_destroy(lr_context ctx)
     if (!ctx)
         return fail(nullptr, LR_ERR_INVALID_ARG, "context is NULL");
     (void)hipDeviceSynchronize();
+    for (auto &g : ctx->graphs)
+        (void)hipGraphExecDestroy(g.second.exec);
+    for (auto &sl : ctx->slots)
+        if (sl.done)
+            (void)hipEventDestroy(sl.done);
+    for (uint32_t i = 0; i < kTabRing; i++)
+        if (ctx->tab_ev[i])
+            (void)hipEventDestroy(ctx->tab_ev[i]);
+    if (ctx->capture_stream)
+        (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->host_tab)
+        (void)hipHostFree(ctx->host_tab);
     if (ctx->ws_free)
         (void)hipEventDestroy(ctx->ws_free);
     for (auto &e : ctx->ring)
@@ -575,8 +977,7 @@ lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32
     std::unique_lock<std::mutex> lock(ctx->mu, std::try_to_lock);
     if (!lock.owns_lock())
         return fail(ctx, LR_ERR_BUSY, "context in use by another thread");
-    return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, ctx->cfg.bin_size,
-                       ctx->cfg.sorter_depth);
+    return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, frame_tune(ctx, scene, width, height));
 }
 
 lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -599,10 +1000,8 @@ lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, 
     d.ids = order_ids;
     d.cap = order_cap;
     if (!rgba_f32 && !counts && !flagged && !order_ids)
-        return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, ctx->cfg.bin_size,
-                           ctx->cfg.sorter_depth);
-    return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, &d, ctx->cfg.bin_size,
-                       ctx->cfg.sorter_depth);
+        return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, frame_tune(ctx, scene, width, height));
+    return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, &d, frame_tune(ctx, scene, width, height));
 }
 
 lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -616,7 +1015,7 @@ lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *ca
     DebugOut d;
     d.rgba = rgba_f32;
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 1, rgba_f32 ? &d : nullptr,
-                       ctx->cfg.bin_size, ctx->cfg.sorter_depth);
+                       frame_tune(ctx, scene, width, height));
 }
 
 lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, void *stream)
@@ -626,15 +1025,39 @@ lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, vo
     std::unique_lock<std::mutex> lock(ctx->mu, std::try_to_lock);
     if (!lock.owns_lock())
         return fail(ctx, LR_ERR_BUSY, "context in use by another thread");
+    if (n == 0)
+        return LR_OK;
+    return batch_impl(ctx, reqs, n, pick_stream(ctx, stream));
+}
+
+lr_status lr_set_tuning(lr_context ctx, const lr_tune_rule *rules, uint32_t n)
+{
+    if (!ctx || (!rules && n))
+        return fail(ctx, LR_ERR_INVALID_ARG, "NULL argument");
     for (uint32_t i = 0; i < n; i++) {
-        const lr_request &r = reqs[i];
-        uint32_t bin = r.bin_size ? r.bin_size : ctx->cfg.bin_size;
-        uint32_t k = r.sorter_depth ? r.sorter_depth : ctx->cfg.sorter_depth;
-        lr_status st = render_impl(ctx, r.scene, &r.camera, r.width, r.height, r.out_rgba8, stream, 0, nullptr,
-                                   bin, k);
-        if (st != LR_OK)
-            return st;
+        const lr_tune_rule &u = rules[i];
+        if (!u.max_pixels || !valid_bin(u.bin_size) || !valid_block_h(u.block_h) || !valid_k(u.sorter_depth) ||
+            !(u.max_quads_per_pixel > 0.0f))
+            return fail(ctx, LR_ERR_INVALID_ARG, "tuning rule " + std::to_string(i) + " is invalid");
     }
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->rules.assign(rules, rules + n);
+    return LR_OK;
+}
+
+lr_status lr_request_bytes(lr_context ctx, const lr_request *req, uint64_t *bytes)
+{
+    if (!ctx || !req || !bytes)
+        return fail(ctx, LR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    const Tune t = resolve_tune(ctx, *req);
+    if (t.half > 1)
+        return fail(ctx, LR_ERR_INVALID_ARG, "block_h must be 4 or 8");
+    Plan plan;
+    lr_status st = check_frame(ctx, req->scene, &req->camera, req->width, req->height, t, plan);
+    if (st != LR_OK)
+        return st;
+    *bytes = (plan.total + 255) & ~uint64_t(255);
     return LR_OK;
 }
 
@@ -651,27 +1074,16 @@ lr_status lr_get_stats(lr_context ctx, lr_stats *out)
     if (!ctx || !out)
         return fail(ctx, LR_ERR_INVALID_ARG, "NULL argument");
     std::lock_guard<std::mutex> lock(ctx->mu);
-    lr_status st = sync_impl(ctx, false);
     std::memset(out, 0, sizeof(*out));
-    if (!ctx->have_frame)
-        return st;
-    const lr::FrameCounters &c = *ctx->host_ctr;
-    unsigned long long sum[lr::ST_COUNT] = {};
-    for (uint32_t k = 0; k < lr::kStripes; k++)
-        for (uint32_t i = 0; i < lr::ST_COUNT; i++)
-            sum[i] += c.stripe[k].v[i];
-    out->quads = ctx->last_quads;
-    out->visible = sum[lr::ST_CULL0 + lr::VISIBLE];
-    for (int r = 1; r < 6; r++)
-        out->culled[r] = sum[lr::ST_CULL0 + r];
-    out->bin_pairs = c.pairs_total;
-    out->block_entries = sum[lr::ST_ENTRIES];
-    out->fragments = sum[lr::ST_FRAGMENTS];
-    for (uint32_t k = 0; k < lr::kQueues; k++) {
-        out->flagged_pixels += c.stripe[k].flag_n;
-        out->dense_blocks += c.stripe[k].dense_n;
+    lr_status st = sync_impl(ctx, false);
+    if (ctx->have_frame) {
+        *out = ctx->acc;
+        for (const FrameRef &fr : ctx->last_frames) {
+            lr_status s2 = add_frame_stats(ctx, fr, out);
+            if (s2 != LR_OK)
+                return s2;
+        }
     }
-    out->error_word = c.error;
     if (ctx->timing && ctx->ring_count) {
         const uint32_t last = (ctx->ring_head + kRing - 1) % kRing;
         stage_times(ctx, last, out->stage_us);
@@ -705,7 +1117,7 @@ lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, u
     std::lock_guard<std::mutex> lock(ctx->mu);
     lr::FrameArgs a;
     Plan plan;
-    lr_status st = build_args(ctx, scene, cam, width, height, nullptr, ctx->cfg.bin_size, a, plan);
+    lr_status st = build_args(ctx, scene, cam, width, height, nullptr, default_tune(ctx), a, plan);
     if (st != LR_OK)
         return st;
     LR_HIP(ctx, hipDeviceSynchronize());
@@ -755,7 +1167,9 @@ lr_status lr_debug_bins(lr_context ctx, lr_scene scene, const lr_camera *cam, ui
         bin_size = ctx->cfg.bin_size;
     lr::FrameArgs a;
     Plan plan;
-    lr_status st = build_args(ctx, scene, cam, width, height, nullptr, bin_size, a, plan);
+    Tune t = default_tune(ctx);
+    t.bin = bin_size;
+    lr_status st = build_args(ctx, scene, cam, width, height, nullptr, t, a, plan);
     if (st != LR_OK)
         return st;
     LR_HIP(ctx, hipDeviceSynchronize());
@@ -767,11 +1181,8 @@ lr_status lr_debug_bins(lr_context ctx, lr_scene scene, const lr_camera *cam, ui
         *total = c.pairs_total;
     if (counts)
         LR_HIP(ctx, hipMemcpy(counts, a.bin_count, (size_t)a.nbins * 4, hipMemcpyDeviceToHost));
-    if (c.error & lr::kErrPairs) {
-        uint64_t want = (uint64_t)c.pairs_total + c.pairs_total / 4 + 1024;
-        ctx->pair_hint = (uint32_t)std::min<uint64_t>(want, 0xF0000000ull);
-        return fail(ctx, LR_ERR_CAPACITY, "bin lists overflowed; capacity raised, call again");
-    }
+    if (c.error & lr::kErrPairs)
+        return sync_impl(ctx, true);  // raises the capacity hint; call again
     if (ids) {
         if (c.pairs_total > ids_cap)
             return fail(ctx, LR_ERR_CAPACITY, "ids_cap smaller than the number of pairs");

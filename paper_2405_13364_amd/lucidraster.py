@@ -24,9 +24,11 @@ LR_ERR_CAPACITY = -4
 LR_ERR_NOT_FOUND = -5
 LR_ERR_BUSY = -6
 LR_FLAG_TIMING = 1
+LR_FLAG_NO_GRAPH = 2
 
 SORTER_DEPTHS = (2, 4, 8, 12, 16, 24, 32)
 BIN_SIZES = (16, 32, 64)
+BLOCK_HEIGHTS = (4, 8)
 STAGES = ("setup", "bin_count", "bin_scan", "bin_scatter", "raster", "unused", "fallback", "total")
 
 
@@ -45,7 +47,8 @@ class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("stream", ctypes.c_void_p), ("arena", ctypes.c_void_p),
                 ("arena_bytes", ctypes.c_uint64), ("bin_size", ctypes.c_uint32),
                 ("block_h", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("flags", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("batch_slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -60,13 +63,20 @@ class Stats(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_uint64), ("camera", Camera), ("width", ctypes.c_uint32),
                 ("height", ctypes.c_uint32), ("out_rgba8", ctypes.c_void_p),
-                ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32)]
+                ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
+                ("block_h", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class TuneRule(ctypes.Structure):
+    _fields_ = [("max_pixels", ctypes.c_uint32), ("max_quads_per_pixel", ctypes.c_float),
+                ("bin_size", ctypes.c_uint32), ("block_h", ctypes.c_uint32),
+                ("sorter_depth", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 EXPORTS = ["lr_status_string", "lr_last_error", "lr_create", "lr_destroy", "lr_upload_scene",
            "lr_release_scene", "lr_render", "lr_render_debug", "lr_render_unsorted",
-           "lr_render_batch", "lr_sync", "lr_get_stats", "lr_get_stage_times", "lr_debug_setup",
-           "lr_debug_bins"]
+           "lr_render_batch", "lr_set_tuning", "lr_request_bytes", "lr_sync", "lr_get_stats",
+           "lr_get_stage_times", "lr_debug_setup", "lr_debug_bins"]
 
 _lib = None
 
@@ -94,6 +104,8 @@ def load_library(path: str = LIB_PATH):
         "lr_render_debug": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P, P, P, P, P, P, U32],
         "lr_render_unsorted": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P, P],
         "lr_render_batch": [CTX, ctypes.POINTER(Request), U32, P],
+        "lr_set_tuning": [CTX, ctypes.POINTER(TuneRule), U32],
+        "lr_request_bytes": [CTX, ctypes.POINTER(Request), ctypes.POINTER(U64)],
         "lr_sync": [CTX],
         "lr_get_stats": [CTX, ctypes.POINTER(Stats)],
         "lr_get_stage_times": [CTX, U32, P, ctypes.POINTER(U32)],
@@ -133,7 +145,8 @@ class Context:
     """A rendering context on one GPU with a torch-owned device arena."""
 
     def __init__(self, arena_bytes: int = 1 << 30, device: int = 0, bin_size: int = 32,
-                 sorter_depth: int = 8, timing: bool = False, stream=None):
+                 sorter_depth: int = 8, timing: bool = False, stream=None, block_h: int = 8,
+                 batch_slots: int = 2, graphs: bool = True, tuning=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -144,12 +157,15 @@ class Context:
         self.stream = stream
         cfg = Config(device=device, stream=None if stream is None else int(stream.cuda_stream),
                      arena=self.arena.data_ptr(), arena_bytes=int(arena_bytes), bin_size=bin_size,
-                     block_h=8, sorter_depth=sorter_depth, flags=LR_FLAG_TIMING if timing else 0,
-                     hbm_budget_bytes=0)
-        self.bin_size, self.sorter_depth = bin_size, sorter_depth
+                     block_h=block_h, sorter_depth=sorter_depth,
+                     flags=(LR_FLAG_TIMING if timing else 0) | (0 if graphs else LR_FLAG_NO_GRAPH),
+                     hbm_budget_bytes=0, batch_slots=batch_slots)
+        self.bin_size, self.sorter_depth, self.block_h = bin_size, sorter_depth, block_h
         h = ctypes.c_void_p()
         self._check(self.lib.lr_create(ctypes.byref(cfg), ctypes.byref(h)), None)
         self.h = h
+        if tuning:
+            self.set_tuning(tuning)
 
     # -- plumbing
     def _check(self, st: int, h=None):
@@ -269,20 +285,55 @@ class Context:
             res["order_ids"] = ids[:total]
         return res
 
+    @staticmethod
+    def _request(req, out_ptr=None) -> Request:
+        """(scene, cam, W, H, out[, bin_size[, sorter_depth[, block_h]]]) -> lr_request;
+        missing or None tuning fields are 0 (tuning rules, then context defaults)."""
+        scene, cam, W, H, out = req[:5]
+        tune = list(req[5:8]) + [None] * (3 - len(req[5:8]))
+        r = Request()
+        r.scene = scene
+        r.camera = camera_struct(cam)
+        r.width, r.height = W, H
+        r.out_rgba8 = out_ptr if out_ptr is not None else (out.data_ptr() if out is not None else None)
+        r.bin_size = tune[0] or 0
+        r.sorter_depth = tune[1] or 0
+        r.block_h = tune[2] or 0
+        return r
+
     def render_batch(self, reqs, stream=None, check: bool = True):
-        """reqs: list of (scene, cam, W, H, out, bin_size, sorter_depth)."""
+        """Render a list of requests (scene, cam, W, H, out[, bin_size, sorter_depth,
+        block_h]) in batched launches.  With check, waits and re-renders once if a
+        capacity was exceeded."""
         arr = (Request * len(reqs))()
         for k, req in enumerate(reqs):
-            scene, cam, W, H, out, bs, kd = req[:7]
-            arr[k].scene = scene
-            arr[k].camera = camera_struct(cam)
-            arr[k].width, arr[k].height = W, H
-            arr[k].out_rgba8 = out.data_ptr()
-            arr[k].bin_size = bs or 0
-            arr[k].sorter_depth = kd or 0
-        self._check(self.lib.lr_render_batch(self.h, arr, len(reqs), self._stream(stream)), self.h)
-        if check:
-            self.sync()
+            arr[k] = self._request(req)
+        for attempt in range(2):
+            self._check(self.lib.lr_render_batch(self.h, arr, len(reqs), self._stream(stream)), self.h)
+            if not check:
+                return
+            st = self.lib.lr_sync(self.h)
+            if st == LR_ERR_CAPACITY and attempt == 0:
+                continue
+            self._check(st, self.h)
+            return
+
+    def set_tuning(self, rules):
+        """Tuning rules: dicts with max_pixels, max_quads_per_pixel, bin_size,
+        block_h, sorter_depth (first match wins)."""
+        arr = (TuneRule * max(len(rules), 1))()
+        for k, u in enumerate(rules):
+            arr[k] = TuneRule(int(u["max_pixels"]), float(u["max_quads_per_pixel"]), int(u["bin_size"]),
+                              int(u["block_h"]), int(u["sorter_depth"]), 0)
+        self._check(self.lib.lr_set_tuning(self.h, arr, len(rules)), self.h)
+
+    def request_bytes(self, scene: int, cam, W: int, H: int, bin_size=None, sorter_depth=None,
+                      block_h=None) -> int:
+        """Device bytes one request holds while in flight (after tuning)."""
+        r = self._request((scene, cam, W, H, None, bin_size, sorter_depth, block_h), out_ptr=0)
+        b = ctypes.c_uint64()
+        self._check(self.lib.lr_request_bytes(self.h, ctypes.byref(r), ctypes.byref(b)), self.h)
+        return int(b.value)
 
     def sync(self):
         self._check(self.lib.lr_sync(self.h), self.h)

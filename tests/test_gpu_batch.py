@@ -1,0 +1,188 @@
+"""GPU: batched rendering (one launch per stage over many frames, replayed
+from captured hipGraphs) against standalone renders and the oracle.
+
+Bar: every frame of a batch is bit-identical to lr_render of the same
+request with the same tuning (bin size, sorter depth, block shape); a few
+frames are also checked against the oracle (RGBA8 within 1 LSB)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13364_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+TUNES = [(16, 8, 8), (32, 8, 8), (64, 8, 8), (32, 4, 4), (16, 32, 4), (32, 12, 8), (64, 24, 4), (32, 2, 8)]
+
+
+@pytest.fixture(scope="module")
+def lr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_13364_amd import lucidraster
+    return lucidraster
+
+
+_singles = {}
+
+
+def single_ctx(lr, tune):
+    if tune not in _singles:
+        b, k, bh = tune
+        _singles[tune] = lr.Context(arena_bytes=256 << 20, bin_size=b, sorter_depth=k, block_h=bh)
+    return _singles[tune]
+
+
+def single_render(lr, sc, cam, tune):
+    ctx = single_ctx(lr, tune)
+    h = ctx.upload(sc.v, sc.rgba)
+    try:
+        return ctx.render(h, cam, sc.width, sc.height).cpu().numpy()
+    finally:
+        ctx.release(h)
+
+
+def mixed_frames(n, seed0=500, max_px=(200, 150)):
+    """Small frames of uneven size, density and recipe."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(n):
+        W = int(rng.integers(1, max_px[0]))
+        H = int(rng.integers(1, max_px[1]))
+        nq = int(rng.integers(1, 4000))
+        gauss = bool(rng.integers(0, 2))
+        out.append(scenes.small(W, H, nq, seed0 + i, side=(1.0, 24.0), gaussian=gauss, alpha=(0.05, 0.8)))
+    return out
+
+
+def run_batch(ctx, frames, tunes, cams=None, stream=None):
+    hs = [ctx.upload(s.v, s.rgba) for s in frames]
+    outs = [ctx.new_image(s.width, s.height) for s in frames]
+    cams = cams or [s.camera for s in frames]
+    reqs = [(h, c, s.width, s.height, o) + tuple(t) for h, c, s, o, t in zip(hs, cams, frames, outs, tunes)]
+    ctx.render_batch(reqs, stream=stream)
+    return hs, outs, reqs
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_mixed_tunings_bit_identical(lr, graphs):
+    ctx = lr.Context(arena_bytes=512 << 20, graphs=graphs)
+    frames = mixed_frames(16)
+    tunes = [TUNES[i % len(TUNES)] for i in range(len(frames))]
+    hs, outs, _ = run_batch(ctx, frames, tunes)
+    for i, (s, o, t) in enumerate(zip(frames, outs, tunes)):
+        np.testing.assert_array_equal(o.cpu().numpy(), single_render(lr, s, s.camera, t), err_msg=f"frame {i} {t}")
+    ctx.close()
+
+
+def test_batch_against_oracle(lr):
+    ctx = lr.Context(arena_bytes=512 << 20)
+    frames = [scenes.small(96, 72, 3000, 41, side=(2, 24)), scenes.scene("c1"),
+              scenes.small(160, 120, 20000, 42, side=(1, 20), gaussian=True, alpha=(0.05, 0.5))]
+    tunes = [(16, 8, 4), (32, 2, 8), (64, 16, 4)]
+    _, outs, _ = run_batch(ctx, frames, tunes)
+    for s, o in zip(frames, outs):
+        ref = oracle.render(s.v, s.rgba, s.camera, s.width, s.height, want_order=False)
+        d = np.abs(o.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32)).max()
+        assert d <= 1, s.name
+    st = ctx.stats()
+    total = 0
+    for s in frames:
+        total += oracle.render(s.v, s.rgba, s.camera, s.width, s.height, want_order=False)["total"]
+    assert st["fragments"] == total
+    ctx.close()
+
+
+def test_graph_replays_with_eager_work_between(lr):
+    """The same batch shape replayed with new cameras; eager renders and
+    synchronisations in between; every replay checked."""
+    import torch
+    ctx = lr.Context(arena_bytes=512 << 20)
+    frames = mixed_frames(6, seed0=700)
+    tunes = [TUNES[i % len(TUNES)] for i in range(len(frames))]
+    hs = [ctx.upload(s.v, s.rgba) for s in frames]
+    outs = [ctx.new_image(s.width, s.height) for s in frames]
+    for rep in range(4):
+        cams = [scenes.Camera.jittered(0.7 * rep - 1.0, 0.4 * rep) for _ in frames]
+        ctx.render_batch([(h, c, s.width, s.height, o) + t for h, c, s, o, t in zip(hs, cams, frames, outs, tunes)])
+        # eager work between replays
+        extra = ctx.render(hs[0], frames[0].camera, frames[0].width, frames[0].height)
+        torch.cuda.synchronize()
+        assert extra.shape[0] == frames[0].height
+        for i, (s, o, t, c) in enumerate(zip(frames, outs, tunes, cams)):
+            np.testing.assert_array_equal(o.cpu().numpy(), single_render(lr, s, c, t), err_msg=f"rep {rep} frame {i}")
+    ctx.close()
+
+
+def test_batch_of_more_than_64_frames(lr):
+    """Several launch groups in one call (and in one workspace slot); the
+    statistics still sum every frame."""
+    ctx = lr.Context(arena_bytes=512 << 20, batch_slots=1)
+    frames = [scenes.small(24 + i % 9, 16 + i % 7, 150 + 7 * i, 900 + i, side=(1, 8)) for i in range(70)]
+    tunes = [TUNES[i % len(TUNES)] for i in range(len(frames))]
+    _, outs, _ = run_batch(ctx, frames, tunes)
+    st = ctx.stats()
+    total = 0
+    for i, (s, o, t) in enumerate(zip(frames, outs, tunes)):
+        np.testing.assert_array_equal(o.cpu().numpy(), single_render(lr, s, s.camera, t), err_msg=f"frame {i}")
+        total += oracle.render(s.v, s.rgba, s.camera, s.width, s.height, want_order=False)["total"]
+    assert st["fragments"] == total
+    ctx.close()
+
+
+def test_batch_capacity_overflow_is_retried(lr):
+    """Quads spanning many 16-pixel bins overflow the first bin-list guess;
+    the batch reports it, raises the capacity and the retry is exact."""
+    ctx = lr.Context(arena_bytes=1 << 30)
+    big = scenes.small(640, 480, 40000, 77, side=(16.0, 32.0), alpha=(0.05, 0.3))
+    frames = [scenes.small(64, 48, 500, 78), big]
+    tunes = [(16, 8, 8), (16, 8, 8)]
+    hs = [ctx.upload(s.v, s.rgba) for s in frames]
+    outs = [ctx.new_image(s.width, s.height) for s in frames]
+    reqs = [(h, s.camera, s.width, s.height, o) + t for h, s, o, t in zip(hs, frames, outs, tunes)]
+    ctx.render_batch(reqs, check=False)
+    with pytest.raises(lr.LRError) as e:
+        ctx.sync()
+    assert e.value.status == lr.LR_ERR_CAPACITY
+    ctx.render_batch(reqs)  # planned with the raised capacity
+    for s, o, t in zip(frames, outs, tunes):
+        np.testing.assert_array_equal(o.cpu().numpy(), single_render(lr, s, s.camera, t))
+    ctx.close()
+
+
+def test_batches_on_two_streams(lr):
+    """Two batches in flight on two streams use two workspace slots."""
+    import torch
+    ctx = lr.Context(arena_bytes=512 << 20, batch_slots=2)
+    fa, fb = mixed_frames(5, seed0=800), mixed_frames(5, seed0=900)
+    ta = [TUNES[i % len(TUNES)] for i in range(5)]
+    tb = [TUNES[(i + 3) % len(TUNES)] for i in range(5)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    _, oa, _ = run_batch(ctx, fa, ta, stream=s1)
+    _, ob, _ = run_batch(ctx, fb, tb, stream=s2)
+    torch.cuda.synchronize()
+    for frames, outs, tunes in ((fa, oa, ta), (fb, ob, tb)):
+        for s, o, t in zip(frames, outs, tunes):
+            np.testing.assert_array_equal(o.cpu().numpy(), single_render(lr, s, s.camera, t))
+    ctx.close()
+
+
+def test_tuning_rules_and_request_bytes(lr):
+    ctx = lr.Context(arena_bytes=512 << 20)
+    sc = scenes.small(128, 96, 4000, 55, side=(2, 20))
+    h = ctx.upload(sc.v, sc.rgba)
+    b8 = ctx.request_bytes(h, sc.camera, sc.width, sc.height, 32, 8, 8)
+    b4 = ctx.request_bytes(h, sc.camera, sc.width, sc.height, 32, 8, 4)
+    assert b4 > b8 > sc.n * 128  # half-blocks double the entry scratch
+    ctx.set_tuning([{"max_pixels": 128 * 96, "max_quads_per_pixel": 1.0, "bin_size": 16, "block_h": 4,
+                     "sorter_depth": 16}])
+    assert ctx.request_bytes(h, sc.camera, sc.width, sc.height) == \
+        ctx.request_bytes(h, sc.camera, sc.width, sc.height, 16, 16, 4)
+    out = ctx.new_image(sc.width, sc.height)
+    ctx.render_batch([(h, sc.camera, sc.width, sc.height, out)])
+    np.testing.assert_array_equal(out.cpu().numpy(), single_render(lr, sc, sc.camera, (16, 16, 4)))
+    with pytest.raises(lr.LRError):
+        ctx.set_tuning([{"max_pixels": 0, "max_quads_per_pixel": 1.0, "bin_size": 16, "block_h": 4,
+                         "sorter_depth": 16}])
+    ctx.close()

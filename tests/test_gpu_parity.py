@@ -30,10 +30,10 @@ def lr():
 _ctx_cache = {}
 
 
-def ctx_for(lr, bin_size=32, k=8, arena=512 << 20):
-    key = (bin_size, k, arena)
+def ctx_for(lr, bin_size=32, k=8, arena=512 << 20, block_h=8):
+    key = (bin_size, k, arena, block_h)
     if key not in _ctx_cache:
-        _ctx_cache[key] = lr.Context(arena_bytes=arena, bin_size=bin_size, sorter_depth=k)
+        _ctx_cache[key] = lr.Context(arena_bytes=arena, bin_size=bin_size, sorter_depth=k, block_h=block_h)
     return _ctx_cache[key]
 
 
@@ -155,21 +155,31 @@ def test_unsorted_parity(lr, name):
 
 
 def test_invariance_over_sorter_depth_and_bins(lr):
-    """Sorter depth, bin size and repetition never change a single bit."""
+    """Sorter depth, bin size, block shape and repetition never change a single bit."""
     sc = SCENES["gauss"]()
     base = gpu_render(lr, ctx_for(lr), sc, order=False)
     b32 = base["rgba_f32"].cpu().numpy()
     b8 = base["rgba8"].cpu().numpy()
     flagged = {}
-    for bin_size in (16, 32, 64):
-        for k in (2, 4, 8, 16, 32):
-            got = gpu_render(lr, ctx_for(lr, bin_size, k), sc, order=False)
-            np.testing.assert_array_equal(got["rgba_f32"].cpu().numpy().view(np.uint32), b32.view(np.uint32),
-                                          err_msg=f"bin {bin_size} K {k}")
-            np.testing.assert_array_equal(got["rgba8"].cpu().numpy(), b8)
-            flagged[(bin_size, k)] = int(got["flagged"].cpu().numpy().sum())
+    for bh in (8, 4):
+        for bin_size in (16, 32, 64):
+            for k in ((2, 4, 8, 16, 32) if bh == 8 else (2, 8, 32)):
+                got = gpu_render(lr, ctx_for(lr, bin_size, k, block_h=bh), sc, order=False)
+                np.testing.assert_array_equal(got["rgba_f32"].cpu().numpy().view(np.uint32),
+                                              b32.view(np.uint32), err_msg=f"bin {bin_size} K {k} block h {bh}")
+                np.testing.assert_array_equal(got["rgba8"].cpu().numpy(), b8)
+                flagged[(bh, bin_size, k)] = int(got["flagged"].cpu().numpy().sum())
     # a shallower sorter sends more pixels down the exact path
-    assert flagged[(32, 2)] >= flagged[(32, 32)]
+    assert flagged[(8, 32, 2)] >= flagged[(8, 32, 32)]
+
+
+@pytest.mark.parametrize("name", ["gauss", "c1", "ragged", "wide"])
+def test_half_block_parity(lr, name):
+    """8x4 half-block sort keys: counts, order and colour against the oracle."""
+    sc = SCENES[name]()
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    got = gpu_render(lr, ctx_for(lr, 32, 8, block_h=4), sc)
+    check_frame(got, ref, f"{name} 8x4")
 
 
 def test_forced_fallback_is_exact(lr):
@@ -196,11 +206,12 @@ def stacked_block_scene(nq, W=64, H=48, seed=5):
     return scenes.from_quads(quads, W, H, name=f"stack{nq}")
 
 
+@pytest.mark.parametrize("bh", [8, 4])
 @pytest.mark.parametrize("nq", [1500, 9000])
-def test_dense_block_paths(lr, nq):
+def test_dense_block_paths(lr, nq, bh):
     sc = stacked_block_scene(nq)
     ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
-    ctx = ctx_for(lr)
+    ctx = ctx_for(lr, block_h=bh)
     got = gpu_render(lr, ctx, sc)
     check_frame(got, ref, f"stack {nq}")
     st = ctx.stats()

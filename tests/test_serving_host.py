@@ -1,0 +1,99 @@
+"""Host policy of the render server on a simulated GPU (no device needed):
+admission by memory budget, continuous batching over stream slots, arrival
+order, and the one-at-a-time baseline."""
+import numpy as np
+import pytest
+
+from paper_2405_13364_amd.serving import Request, Server, SimBackend, poisson_trace, summarize
+
+
+def reqs_at(times, W=64, H=48, scene_of=lambda i: 1):
+    return [Request(i, float(t), scene_of(i), None, W, H) for i, t in enumerate(times)]
+
+
+def inflight_bytes_over_time(log, fp, cost, setup):
+    """Replays the backend log: max bytes in flight at any submit instant."""
+    spans = []
+    for t, slot, rids in log:
+        fin = t + setup + sum(cost[r] for r in rids)
+        spans.append((t, fin, sum(fp[r] for r in rids)))
+    worst = 0
+    for t, _, _ in spans:
+        worst = max(worst, sum(b for s, f, b in spans if s <= t < f))
+    return worst
+
+
+def test_budget_is_never_exceeded():
+    n = 40
+    cost = {i: 1e-3 for i in range(n)}
+    fp = {i: 100 + 10 * (i % 7) for i in range(n)}  # a footprint per scene (i % 7)
+    be = SimBackend(cost, fp)
+    srv = Server(be, budget_bytes=450, slots=3, max_batch=8)
+    done = srv.run(reqs_at([0.0] * n, scene_of=lambda i: i % 7))
+    assert sorted(c.rid for c in done) == list(range(n))
+    assert inflight_bytes_over_time(be.log, fp, cost, be.setup) <= 450
+
+
+def test_batches_fill_free_slots_in_arrival_order():
+    n = 16
+    cost = {i: 1e-3 for i in range(n)}
+    fp = {i: 1 for i in range(n)}
+    be = SimBackend(cost, fp)
+    Server(be, budget_bytes=10**9, slots=2, max_batch=4).run(reqs_at([0.0] * n))
+    order = [r for _, _, rids in be.log for r in rids]
+    assert order == list(range(n))
+    assert all(len(rids) == 4 for _, _, rids in be.log)
+    # the first two batches start together on the two slots
+    assert be.log[0][0] == be.log[1][0] == 0.0 and {be.log[0][1], be.log[1][1]} == {0, 1}
+
+
+def test_late_arrivals_join_a_free_slot_while_another_runs():
+    cost = {0: 10e-3, 1: 1e-3}
+    fp = {0: 1, 1: 1}
+    be = SimBackend(cost, fp)
+    done = Server(be, budget_bytes=100, slots=2, max_batch=4).run(reqs_at([0.0, 2e-3]))
+    by = {c.rid: c for c in done}
+    assert by[1].submit == pytest.approx(2e-3)          # admitted on arrival, not after request 0
+    assert by[1].finish < by[0].finish
+    assert by[0].slot != by[1].slot
+
+
+def test_one_at_a_time_is_sequential():
+    n = 10
+    cost = {i: 1e-3 for i in range(n)}
+    fp = {i: 1 for i in range(n)}
+    be = SimBackend(cost, fp, setup=0.0)
+    done = Server(be, budget_bytes=100, slots=1, max_batch=1).run(reqs_at([0.0] * n))
+    assert all(len(r) == 1 for _, _, r in be.log)
+    fin = sorted(c.finish for c in done)
+    assert fin == pytest.approx([1e-3 * (k + 1) for k in range(n)])
+
+
+def test_batching_beats_one_at_a_time_under_load():
+    """With a fixed per-launch cost, batches amortise it: more frames/s and a
+    lower p99 at the same arrival trace."""
+    rng = np.random.default_rng(0)
+    n = 400
+    times = np.cumsum(rng.exponential(1 / 4000.0, n))
+    cost = {i: 2e-4 for i in range(n)}
+    fp = {i: 1 for i in range(n)}
+    one = summarize(Server(SimBackend(cost, fp, setup=2e-4), 100, slots=1, max_batch=1).run(reqs_at(times)))
+    many = summarize(Server(SimBackend(cost, fp, setup=2e-4), 100, slots=2, max_batch=16).run(reqs_at(times)))
+    assert many["frames_per_s"] > one["frames_per_s"]
+    assert many["p99_ms"] < one["p99_ms"]
+
+
+def test_oversized_request_is_rejected():
+    be = SimBackend({0: 1e-3}, {0: 10**6})
+    with pytest.raises(ValueError):
+        Server(be, budget_bytes=1000).run(reqs_at([0.0]))
+
+
+def test_poisson_trace_is_seeded():
+    meta = [(11, 64, 48), (12, 128, 96)]
+    a = poisson_trace(1000.0, 500, meta, seed=3000)
+    b = poisson_trace(1000.0, 500, meta, seed=3000)
+    assert [(r.arrival, r.scene) for r in a] == [(r.arrival, r.scene) for r in b]
+    rate = len(a) / a[-1].arrival
+    assert 850 < rate < 1150
+    assert {r.scene for r in a} == {11, 12}
