@@ -78,7 +78,8 @@ static_assert(sizeof(StatStripe) == 128, "one line per stripe");
 struct FrameCounters {
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
-    uint32_t pad[30];
+    uint32_t scan_done;        // workgroups of the bin scan that have finished
+    uint32_t pad[29];
     StatStripe stripe[kStripes];
 };
 
@@ -144,6 +145,9 @@ struct FrameArgs {
     unsigned long long *ent_mask;  // 64-sample coverage mask
     uint32_t *ent_id;         // quad index
     FrameCounters *ctr;
+    // single frames: the other of the workspace's two counter sets, zeroed by
+    // this frame's last kernel for the next frame (null: k_frame_begin zeroes ctr)
+    FrameCounters *ctr_next;
     ErrLog *elog;
     uint32_t tag;             // host-assigned frame tag for the error log
     uint8_t *out;             // RGBA8

@@ -420,6 +420,10 @@ __device__ __forceinline__ bool quad_bins(uint2 bb, uint32_t shift, uint32_t &bx
     return true;
 }
 
+// Groups of 64 quads (and of 64 bins) whose loads a binning wave issues
+// together.
+constexpr uint32_t kBinPrefetch = 8;
+
 template <class Src>
 __global__ __launch_bounds__(64) void k_bin_count(Src src)
 {
@@ -432,13 +436,20 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
         s_hist[b] = 0;
     __syncthreads();
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
-    for (uint32_t base = q0; base < q1; base += 64) {
-        uint32_t q = base + lane;
-        if (q < q1) {
+    // bboxes of 8 groups of 64 quads are loaded before any is used
+    for (uint32_t base = q0; base < q1; base += 64 * kBinPrefetch) {
+        uint2 bb[kBinPrefetch];
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const uint32_t q = base + 64 * k + lane;
+            bb[k] = q < q1 ? bbox[q] : make_uint2(0xffffu, 0xffffu);  // (0xffff, 0xffff): no pixel
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
             uint32_t bx0, by0, bw, np;
-            if (quad_bins(bbox[q], a.bin_shift, bx0, by0, bw, np)) {
-                for (uint32_t k = 0; k < np; k++) {
-                    uint32_t by = by0 + k / bw, bx = bx0 + k % bw;
+            if (quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
+                for (uint32_t j = 0; j < np; j++) {
+                    uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
                     atomicAdd(&s_hist[by * a.nbx + bx], 1u);
                 }
             }
@@ -450,45 +461,56 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
         row[b] = s_hist[b];
 }
 
-// Workgroups of the tile scan: ceil(nbins / 64) per tile of 64 units.
-__host__ __device__ __forceinline__ uint32_t scan_groups_x(uint32_t nbins) { return (nbins + 63) / 64; }
-
-// table[u][b] -> exclusive prefix over the units of one tile; tile totals.
-template <class Src>
-__global__ __launch_bounds__(64) void k_bin_scan_tiles(Src src)
+// Workgroups of the bin scan: one per (tile of 64 units, 1024 bins).
+__host__ __device__ __forceinline__ uint32_t scan_groups(uint32_t nbins, uint32_t ntiles)
 {
-    uint32_t blk;
-    const FrameArgs &a = *frame_of(src, blk);
-    const uint32_t gx = scan_groups_x(a.nbins);
-    const uint32_t b = (blk % gx) * 64 + threadIdx.x, tile = blk / gx;
-    if (b >= a.nbins)
-        return;
-    const uint32_t u0 = tile * 64, u1 = min(u0 + 64, a.nunits);
-    uint32_t run = 0;
-    // loads of a group are issued before its stores so they overlap in flight
-    for (uint32_t g = u0; g < u1; g += 16) {
-        uint32_t v[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++)
-            v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if (g + k < u1)
-                a.table[(size_t)(g + k) * a.nbins + b] = run;
-            run += v[k];
-        }
-    }
-    a.tile_sums[(size_t)tile * a.nbins + b] = run;
+    return (nbins + 1023) / 1024 * ntiles;
 }
 
-// Per bin: prefix over tiles and the bin total; then the prefix over bins.
+// Bin scan in one launch.  Each workgroup turns its column segments of
+// table[u][b] (64 units of one tile, 1024 bins) into exclusive prefixes over
+// the tile's units and writes the tile totals; the last workgroup to finish
+// then takes, per bin, the prefix over tiles and the bin total, and the
+// prefix over bins.
 template <class Src>
-__global__ __launch_bounds__(1024) void k_bin_scan_final(Src src)
+__global__ __launch_bounds__(1024) void k_bin_scan(Src src)
 {
     __shared__ uint32_t s_part[1024];
+    __shared__ uint32_t s_ticket;
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
     const uint32_t t = threadIdx.x;
+    const uint32_t gy = (a.nbins + 1023) / 1024;
+    {
+        const uint32_t b = (blk % gy) * 1024 + t, tile = blk / gy;
+        if (b < a.nbins) {
+            const uint32_t u0 = tile * 64, u1 = min(u0 + 64, a.nunits);
+            uint32_t run = 0;
+            // loads of a group are issued before its stores so they overlap in flight
+            for (uint32_t g = u0; g < u1; g += 16) {
+                uint32_t v[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (g + k < u1)
+                        a.table[(size_t)(g + k) * a.nbins + b] = run;
+                    run += v[k];
+                }
+            }
+            a.tile_sums[(size_t)tile * a.nbins + b] = run;
+        }
+    }
+    // the last workgroup to finish sees every tile total
+    __threadfence();
+    __syncthreads();
+    if (t == 0)
+        s_ticket = atomicAdd(&a.ctr->scan_done, 1u);
+    __syncthreads();
+    if (s_ticket != gy * a.ntiles - 1)
+        return;
+    __threadfence();
     const uint32_t per = (a.nbins + 1023) / 1024;
     const uint32_t b0 = min(t * per, a.nbins), b1 = min(b0 + per, a.nbins);
     uint32_t sum = 0;
@@ -532,6 +554,18 @@ __global__ __launch_bounds__(1024) void k_bin_scan_final(Src src)
     }
 }
 
+// Zeroes the next frame's counter set (single frames), spread over the
+// calling kernel's workgroups.
+__device__ __forceinline__ void clear_next_counters(const FrameArgs &a, uint32_t blk, uint32_t nblk)
+{
+    if (!a.ctr_next)
+        return;
+    uint4 *p = reinterpret_cast<uint4 *>(a.ctr_next);
+    const uint32_t n = sizeof(FrameCounters) / 16;
+    for (uint32_t i = blk * blockDim.x + threadIdx.x; i < n; i += nblk * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
 template <class Src>
 __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 {
@@ -544,16 +578,32 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
     const uint32_t lane = threadIdx.x, u = blk;
     const uint32_t *row = a.table + (size_t)u * a.nbins;
     const uint32_t *tsum = a.tile_sums + (size_t)(u >> 6) * a.nbins;
-    for (uint32_t b = lane; b < a.nbins; b += 64)
-        s_off[b] = a.bin_start[b] + tsum[b] + row[b];
+    for (uint32_t b0 = 0; b0 < a.nbins; b0 += 64 * kBinPrefetch) {
+        uint32_t v[kBinPrefetch];
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const uint32_t b = b0 + 64 * k + lane;
+            v[k] = b < a.nbins ? a.bin_start[b] + tsum[b] + row[b] : 0;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const uint32_t b = b0 + 64 * k + lane;
+            if (b < a.nbins)
+                s_off[b] = v[k];
+        }
+    }
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
+    const uint2 none = make_uint2(0xffffu, 0xffffu);
+    uint2 next = q0 + lane < q1 ? bbox[q0 + lane] : none;
     for (uint32_t base = q0; base < q1; base += 64) {
-        uint32_t q = base + lane;
+        const uint32_t q = base + lane;
+        const uint2 cur = next;
+        // the next group's bboxes load while this group is scattered
+        next = q + 64 < q1 ? bbox[q + 64] : none;
         uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
-        if (q < q1)
-            quad_bins(bbox[q], a.bin_shift, bx0, by0, bw, np);
+        quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
         // inclusive prefix of np over the wave
         uint32_t incl = np;
         for (int off = 1; off < 64; off <<= 1) {
@@ -837,20 +887,44 @@ struct Stage {
 // Entries one on-chip sort takes; longer block lists are cut into slices.
 constexpr uint32_t kSortCap = 1024;
 
+// A block with at most kFast entries keeps everything its walk needs on
+// chip: sort keys, masks and each entry's depth plane and colour, in slot
+// order.  These share storage with the sort keys of longer lists (slots at
+// and above kFast overwrite them, which only happens when the block is not
+// on the fast path).
+constexpr uint32_t kFast = 64;
+struct FastEntries {
+    uint32_t key[kFast];                // the first kFast sort keys
+    unsigned long long mask[kFast];
+    Stage st[kFast];
+    uint32_t id[kFast];
+};
+union WaveKeys {
+    uint32_t key[kSortCap];
+    FastEntries f;
+};
+static_assert(sizeof(FastEntries) <= sizeof(uint32_t) * kSortCap, "fast entries alias the key array");
+
 // Per-wave LDS of the sorted raster: candidate batch, sort keys of the
-// current slice (also the slicing histogram), phase-3 staging.
+// current slice (also the slicing histogram) or the fast entries, phase-3
+// staging in sorted order.
 struct WaveLds {
     uint32_t cand[128];
-    uint32_t key[kSortCap];
+    WaveKeys k;
     Stage stage[64];
     uint32_t sid[64];
 };
 
+// A workgroup's window on its bin list: the whole list when it has at most
+// kListCap quads (loaded once for every round of blocks), else one chunk of
+// NW * 64 at a time.
+constexpr uint32_t kListCap = 512;
 template <int NW>
 struct BinChunk {
-    uint32_t q[NW * 64];
-    uint2 bb[NW * 64];
+    uint32_t q[kListCap];
+    uint2 bb[kListCap];
 };
+static_assert(kListCap >= 4 * 64, "a chunk is NW * 64 quads");
 
 struct BlockGeom {
     int px0, py0, px1, py1;  // block pixel rect clipped to the screen
@@ -884,19 +958,22 @@ __device__ __forceinline__ BlockGeom block_geom(const FrameArgs &a, uint32_t bxk
 // workgroup call this together (the chunk loads are shared).
 template <int NW, typename Lds, typename F>
 __device__ void scan_bin(const uint2 *__restrict__ bbox, const uint32_t *__restrict__ pairs, BinChunk<NW> &C,
-                         Lds &L, uint32_t start, uint32_t cnt, const BlockGeom &g, F &&on_batch)
+                         Lds &L, uint32_t start, uint32_t cnt, bool cached, const BlockGeom &g, F &&on_batch)
 {
     const uint32_t tid = threadIdx.x, lane = tid & 63;
     uint32_t nc = 0;
-    for (uint32_t base = 0; base < cnt; base += NW * 64) {
-        const uint32_t t = base + tid;
-        if (t < cnt) {
-            const uint32_t q = pairs[start + t];
-            C.q[tid] = q;
-            C.bb[tid] = bbox[q];
+    const uint32_t step = cached ? cnt : NW * 64;
+    for (uint32_t base = 0; base < cnt; base += step) {
+        if (!cached) {
+            const uint32_t t = base + tid;
+            if (t < cnt) {
+                const uint32_t q = pairs[start + t];
+                C.q[tid] = q;
+                C.bb[tid] = bbox[q];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const uint32_t m = min(cnt - base, (uint32_t)NW * 64);
+        const uint32_t m = min(cnt - base, step);
         if (g.active) {
             for (uint32_t c = 0; c < m; c += 64) {
                 const uint32_t e = c + lane;
@@ -924,13 +1001,27 @@ __device__ void scan_bin(const uint2 *__restrict__ bbox, const uint32_t *__restr
                 }
             }
         }
-        __syncthreads();
+        if (!cached)
+            __syncthreads();
     }
     if (g.active && nc) {
         wave_sync();
         on_batch(nc);
         wave_sync();
     }
+}
+
+// Loads a bin list of at most kListCap quads into the workgroup's window.
+template <int NW>
+__device__ __forceinline__ void load_bin_list(const uint2 *__restrict__ bbox, const uint32_t *__restrict__ pairs,
+                                              BinChunk<NW> &C, uint32_t start, uint32_t cnt)
+{
+    for (uint32_t t = threadIdx.x; t < cnt; t += NW * 64) {
+        const uint32_t q = pairs[start + t];
+        C.q[t] = q;
+        C.bb[t] = bbox[q];
+    }
+    __syncthreads();
 }
 
 // Queue a block's pixels for the exact per-pixel sort (wave-aggregated, on
@@ -1033,13 +1124,25 @@ struct PixelSorter {
 // each keyed at the centroid of its own samples: one sort then orders both
 // 8x4 halves, and a pixel only sees the entries of its half.
 __device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32_t ebase, uint32_t sb,
-                                          uint32_t slot, uint32_t code, uint64_t mask, uint32_t q)
+                                          uint32_t slot, uint32_t code, uint64_t mask, uint32_t q,
+                                          const QuadRec &r)
 {
     a.ent_code[ebase + slot] = code;
     a.ent_mask[ebase + slot] = mask;
     a.ent_id[ebase + slot] = q;
+    if (slot < kFast) {
+        L.k.f.mask[slot] = mask;
+        Stage st;
+        st.A = r.A;
+        st.B = r.B;
+        st.C0 = r.C0;
+        st.ij = (r.bb_i & 0xffffu) | (r.bb_j << 16);
+        st.rgba = r.rgba;
+        L.k.f.st[slot] = st;
+        L.k.f.id[slot] = q;
+    }
     if (slot < kSortCap)
-        L.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
+        L.k.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
 }
 
 __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *__restrict__ rec,
@@ -1049,9 +1152,11 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
 {
     uint64_t m0 = 0, m1 = 0;  // entries: m0 (whole block, or rows 0-3), m1 (rows 4-7)
     uint32_t q = 0, c0 = 0, c1 = 0;
+    const QuadRec *rp = rec;
     if (lane < m) {
         q = L.cand[lane];
-        const QuadRec &r = rec[q];
+        rp = rec + q;
+        const QuadRec &r = *rp;
         const uint64_t mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
         m0 = half ? (mk & 0xFFFFFFFFull) : mk;
         m1 = half ? (mk & ~0xFFFFFFFFull) : 0;
@@ -1064,9 +1169,9 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
     const uint64_t b1 = half ? ballot(m1 != 0) : 0;
     const uint32_t n0 = (uint32_t)__popcll(b0);
     if (m0)
-        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q);
+        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, *rp);
     if (m1)
-        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q);
+        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, *rp);
     uint32_t mn = min(m0 ? c0 : 0xFFFFFFFFu, m1 ? c1 : 0xFFFFFFFFu);
     uint32_t mx = max(m0 ? c0 : 0u, m1 ? c1 : 0u);
     for (int off = 32; off > 0; off >>= 1) {
@@ -1087,12 +1192,12 @@ __device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec
                              uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
 {
     wave_sync();
-    wave_bitonic_sort<uint32_t>(L.key, n, 0xFFFFFFFFu, lane);
+    wave_bitonic_sort<uint32_t>(L.k.key, n, 0xFFFFFFFFu, lane);
     for (uint32_t seg = 0; seg < n; seg += 64) {
         const uint32_t e = seg + lane;
         uint64_t m = 0;
         if (e < n) {
-            const uint32_t slot = ebase + (L.key[e] & ((1u << sb) - 1));
+            const uint32_t slot = ebase + (L.k.key[e] & ((1u << sb) - 1));
             m = a.ent_mask[slot];
             const uint32_t q = a.ent_id[slot];
             const QuadRec &r = rec[q];
@@ -1124,6 +1229,56 @@ __device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec
     }
 }
 
+// Ascending sort of one 32-bit key per lane across the wave (bitonic network
+// over lane indices, exchanges by cross-lane permutes).
+__device__ __forceinline__ uint32_t wave_sort_reg(uint32_t v, uint32_t lane)
+{
+#pragma unroll
+    for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = shfl_xor(v, (int)j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            v = keep_min ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
+
+// Phases 2 and 3 for a block of n <= kFast entries, all on chip: the keys
+// are sorted in registers and each entry's mask, plane and colour come from
+// the fast entries written during phase 1.
+template <int K, bool DEBUG>
+__device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t sb, const BlockGeom &g,
+                          uint32_t lane, PixelSorter<K, DEBUG> &ps)
+{
+    wave_sync();
+    uint32_t key = lane < n ? L.k.f.key[lane] : 0xFFFFFFFFu;
+    key = wave_sort_reg(key, lane);
+    uint64_t m = 0;
+    if (lane < n) {
+        const uint32_t slot = key & ((1u << sb) - 1);
+        m = L.k.f.mask[slot];
+        L.stage[lane] = L.k.f.st[slot];
+        if (DEBUG)
+            L.sid[lane] = L.k.f.id[slot];
+    }
+    wave_sync();
+    uint64_t col = transpose64(m, lane);
+    if (!g.on)
+        col = 0;
+    while (col) {
+        const uint32_t k = (uint32_t)__builtin_ctzll(col);
+        col &= col - 1;
+        const Stage st = L.stage[k];
+        const float kf = frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
+        ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.sid[k] : 0);
+        if (ps.flagged)
+            col = 0;
+    }
+    wave_sync();
+}
+
 // A block with n > kSortCap entries: a 256-bucket histogram of its block
 // keys over [kmin, kmax] splits the key range into slices of at most
 // kSortCap entries (whole buckets, nearest first); each slice is gathered
@@ -1139,7 +1294,7 @@ __device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec,
     const uint32_t span = kmax - kmin;  // < 2^31
     const uint32_t bits = span ? 32 - __builtin_clz(span) : 1;
     const uint32_t hs = bits > 8 ? bits - 8 : 0;  // bucket = (code - kmin) >> hs, in [0, 256)
-    uint32_t *hist = L.key;  // reused: 256 counters, then the slice keys
+    uint32_t *hist = L.k.key;  // reused: 256 counters, then the slice keys
     for (uint32_t b = lane; b < 256; b += 64)
         hist[b] = 0;
     wave_sync();
@@ -1182,7 +1337,7 @@ __device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec,
             }
             const uint64_t bm = ballot(in);
             if (in)
-                L.key[ns + rank_below(bm)] = (((code - lo) >> sh) << sb) | e;
+                L.k.key[ns + rank_below(bm)] = (((code - lo) >> sh) << sb) | e;
             ns += (uint32_t)__popcll(bm);
         }
         walk_entries<K, DEBUG>(a, rec, L, ns, ebase, sb, g, lane, ps);
@@ -1248,19 +1403,27 @@ __global__ __launch_bounds__(kRasterWaves * 64) void k_raster(Src src)
     // entry index bits in a sort key: enough for kSortCap and for ecap
     const uint32_t sb = max(10u, ecap > 1 ? 32 - __builtin_clz(ecap - 1) : 1u);
     WaveLds &L = Lw[wave];
+    const bool cached = cnt <= kListCap;
+    if (cached)
+        load_bin_list<NW>(bbox, pairs, C, start, cnt);
     for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
         const uint32_t k = r0 + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         uint32_t n = 0, kmin = 0xFFFFFFFFu, kmax = 0;
-        scan_bin<NW>(bbox, pairs, C, L, start, cnt, g, [&](uint32_t m) {
+        scan_bin<NW>(bbox, pairs, C, L, start, cnt, cached, g, [&](uint32_t m) {
             sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, half, n, kmin, kmax);
         });
         if (!g.active)
             continue;
-        // entries written by other lanes of this wave are read back below
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         PixelSorter<K, DEBUG> ps;
         ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
+        if (n <= kFast) {
+            walk_fast<K, DEBUG>(a, L, n, sb, g, lane, ps);
+            finish_block<K, DEBUG>(a, g, lane, ps, n);
+            continue;
+        }
+        // entries written by other lanes of this wave are read back below
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         if (n <= kSortCap) {
             walk_entries<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps);
         } else {
@@ -1298,6 +1461,7 @@ __global__ __launch_bounds__(64) void k_fallback(Src src)
     const QuadXY *__restrict__ xyp = a.xy;
     const uint2 *__restrict__ bbox = a.bbox;
     const uint32_t *__restrict__ pairs = a.pairs;
+    clear_next_counters(a, blk, kQueues * a.fb_groups);
     if (a.ctr->error & kErrPairs)
         return;
     const uint32_t lane = threadIdx.x;
@@ -1408,6 +1572,7 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
     const QuadXY *__restrict__ xyp = a.xy;
     const uint2 *__restrict__ bbox = a.bbox;
     const uint32_t *__restrict__ pairs = a.pairs;
+    clear_next_counters(a, bin, a.nbins);
     if (a.ctr->error & kErrPairs)
         return;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1415,12 +1580,15 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
     const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
     const uint32_t bx_bin = (bin % a.nbx) * bpb, by_bin = (bin / a.nbx) * bpb;
     UnsortedLds &U = Uw[wave];
+    const bool cached = cnt <= kListCap;
+    if (cached)
+        load_bin_list<NW>(bbox, pairs, C, start, cnt);
     for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
         const uint32_t k = r0 + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
         uint32_t nfrag = 0, ntot = 0;
-        scan_bin<NW>(bbox, pairs, C, U, start, cnt, g, [&](uint32_t m) {
+        scan_bin<NW>(bbox, pairs, C, U, start, cnt, cached, g, [&](uint32_t m) {
             uint64_t mk = 0;
             if (lane < m) {
                 const uint32_t q = U.cand[lane];
@@ -1485,7 +1653,9 @@ uint32_t fallback_groups(uint32_t nblocks)
 static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEvent_t *ev, bool bins)
 {
     const OneFrame f{a};
-    hipLaunchKernelGGL(k_frame_begin<OneFrame>, dim3(1), dim3(256), 0, s, f);
+    // single frames find their counters zeroed by the previous frame
+    if (!a.ctr_next)
+        hipLaunchKernelGGL(k_frame_begin<OneFrame>, dim3(1), dim3(256), 0, s, f);
     hipLaunchKernelGGL(k_setup<OneFrame>, dim3((a.n + 255) / 256), dim3(256), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[1], s);
@@ -1494,8 +1664,7 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
     hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
         (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_bin_scan_tiles<OneFrame>, dim3(scan_groups_x(a.nbins) * a.ntiles), dim3(64), 0, s, f);
-    hipLaunchKernelGGL(k_bin_scan_final<OneFrame>, dim3(1), dim3(1024), 0, s, f);
+    hipLaunchKernelGGL(k_bin_scan<OneFrame>, dim3(scan_groups(a.nbins, a.ntiles)), dim3(1024), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(k_bin_scatter<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
@@ -1623,9 +1792,8 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     const FrameMap mu = stage_map(dev, nf, [&](uint32_t f) { return host[f].nunits; });
     hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
     const FrameMap mt =
-        stage_map(dev, nf, [&](uint32_t f) { return scan_groups_x(host[f].nbins) * host[f].ntiles; });
-    hipLaunchKernelGGL(k_bin_scan_tiles<FrameMap>, dim3(mt.wg0[nf]), dim3(64), 0, s, mt);
-    hipLaunchKernelGGL(k_bin_scan_final<FrameMap>, dim3(nf), dim3(1024), 0, s, one);
+        stage_map(dev, nf, [&](uint32_t f) { return scan_groups(host[f].nbins, host[f].ntiles); });
+    hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(1024), 0, s, mt);
     hipLaunchKernelGGL(k_bin_scatter<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
     static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
     for (int K : kDepths) {

@@ -134,6 +134,7 @@ struct lr_context_s {
     std::map<lr_scene, SceneRec> scenes;
     lr_scene next_scene = 1;
     Workspace ws;
+    uint32_t ws_set = 0;                     // counter set (0/1) the next single frame uses
     std::map<HintKey, uint32_t> pair_hints;  // bin-list capacity learnt from overflows
     std::vector<FrameRef> last_frames;       // frames of the last render call
     lr_stats acc{};                          // stats of its frames whose counters were reused
@@ -234,6 +235,9 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
         o += (bytes + 255) & ~uint64_t(255);
         return r;
     };
+    // two counter sets first, at the same place for every plan: a single frame
+    // uses one and zeroes the other for the next frame
+    p.o_ctr = take(2 * sizeof(lr::FrameCounters));
     p.o_rec = take((uint64_t)n * sizeof(lr::QuadRec));
     p.o_xy = take((uint64_t)n * sizeof(lr::QuadXY));
     p.o_bbox = take((uint64_t)n * 8);
@@ -252,7 +256,6 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_ecode = take(ents * 4);
     p.o_emask = take(ents * 8);
     p.o_eid = take(ents * 4);
-    p.o_ctr = take(sizeof(lr::FrameCounters));
     p.total = o;
     return p;
 }
@@ -286,6 +289,9 @@ lr_status ensure_workspace(lr_context ctx, uint64_t bytes)
     ctx->ws.off = off;
     ctx->ws.bytes = want;
     ctx->ws.valid = true;
+    // both counter sets start at zero
+    LR_HIP(ctx, hipMemset(ctx->arena + off, 0, 2 * sizeof(lr::FrameCounters)));
+    ctx->ws_set = 0;
     return LR_OK;
 }
 
@@ -400,7 +406,10 @@ lr_status build_args(lr_context ctx, lr_scene scene, const lr_camera *cam, uint3
     st = ensure_workspace(ctx, plan.total);
     if (st != LR_OK)
         return st;
-    fill_args(ctx, ctx->scenes[scene], cam, out, plan, ctx->arena + ctx->ws.off, a);
+    char *base = ctx->arena + ctx->ws.off;
+    fill_args(ctx, ctx->scenes[scene], cam, out, plan, base, a);
+    a.ctr = reinterpret_cast<lr::FrameCounters *>(base + plan.o_ctr) + ctx->ws_set;
+    a.ctr_next = reinterpret_cast<lr::FrameCounters *>(base + plan.o_ctr) + (ctx->ws_set ^ 1u);
     tag_frame(ctx, scene, plan, a);
     return LR_OK;
 }
@@ -494,7 +503,9 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     LR_HIP(ctx, hipEventRecord(ctx->ws_free, s));
     ctx->last_stream = s;
     ctx->have_frame = true;
-    ctx->last_frames.assign(1, FrameRef{ctx->ws.off + plan.o_ctr, a.n, -1});
+    ctx->last_frames.assign(1, FrameRef{ctx->ws.off + plan.o_ctr + ctx->ws_set * sizeof(lr::FrameCounters),
+                                        a.n, -1});
+    ctx->ws_set ^= 1u;
     std::memset(&ctx->acc, 0, sizeof(ctx->acc));
     return LR_OK;
 }
@@ -1123,6 +1134,8 @@ lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, u
     LR_HIP(ctx, hipDeviceSynchronize());
     LR_HIP(ctx, lr::launch_setup_only(a, ctx->stream));
     LR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    // the next frame expects its counter set zeroed
+    LR_HIP(ctx, hipMemset(a.ctr, 0, sizeof(lr::FrameCounters)));
     const uint32_t n = a.n;
     std::vector<lr::QuadRec> rec(n);
     std::vector<lr::QuadXY> xy(n);
@@ -1177,6 +1190,8 @@ lr_status lr_debug_bins(lr_context ctx, lr_scene scene, const lr_camera *cam, ui
     LR_HIP(ctx, hipStreamSynchronize(ctx->stream));
     lr::FrameCounters c;
     LR_HIP(ctx, hipMemcpy(&c, a.ctr, sizeof(c), hipMemcpyDeviceToHost));
+    // the next frame expects its counter set zeroed
+    LR_HIP(ctx, hipMemset(a.ctr, 0, sizeof(lr::FrameCounters)));
     if (total)
         *total = c.pairs_total;
     if (counts)
