@@ -78,8 +78,7 @@ static_assert(sizeof(StatStripe) == 128, "one line per stripe");
 struct FrameCounters {
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
-    uint32_t scan_done;        // workgroups of the bin scan that have finished
-    uint32_t pad[29];
+    uint32_t pad[30];
     StatStripe stripe[kStripes];
 };
 
@@ -124,9 +123,7 @@ struct FrameArgs {
     uint32_t nbx, nby, nbins;
     uint32_t unit_quads;    // quads per binning unit (multiple of 64)
     uint32_t nunits;
-    uint32_t ntiles;        // ceil(nunits / 64)
     uint32_t *table;        // [nunits][nbins]
-    uint32_t *tile_sums;    // [ntiles][nbins]
     uint32_t *bin_start;    // [nbins + 1]
     uint32_t *bin_count;    // [nbins]
     uint32_t *pairs;        // [pair_cap]

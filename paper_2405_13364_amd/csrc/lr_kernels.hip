@@ -84,6 +84,15 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t m, uint32_t lane)
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// Orders LDS accesses among the lanes of one wave (a wavefront-scope fence:
+// no wait for outstanding global memory operations).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Fragment order code: ascending code = nearer first (the high word of the
 // total order; the quad index is the low word).  k >= +0 always.
 __device__ __forceinline__ float frag_key(double A, double B, double C0, int di, int dj)
@@ -461,94 +470,66 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
         row[b] = s_hist[b];
 }
 
-// Workgroups of the bin scan: one per (tile of 64 units, 1024 bins).
-__host__ __device__ __forceinline__ uint32_t scan_groups(uint32_t nbins, uint32_t ntiles)
-{
-    return (nbins + 1023) / 1024 * ntiles;
-}
+// Workgroups of the bin scan: one per group of 64 bins.
+__host__ __device__ __forceinline__ uint32_t scan_groups(uint32_t nbins) { return (nbins + 63) / 64; }
 
-// Bin scan in one launch.  Each workgroup turns its column segments of
-// table[u][b] (64 units of one tile, 1024 bins) into exclusive prefixes over
-// the tile's units and writes the tile totals; the last workgroup to finish
-// then takes, per bin, the prefix over tiles and the bin total, and the
-// prefix over bins.
+// Bin scan over units.  A workgroup owns 64 bins (one per lane) and walks
+// their whole columns of table[u][b]; its 16 waves split the units.  Pass 1
+// sums each wave's share, the shares' exclusive prefix gives each wave its
+// base, and pass 2 rewrites the column as exclusive prefixes over units; the
+// column total is the bin's count.  (The prefix over bins is taken by the
+// scatter, which needs it first.)
+constexpr uint32_t kScanWaves = 16;
+
 template <class Src>
-__global__ __launch_bounds__(1024) void k_bin_scan(Src src)
+__global__ __launch_bounds__(kScanWaves * 64) void k_bin_scan(Src src)
 {
-    __shared__ uint32_t s_part[1024];
-    __shared__ uint32_t s_ticket;
+    __shared__ uint32_t s_share[kScanWaves][64];
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
-    const uint32_t t = threadIdx.x;
-    const uint32_t gy = (a.nbins + 1023) / 1024;
-    {
-        const uint32_t b = (blk % gy) * 1024 + t, tile = blk / gy;
-        if (b < a.nbins) {
-            const uint32_t u0 = tile * 64, u1 = min(u0 + 64, a.nunits);
-            uint32_t run = 0;
-            // loads of a group are issued before its stores so they overlap in flight
-            for (uint32_t g = u0; g < u1; g += 16) {
-                uint32_t v[16];
+    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const uint32_t b = blk * 64 + lane;
+    const bool on = b < a.nbins;
+    const uint32_t per = (a.nunits + kScanWaves - 1) / kScanWaves;
+    const uint32_t u0 = min(wave * per, a.nunits), u1 = min(u0 + per, a.nunits);
+    uint32_t sum = 0;
+    if (on) {
+        // loads of a group are issued before they are summed
+        for (uint32_t g = u0; g < u1; g += 16) {
+            uint32_t v[16];
 #pragma unroll
-                for (int k = 0; k < 16; k++)
-                    v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+            for (int k = 0; k < 16; k++)
+                v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
 #pragma unroll
-                for (int k = 0; k < 16; k++) {
-                    if (g + k < u1)
-                        a.table[(size_t)(g + k) * a.nbins + b] = run;
-                    run += v[k];
-                }
-            }
-            a.tile_sums[(size_t)tile * a.nbins + b] = run;
+            for (int k = 0; k < 16; k++)
+                sum += v[k];
         }
     }
-    // the last workgroup to finish sees every tile total
-    __threadfence();
+    s_share[wave][lane] = sum;
     __syncthreads();
-    if (t == 0)
-        s_ticket = atomicAdd(&a.ctr->scan_done, 1u);
-    __syncthreads();
-    if (s_ticket != gy * a.ntiles - 1)
-        return;
-    __threadfence();
-    const uint32_t per = (a.nbins + 1023) / 1024;
-    const uint32_t b0 = min(t * per, a.nbins), b1 = min(b0 + per, a.nbins);
-    uint32_t sum = 0;
-    for (uint32_t b = b0; b < b1; b++) {
+    if (wave == 0) {
         uint32_t run = 0;
-        for (uint32_t tile = 0; tile < a.ntiles; tile++) {
-            uint32_t *p = a.tile_sums + (size_t)tile * a.nbins + b;
-            uint32_t v = *p;
-            *p = run;
+        for (uint32_t w = 0; w < kScanWaves; w++) {
+            const uint32_t v = s_share[w][lane];
+            s_share[w][lane] = run;
             run += v;
         }
-        a.bin_count[b] = run;
-        sum += run;
+        if (on)
+            a.bin_count[b] = run;
     }
-    s_part[t] = sum;
     __syncthreads();
-    // inclusive scan of the 1024 per-thread sums (Hillis-Steele)
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        uint32_t v = (t >= off) ? s_part[t - off] : 0;
-        __syncthreads();
-        s_part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = (t == 0) ? 0 : s_part[t - 1];
-    for (uint32_t b = b0; b < b1; b++) {
-        a.bin_start[b] = run;
-        run += a.bin_count[b];
-    }
-    if (t == 1023) {
-        uint32_t total = s_part[1023];
-        a.bin_start[a.nbins] = total;
-        a.ctr->pairs_total = total;
-        if (total > a.pair_cap) {
-            a.ctr->error |= kErrPairs;
-            const uint32_t i = atomicAdd(&a.elog->n, 1u);
-            if (i < kErrLogCap) {
-                a.elog->e[i].tag = a.tag;
-                a.elog->e[i].pairs = total;
+    if (on) {
+        uint32_t run = s_share[wave][lane];
+        for (uint32_t g = u0; g < u1; g += 16) {
+            uint32_t v[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++)
+                v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+#pragma unroll
+            for (int k = 0; k < 16; k++) {
+                if (g + k < u1)
+                    a.table[(size_t)(g + k) * a.nbins + b] = run;
+                run += v[k];
             }
         }
     }
@@ -566,42 +547,84 @@ __device__ __forceinline__ void clear_next_counters(const FrameArgs &a, uint32_t
         p[i] = make_uint4(0, 0, 0, 0);
 }
 
+// Quads whose bboxes the scatter stages in LDS at a time: all loads of a
+// group are issued before its stores, so no wait for earlier stores (loads
+// and stores share one completion counter) sits inside the scatter loop.
+constexpr uint32_t kScatterGroup = 512;
+
 template <class Src>
 __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 {
     extern __shared__ uint32_t s_off[];
     __shared__ uint32_t s_pref[64];
     __shared__ uint32_t s_rect[64][3];
+    __shared__ uint2 s_bb[kScatterGroup];
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
     const uint2 *__restrict__ bbox = a.bbox;
     const uint32_t lane = threadIdx.x, u = blk;
     const uint32_t *row = a.table + (size_t)u * a.nbins;
-    const uint32_t *tsum = a.tile_sums + (size_t)(u >> 6) * a.nbins;
+    // every workgroup takes the exclusive prefix over the bin counts itself
+    // (the first one also publishes it as bin_start); its offset in bin b is
+    // that plus its own row of the scanned table
+    uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < a.nbins; b0 += 64 * kBinPrefetch) {
-        uint32_t v[kBinPrefetch];
+        uint32_t c[kBinPrefetch], r[kBinPrefetch];
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
             const uint32_t b = b0 + 64 * k + lane;
-            v[k] = b < a.nbins ? a.bin_start[b] + tsum[b] + row[b] : 0;
+            c[k] = b < a.nbins ? a.bin_count[b] : 0;
+            r[k] = b < a.nbins ? row[b] : 0;
         }
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
             const uint32_t b = b0 + 64 * k + lane;
-            if (b < a.nbins)
-                s_off[b] = v[k];
+            uint32_t incl = c[k];
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
+                if (lane >= (uint32_t)off)
+                    incl += v;
+            }
+            const uint32_t start = carry + incl - c[k];
+            carry += lane_value(incl, 63);
+            if (b < a.nbins) {
+                s_off[b] = start + r[k];
+                if (u == 0)
+                    a.bin_start[b] = start;
+            }
         }
     }
-    __syncthreads();
+    if (u == 0 && lane == 0) {
+        a.bin_start[a.nbins] = carry;
+        a.ctr->pairs_total = carry;
+        if (carry > a.pair_cap) {
+            a.ctr->error |= kErrPairs;
+            const uint32_t i = atomicAdd(&a.elog->n, 1u);
+            if (i < kErrLogCap) {
+                a.elog->e[i].tag = a.tag;
+                a.elog->e[i].pairs = carry;
+            }
+        }
+    }
+    wave_sync();  // one wave per workgroup
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
-    const uint2 none = make_uint2(0xffffu, 0xffffu);
-    uint2 next = q0 + lane < q1 ? bbox[q0 + lane] : none;
+    const uint2 none = make_uint2(0xffffu, 0xffffu);  // no pixel
     for (uint32_t base = q0; base < q1; base += 64) {
         const uint32_t q = base + lane;
-        const uint2 cur = next;
-        // the next group's bboxes load while this group is scattered
-        next = q + 64 < q1 ? bbox[q + 64] : none;
+        if ((base - q0) % kScatterGroup == 0) {
+            uint2 bb[kScatterGroup / 64];
+#pragma unroll
+            for (uint32_t k = 0; k < kScatterGroup / 64; k++) {
+                const uint32_t qq = base + 64 * k + lane;
+                bb[k] = qq < q1 ? bbox[qq] : none;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kScatterGroup / 64; k++)
+                s_bb[64 * k + lane] = bb[k];
+            wave_sync();
+        }
+        const uint2 cur = s_bb[(base - q0) % kScatterGroup + lane];
         uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
         quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
         // inclusive prefix of np over the wave
@@ -616,7 +639,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
         s_rect[lane][0] = bx0;
         s_rect[lane][1] = by0;
         s_rect[lane][2] = bw;
-        __syncthreads();
+        wave_sync();  // one wave per workgroup
         for (uint32_t w = 0; w < total; w += 64) {
             const uint32_t p = w + lane;
             const bool valid = p < total;
@@ -654,7 +677,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
             if (valid && pos < a.pair_cap)
                 a.pairs[pos] = qv;
         }
-        __syncthreads();
+        wave_sync();  // one wave per workgroup
     }
 }
 
@@ -667,13 +690,6 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 // them into batches of 64.  A batch is processed one candidate per lane:
 // gather the quad's record, build its 64-sample coverage mask of the block,
 // keep the non-empty ones.
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Exact coverage of the quad's triangle pair at pixel (px, py) with fp64
 // edge functions (all products stay below 2^50).  For quads wider than
@@ -888,13 +904,15 @@ struct Stage {
 constexpr uint32_t kSortCap = 1024;
 
 // A block with at most kFast entries keeps everything its walk needs on
-// chip: sort keys, masks and each entry's depth plane and colour, in slot
-// order.  These share storage with the sort keys of longer lists (slots at
-// and above kFast overwrite them, which only happens when the block is not
-// on the fast path).
+// chip, in slot order: sort keys, codes, masks and each entry's depth plane
+// and colour; it writes no entry to global memory.  When a block's list
+// grows past kFast, its on-chip entries are copied out once and every later
+// entry goes to global memory; the keys of the longer list then overwrite
+// this storage, which they share.
 constexpr uint32_t kFast = 64;
 struct FastEntries {
     uint32_t key[kFast];                // the first kFast sort keys
+    uint32_t code[kFast];
     unsigned long long mask[kFast];
     Stage st[kFast];
     uint32_t id[kFast];
@@ -1125,12 +1143,14 @@ struct PixelSorter {
 // 8x4 halves, and a pixel only sees the entries of its half.
 __device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32_t ebase, uint32_t sb,
                                           uint32_t slot, uint32_t code, uint64_t mask, uint32_t q,
-                                          const QuadRec &r)
+                                          const QuadRec &r, bool to_global)
 {
-    a.ent_code[ebase + slot] = code;
-    a.ent_mask[ebase + slot] = mask;
-    a.ent_id[ebase + slot] = q;
-    if (slot < kFast) {
+    if (to_global) {
+        a.ent_code[ebase + slot] = code;
+        a.ent_mask[ebase + slot] = mask;
+        a.ent_id[ebase + slot] = q;
+    } else {  // slot < kFast
+        L.k.f.code[slot] = code;
         L.k.f.mask[slot] = mask;
         Stage st;
         st.A = r.A;
@@ -1168,10 +1188,17 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
     const uint64_t b0 = ballot(m0 != 0);
     const uint64_t b1 = half ? ballot(m1 != 0) : 0;
     const uint32_t n0 = (uint32_t)__popcll(b0);
+    const bool to_global = n + n0 + (uint32_t)__popcll(b1) > kFast;
+    if (to_global && n <= kFast && lane < n) {
+        // the list leaves the fast path: copy its on-chip entries out first
+        a.ent_code[ebase + lane] = L.k.f.code[lane];
+        a.ent_mask[ebase + lane] = L.k.f.mask[lane];
+        a.ent_id[ebase + lane] = L.k.f.id[lane];
+    }
     if (m0)
-        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, *rp);
+        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, *rp, to_global);
     if (m1)
-        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, *rp);
+        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, *rp, to_global);
     uint32_t mn = min(m0 ? c0 : 0xFFFFFFFFu, m1 ? c1 : 0xFFFFFFFFu);
     uint32_t mx = max(m0 ? c0 : 0u, m1 ? c1 : 0u);
     for (int off = 32; off > 0; off >>= 1) {
@@ -1346,15 +1373,17 @@ __device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec,
     return true;
 }
 
-// Outputs of a finished block.
+// Outputs of a finished block: the pixel, flagged pixels to the exact
+// queue, and the wave's running statistics.
 template <int K, bool DEBUG>
 __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps,
-                             uint32_t entries)
+                             uint32_t entries, unsigned long long &st_ent, unsigned long long &st_frag)
 {
     if (g.on && !ps.flagged)
         ps.flush(a, g.on);
     push_flagged(a, g.on && ps.flagged, g, lane);
-    if (g.on && !ps.flagged) {
+    const bool write = g.on && !ps.flagged;
+    if (write) {
         reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(ps.R, ps.G, ps.B, 1.0f - ps.T);
         if (DEBUG && a.dbg_rgba)
             reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(ps.R, ps.G, ps.B, 1.0f - ps.T);
@@ -1366,14 +1395,11 @@ __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t la
             a.dbg_flag[g.pix] = ps.flagged ? 1 : 0;
     }
     // statistics (flagged pixels are counted by the exact path)
-    uint32_t wsum = (g.on && !ps.flagged) ? ps.nfrag : 0;
+    uint32_t wsum = write ? ps.nfrag : 0;
     for (int off = 32; off > 0; off >>= 1)
         wsum += shfl_xor(wsum, off);
-    if (lane == 0) {
-        add_stat(a.ctr, ST_ENTRIES, entries);
-        if (wsum)
-            add_stat(a.ctr, ST_FRAGMENTS, wsum);
-    }
+    st_ent += entries;
+    st_frag += wsum;
 }
 
 // Sorted raster: one workgroup of kRasterWaves waves per bin, one 8x8 block
@@ -1406,37 +1432,44 @@ __global__ __launch_bounds__(kRasterWaves * 64) void k_raster(Src src)
     const bool cached = cnt <= kListCap;
     if (cached)
         load_bin_list<NW>(bbox, pairs, C, start, cnt);
-    for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
-        const uint32_t k = r0 + wave;
+    unsigned long long st_ent = 0, st_frag = 0;
+    const uint32_t nrounds = (nb + NW - 1) / NW;
+    for (uint32_t ri = 0; ri < nrounds; ri++) {
+        const uint32_t k = ri * NW + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         uint32_t n = 0, kmin = 0xFFFFFFFFu, kmax = 0;
         scan_bin<NW>(bbox, pairs, C, L, start, cnt, cached, g, [&](uint32_t m) {
             sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, half, n, kmin, kmax);
         });
-        if (!g.active)
-            continue;
-        PixelSorter<K, DEBUG> ps;
-        ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
-        if (n <= kFast) {
-            walk_fast<K, DEBUG>(a, L, n, sb, g, lane, ps);
-            finish_block<K, DEBUG>(a, g, lane, ps, n);
-            continue;
-        }
-        // entries written by other lanes of this wave are read back below
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        if (n <= kSortCap) {
-            walk_entries<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps);
-        } else {
-            if (lane == 0)
-                atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
-            if (!walk_sliced<K, DEBUG>(a, rec, L, n, ebase, sb, kmin, kmax, g, lane, ps)) {
-                // no slice fits: the exact path takes the block
-                ps.flagged = true;
-                if (lane == 0)
-                    atomicOr(&a.ctr->error, kErrDense);
+        if (g.active) {
+            PixelSorter<K, DEBUG> ps;
+            ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
+            if (n <= kFast) {
+                walk_fast<K, DEBUG>(a, L, n, sb, g, lane, ps);
+            } else {
+                // entries written by other lanes of this wave are read back below
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                if (n <= kSortCap) {
+                    walk_entries<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps);
+                } else {
+                    if (lane == 0)
+                        atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
+                    if (!walk_sliced<K, DEBUG>(a, rec, L, n, ebase, sb, kmin, kmax, g, lane, ps)) {
+                        // no slice fits: the exact path takes the block
+                        ps.flagged = true;
+                        if (lane == 0)
+                            atomicOr(&a.ctr->error, kErrDense);
+                    }
+                }
             }
+            finish_block<K, DEBUG>(a, g, lane, ps, n, st_ent, st_frag);
         }
-        finish_block<K, DEBUG>(a, g, lane, ps, n);
+    }
+    if (lane == 0) {
+        if (st_ent)
+            add_stat(a.ctr, ST_ENTRIES, st_ent);
+        if (st_frag)
+            add_stat(a.ctr, ST_FRAGMENTS, st_frag);
     }
 }
 
@@ -1583,8 +1616,10 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
     const bool cached = cnt <= kListCap;
     if (cached)
         load_bin_list<NW>(bbox, pairs, C, start, cnt);
-    for (uint32_t r0 = 0; r0 < nb; r0 += NW) {
-        const uint32_t k = r0 + wave;
+    unsigned long long st_ent = 0, st_frag = 0;
+    const uint32_t nrounds = (nb + NW - 1) / NW;
+    for (uint32_t ri = 0; ri < nrounds; ri++) {
+        const uint32_t k = ri * NW + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
         uint32_t nfrag = 0, ntot = 0;
@@ -1609,24 +1644,28 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
             }
             wave_sync();
         });
-        if (!g.active)
-            continue;
-        if (g.on) {
-            reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(R, G, B, Al);
-            if (DEBUG) {
-                if (a.dbg_rgba)
-                    reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(R, G, B, Al);
-                if (a.dbg_count)
-                    a.dbg_count[g.pix] = nfrag;
+        if (g.active) {
+            if (g.on) {
+                reinterpret_cast<uint32_t *>(a.out)[g.pix] = pack_rgba8(R, G, B, Al);
+                if (DEBUG) {
+                    if (a.dbg_rgba)
+                        reinterpret_cast<float4 *>(a.dbg_rgba)[g.pix] = make_float4(R, G, B, Al);
+                    if (a.dbg_count)
+                        a.dbg_count[g.pix] = nfrag;
+                }
             }
+            uint32_t wsum = nfrag;
+            for (int off = 32; off > 0; off >>= 1)
+                wsum += shfl_xor(wsum, off);
+            st_ent += ntot;
+            st_frag += wsum;
         }
-        uint32_t wsum = nfrag;
-        for (int off = 32; off > 0; off >>= 1)
-            wsum += shfl_xor(wsum, off);
-        if (lane == 0) {
-            add_stat(a.ctr, ST_ENTRIES, ntot);
-            add_stat(a.ctr, ST_FRAGMENTS, wsum);
-        }
+    }
+    if (lane == 0) {
+        if (st_ent)
+            add_stat(a.ctr, ST_ENTRIES, st_ent);
+        if (st_frag)
+            add_stat(a.ctr, ST_FRAGMENTS, st_frag);
     }
 }
 // ---------------------------------------------------------- scene upload
@@ -1664,7 +1703,7 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
     hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
         (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_bin_scan<OneFrame>, dim3(scan_groups(a.nbins, a.ntiles)), dim3(1024), 0, s, f);
+    hipLaunchKernelGGL(k_bin_scan<OneFrame>, dim3(scan_groups(a.nbins)), dim3(kScanWaves * 64), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(k_bin_scatter<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
@@ -1792,8 +1831,8 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     const FrameMap mu = stage_map(dev, nf, [&](uint32_t f) { return host[f].nunits; });
     hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
     const FrameMap mt =
-        stage_map(dev, nf, [&](uint32_t f) { return scan_groups(host[f].nbins, host[f].ntiles); });
-    hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(1024), 0, s, mt);
+        stage_map(dev, nf, [&](uint32_t f) { return scan_groups(host[f].nbins); });
+    hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(kScanWaves * 64), 0, s, mt);
     hipLaunchKernelGGL(k_bin_scatter<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
     static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
     for (int K : kDepths) {

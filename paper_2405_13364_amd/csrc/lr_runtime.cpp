@@ -199,9 +199,9 @@ uint32_t log2u(uint32_t x)
 
 // Byte layout of a frame workspace.
 struct Plan {
-    uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, ntiles, pair_cap, nblk_x, nblk_y,
+    uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks, fb_groups;
-    uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_tiles, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
+    uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
         total;
 };
 
@@ -217,11 +217,10 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.nbx = (W + bin - 1) / bin;
     p.nby = (H + bin - 1) / bin;
     p.nbins = p.nbx * p.nby;
-    // about 1024 binning units, each a multiple of 64 quads, at least 512
-    uint32_t uq = (uint32_t)std::max<uint64_t>(512, (((uint64_t)n + 1023) / 1024 + 63) / 64 * 64);
+    // about 1024 binning units, each a multiple of 64 quads, at least 256
+    uint32_t uq = (uint32_t)std::max<uint64_t>(256, (((uint64_t)n + 1023) / 1024 + 63) / 64 * 64);
     p.unit_quads = uq;
     p.nunits = std::max<uint32_t>(1, (n + uq - 1) / uq);
-    p.ntiles = (p.nunits + 63) / 64;
     // first guess; an overflow is reported and the next frame is planned larger
     uint64_t cap = 5ull * n / 2 + 4ull * p.nbins + 65536;
     cap = std::max<uint64_t>(cap, pair_hint);
@@ -243,7 +242,6 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_bbox = take((uint64_t)n * 8);
     p.o_cull = take((uint64_t)n);
     p.o_table = take((uint64_t)p.nunits * p.nbins * 4);
-    p.o_tiles = take((uint64_t)p.ntiles * p.nbins * 4);
     p.o_start = take(((uint64_t)p.nbins + 1) * 4);
     p.o_count = take((uint64_t)p.nbins * 4);
     p.o_pairs = take((uint64_t)p.pair_cap * 4);
@@ -367,9 +365,7 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
     a.nbins = plan.nbins;
     a.unit_quads = plan.unit_quads;
     a.nunits = plan.nunits;
-    a.ntiles = plan.ntiles;
     a.table = reinterpret_cast<uint32_t *>(base + plan.o_table);
-    a.tile_sums = reinterpret_cast<uint32_t *>(base + plan.o_tiles);
     a.bin_start = reinterpret_cast<uint32_t *>(base + plan.o_start);
     a.bin_count = reinterpret_cast<uint32_t *>(base + plan.o_count);
     a.pairs = reinterpret_cast<uint32_t *>(base + plan.o_pairs);
@@ -669,7 +665,6 @@ lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::Fram
         key.push_back(host[f].n);
         key.push_back(host[f].nunits);
         key.push_back(host[f].nbins);
-        key.push_back(host[f].ntiles);
         key.push_back(host[f].fb_groups);
         key.push_back((uint64_t)ks[f]);
     }
