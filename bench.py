@@ -259,8 +259,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--bin-size", type=int, default=32)
-    ap.add_argument("--sorter-depth", type=int, default=8)
+    ap.add_argument("--bin-size", type=int, default=0, help="0: autotuned (else 32)")
+    ap.add_argument("--sorter-depth", type=int, default=0, help="0: autotuned (else 8)")
+    ap.add_argument("--block-h", type=int, default=0, help="0: autotuned (else 8)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame mixed batch")
@@ -285,8 +286,25 @@ def main():
     log(f"generating workload {args.workload}")
     sc = scenes.scene(args.workload)
     W, H = sc.width, sc.height
+    from paper_2405_13364_amd import autotune
+    rules = autotune.load_rules()
     arena = 2 << 30
-    ctx = lucidraster.Context(arena_bytes=arena, bin_size=args.bin_size, sorter_depth=args.sorter_depth)
+    tuning_note = "fixed"
+    if not (args.bin_size and args.sorter_depth and args.block_h):
+        # online tuning: every (bin, sorter depth, block) timed on this frame
+        log("tuning on the workload frame")
+        tctx = lucidraster.Context(arena_bytes=arena)
+        th_ = tctx.upload(sc.v, sc.rgba)
+        best, ttimes = autotune.tune_frame(tctx, th_, sc.camera, W, H)
+        tctx.close()
+        args.bin_size = args.bin_size or best[0]
+        args.sorter_depth = args.sorter_depth or best[1]
+        args.block_h = args.block_h or best[2]
+        tuning_note = ("online: fastest of %d tunings timed on this frame (rule table pick %s)"
+                       % (len(ttimes), "/".join(map(str, autotune.resolve(rules, W, H, sc.n)))))
+    log(f"tuning: bin {args.bin_size}, sorter depth {args.sorter_depth}, block 8x{args.block_h} ({tuning_note})")
+    ctx = lucidraster.Context(arena_bytes=arena, bin_size=args.bin_size, sorter_depth=args.sorter_depth,
+                              block_h=args.block_h)
     h = ctx.upload(sc.v, sc.rgba)
     out = ctx.new_image(W, H)
     # first frame sizes the workspace (and re-plans bin capacity if needed)
@@ -318,7 +336,7 @@ def main():
     # time between kernels, so the headline above is measured without them)
     log("timing stages")
     ctx_t = lucidraster.Context(arena_bytes=arena, bin_size=args.bin_size, sorter_depth=args.sorter_depth,
-                                timing=True)
+                                block_h=args.block_h, timing=True)
     h_t = ctx_t.upload(sc.v, sc.rgba)
     ctx_t.render(h_t, sc.camera, W, H, out=out)
     time_steps(torch, lambda: ctx_t.render(h_t, sc.camera, W, H, out=out, check=False), args.steps, args.warmup)
@@ -355,7 +373,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "width": W, "height": H,
                    "quads": sc.n, "fragments": int(frags), "bin_size": args.bin_size,
-                   "block": "8x8", "sorter_depth": args.sorter_depth,
+                   "block": f"8x{args.block_h}", "sorter_depth": args.sorter_depth,
+                   "tuning": tuning_note,
                    "arithmetic": "i32 coverage, f64 depth plane, f32 blend"},
         "frames_per_s": round(1000.0 / ms, 2),
         "p50_ms": round(float(np.percentile(per, 50)), 5),
@@ -382,8 +401,6 @@ def main():
     else:
         res["cpu_baseline"] = None
     ctx_t.close()
-    from paper_2405_13364_amd import autotune
-    rules = autotune.load_rules()
     if not args.no_batch:
         log("64-frame mixed batch")
         res["batch"] = mixed_batch_leg(torch, lucidraster, scenes, rules, args.batch_reps, log)

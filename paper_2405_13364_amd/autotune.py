@@ -2,8 +2,10 @@
 
 The sweep renders sample frames of every class (frame size x quads-per-pixel
 bucket), each drawn from the three base workload shapes, under every tuning
-(bin 16/32/64 x 8x8 or 8x4 blocks x sorter depth 8..32), and keeps for each
-class the tuning with the least total GPU time.  The result is a list of
+(bin 16/32/64 x 8x8 or 8x4 blocks x sorter depth 4..32), and keeps for each
+class the tuning with the least mean slowdown over the class's frames (each
+frame's time divided by its own best time, so a dense frame does not decide
+for the light ones).  The result is a list of
 ``lr_tune_rule`` records (first match wins), written as JSON beside this
 module; ``Context(tuning=load_rules())`` installs it.
 
@@ -25,9 +27,9 @@ RULES_PATH = os.path.join(HERE, "tuning.json")
 
 BINS = (16, 32, 64)
 BLOCKS = (8, 4)
-DEPTHS = (8, 12, 16, 24, 32)
+DEPTHS = (4, 8, 12, 16, 24, 32)
 # quads-per-pixel bucket upper bounds and the value sampled in each bucket
-QPP_BUCKETS = ((0.01, 0.005), (0.05, 0.022), (0.2, 0.1), (1.0, 0.45), (1e9, 2.0))
+QPP_BUCKETS = ((0.01, 0.005), (0.05, 0.022), (0.15, 0.08), (0.3, 0.2), (0.6, 0.4), (1.2, 0.8), (1e9, 2.0))
 
 
 def tunings():
@@ -74,23 +76,40 @@ def sweep(resolutions=None, reps: int = 5, log=print) -> Dict[str, object]:
         for qmax, qpp in QPP_BUCKETS:
             frames = sample_frames(W, H, qpp, seed=4000 + W + H)
             hs = [ctx.upload(s.v, s.rgba) for s in frames]
-            cost = {}
+            times = {}
             for tune in tunings():
-                cost[tune] = sum(time_frame(ctx, h, s, tune, reps) for h, s in zip(hs, frames))
+                times[tune] = [time_frame(ctx, h, s, tune, reps) for h, s in zip(hs, frames)]
             for h in hs:
                 ctx.release(h)
-            best = min(cost, key=cost.get)
-            default = cost[(32, 8, 8)]
+            fastest = [min(t[i] for t in times.values()) for i in range(len(frames))]
+            slowdown = {tune: float(np.mean([t[i] / fastest[i] for i in range(len(frames))]))
+                        for tune, t in times.items()}
+            best = min(slowdown, key=slowdown.get)
+            default = (32, 8, 8)
             table.append({"width": W, "height": H, "qpp": qpp, "quads": frames[0].n,
-                          "best": list(best), "best_ms": round(cost[best], 4),
-                          "default_ms": round(default, 4),
-                          "all_ms": {f"{b}/{k}/{bh}": round(v, 4) for (b, k, bh), v in cost.items()}})
+                          "best": list(best), "best_slowdown": round(slowdown[best], 4),
+                          "best_ms": [round(x, 4) for x in times[best]],
+                          "default_ms": [round(x, 4) for x in times[default]],
+                          "fastest_ms": [round(x, 4) for x in fastest]})
             rules.append({"max_pixels": W * H, "max_quads_per_pixel": qmax, "bin_size": best[0],
                           "sorter_depth": best[1], "block_h": best[2]})
             log(f"[autotune] {W}x{H} qpp {qpp}: best bin {best[0]} K {best[1]} block 8x{best[2]} "
-                f"{cost[best]:.3f} ms (bin 32 K 8 8x8: {default:.3f} ms)")
+                f"(mean slowdown {slowdown[best]:.3f}) ms per shape {[round(x, 3) for x in times[best]]}; "
+                f"bin 32 K 8 8x8: {[round(x, 3) for x in times[default]]}")
     ctx.close()
     return {"rules": rules, "sweep": table, "reps": reps, "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def tune_frame(ctx, h, cam, W: int, H: int, reps: int = 10, candidates=None):
+    """Online tuning of one frame: every tuning timed on this very frame (as
+    one-frame batches, median of `reps`); returns the fastest (bin_size,
+    sorter_depth, block_h) and the table of times."""
+    times = {}
+    sc = type("F", (), {"width": W, "height": H, "camera": cam})
+    for tune in candidates or tunings():
+        times[tune] = time_frame(ctx, h, sc, tune, reps)
+    best = min(times, key=times.get)
+    return best, times
 
 
 def load_rules(path: str = RULES_PATH) -> Optional[List[dict]]:
@@ -98,6 +117,16 @@ def load_rules(path: str = RULES_PATH) -> Optional[List[dict]]:
         return None
     with open(path) as fh:
         return json.load(fh)["rules"]
+
+
+def resolve(rules: Optional[List[dict]], W: int, H: int, n: int, default=(32, 8, 8)):
+    """(bin_size, sorter_depth, block_h) the library picks for a frame: the
+    first rule matching its pixel count and quads per pixel."""
+    px = W * H
+    for u in rules or []:
+        if px <= u["max_pixels"] and n / px <= u["max_quads_per_pixel"]:
+            return (u["bin_size"], u["sorter_depth"], u["block_h"])
+    return default
 
 
 def main():

@@ -609,7 +609,6 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
     wave_sync();  // one wave per workgroup
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
-    const uint2 none = make_uint2(0xffffu, 0xffffu);  // no pixel
     for (uint32_t base = q0; base < q1; base += 64) {
         const uint32_t q = base + lane;
         if ((base - q0) % kScatterGroup == 0) {
@@ -617,7 +616,9 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 #pragma unroll
             for (uint32_t k = 0; k < kScatterGroup / 64; k++) {
                 const uint32_t qq = base + 64 * k + lane;
-                bb[k] = qq < q1 ? bbox[qq] : none;
+                bb[k] = make_uint2(0xffffu, 0xffffu);  // no pixel
+                if (qq < q1)
+                    bb[k] = bbox[qq];
             }
 #pragma unroll
             for (uint32_t k = 0; k < kScatterGroup / 64; k++)
@@ -1483,6 +1484,22 @@ __global__ __launch_bounds__(kRasterWaves * 64) void k_raster(Src src)
 // cut), so a round blends the smallest keys left, at least half a buffer.
 
 constexpr uint32_t kFallbackBuf = 4096;
+constexpr uint32_t kFallbackStep = 4;
+
+// The first 112 bytes of a quad record (everything but the fp32 plane) in
+// one go: seven 16-byte loads issued together, so the coverage test and the
+// key wait once per record instead of once per field it branches on.
+__device__ __forceinline__ QuadRec load_rec(const QuadRec *__restrict__ rec, uint32_t q)
+{
+    const uint4 *p = reinterpret_cast<const uint4 *>(rec + q);
+    uint4 d[7];
+#pragma unroll
+    for (int k = 0; k < 7; k++)
+        d[k] = p[k];
+    QuadRec r;
+    __builtin_memcpy(&r, d, sizeof(d));
+    return r;
+}
 
 template <bool DEBUG, class Src>
 __global__ __launch_bounds__(64) void k_fallback(Src src)
@@ -1514,8 +1531,10 @@ __global__ __launch_bounds__(64) void k_fallback(Src src)
             unsigned long long hi = ~0ull;  // the buffer holds every key in (lo, hi]
             bool cut = false;
             uint32_t n = 0, seen = 0;
-            for (uint32_t base = 0; base < cnt; base += 64) {
-                if (n + 64 > kFallbackBuf) {
+            // kFallbackStep chunks of 64 candidates per step: each stage's loads
+            // (list entries, then bboxes, then records) are issued together
+            for (uint32_t base = 0; base < cnt; base += 64 * kFallbackStep) {
+                if (n + 64 * kFallbackStep > kFallbackBuf) {
                     // keep the lower half of the buffer
                     wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
                     n = kFallbackBuf / 2;
@@ -1523,29 +1542,39 @@ __global__ __launch_bounds__(64) void k_fallback(Src src)
                     cut = true;
                     wave_sync();
                 }
-                const uint32_t l = base + lane;
-                bool cov = false;
-                unsigned long long key = 0;
-                if (l < cnt) {
-                    const uint32_t q = pairs[start + l];
-                    const uint2 bb = bbox[q];
-                    if ((int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
-                        (int)(bb.y >> 16) >= j) {
-                        const QuadRec &r = rec[q];
-                        if (pixel_coverage(r, xyp, q, i, j)) {
+                uint32_t q[kFallbackStep];
+                bool ov[kFallbackStep];
+#pragma unroll
+                for (uint32_t c = 0; c < kFallbackStep; c++) {
+                    const uint32_t l = base + 64 * c + lane;
+                    q[c] = l < cnt ? pairs[start + l] : 0xFFFFFFFFu;
+                }
+#pragma unroll
+                for (uint32_t c = 0; c < kFallbackStep; c++) {
+                    const uint2 bb = q[c] != 0xFFFFFFFFu ? bbox[q[c]] : make_uint2(0xffffu, 0u);
+                    ov[c] = (int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
+                            (int)(bb.y >> 16) >= j;
+                }
+#pragma unroll
+                for (uint32_t c = 0; c < kFallbackStep; c++) {
+                    bool cov = false;
+                    unsigned long long key = 0;
+                    if (ov[c]) {
+                        const QuadRec r = load_rec(rec, q[c]);
+                        if (pixel_coverage(r, xyp, q[c], i, j)) {
                             cov = true;
                             const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
                                                       j - (int)(r.bb_j & 0xffffu));
-                            key = ((unsigned long long)order_code(kf) << 32) | q;
+                            key = ((unsigned long long)order_code(kf) << 32) | q[c];
                         }
                     }
+                    seen += (uint32_t)__popcll(ballot(cov));
+                    const bool keep = cov && key > lo && key <= hi;
+                    const uint64_t m = ballot(keep);
+                    if (keep)
+                        s_key[n + rank_below(m)] = key;
+                    n += (uint32_t)__popcll(m);
                 }
-                seen += (uint32_t)__popcll(ballot(cov));
-                const bool keep = cov && key > lo && key <= hi;
-                const uint64_t m = ballot(keep);
-                if (keep)
-                    s_key[n + rank_below(m)] = key;
-                n += (uint32_t)__popcll(m);
                 wave_sync();
             }
             if (total == 0)

@@ -1,0 +1,48 @@
+"""Kernel resources checked on the CPU from the gfx950 assembly: no kernel
+spills to scratch memory, and the raster kernels keep to at most 128 VGPRs
+at the sorter depths the tuner uses for light frames (4 waves per SIMD)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def kernels(tmp_path_factory):
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "paper_2405_13364_amd"))
+    import build as B
+    out = tmp_path_factory.mktemp("isa") / "k.s"
+    cmd = [B.HIPCC, "-x", "hip", "--cuda-device-only", "-S", os.path.join(B.CSRC, "lr_kernels.hip"), "-o", str(out)]
+    cmd += [f for f in B.FLAGS if f != "-fPIC"]
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+    s = out.read_text()
+    res = {}
+    for m in re.finditer(r"\.amdhsa_kernel (\S+)\n(.*?)\.end_amdhsa_kernel", s, re.S):
+        body = m.group(2)
+        res[m.group(1)] = {
+            "scratch": int(re.search(r"private_segment_fixed_size (\d+)", body).group(1)),
+            "vgpr": int(re.search(r"next_free_vgpr (\d+)", body).group(1)),
+            "lds": int(re.search(r"group_segment_fixed_size (\d+)", body).group(1)),
+        }
+    assert len(res) > 20
+    return res
+
+
+def test_no_kernel_uses_scratch(kernels):
+    assert {k: v["scratch"] for k, v in kernels.items() if v["scratch"]} == {}
+
+
+def test_raster_register_budget(kernels):
+    for name, v in kernels.items():
+        if "k_raster" in name and re.search(r"ILi(4|8|12|16)ELb0", name):  # release variants
+            assert v["vgpr"] <= 128, (name, v["vgpr"])
+
+
+def test_lds_fits_four_raster_workgroups(kernels):
+    for name, v in kernels.items():
+        if "k_raster" in name:
+            assert 4 * v["lds"] <= 160 * 1024, (name, v["lds"])
