@@ -552,6 +552,85 @@ __device__ __forceinline__ void clear_next_counters(const FrameArgs &a, uint32_t
 // and stores share one completion counter) sits inside the scatter loop.
 constexpr uint32_t kScatterGroup = 512;
 
+// Scatters the pairs of one group of 64 consecutive quads (lane l holds the
+// bbox of quad base + l) into their bin lists: pair p of the group belongs to
+// the first lane whose inclusive prefix of pair counts exceeds p; lanes whose
+// pairs share a bin take consecutive slots in lane order from one LDS atomic
+// on offs[bin], so every bin list stays in ascending quad order.
+__device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
+                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t lane)
+{
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
+    quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
+    // inclusive prefix of np over the wave
+    uint32_t incl = np;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
+        if (lane >= (uint32_t)off)
+            incl += v;
+    }
+    const uint32_t total = lane_value(incl, 63);
+    s_pref[lane] = incl;
+    s_rect[lane][0] = bx0;
+    s_rect[lane][1] = by0;
+    s_rect[lane][2] = bw;
+    wave_sync();
+    for (uint32_t w = 0; w < total; w += 64) {
+        const uint32_t p = w + lane;
+        const bool valid = p < total;
+        uint32_t bin = 0, qv = 0;
+        if (valid) {
+            // owning quad: first lane whose inclusive prefix exceeds p
+            uint32_t lo = 0, hi = 63;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (s_pref[mid] > p)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            uint32_t k = p - (lo ? s_pref[lo - 1] : 0);
+            uint32_t rbw = s_rect[lo][2];
+            bin = (s_rect[lo][1] + k / rbw) * a.nbx + s_rect[lo][0] + k % rbw;
+            qv = base + lo;
+        }
+        // lanes holding the same bin: AND over the bits of the bin index
+        uint64_t peers = ballot(valid);
+        for (uint32_t bit = 0; bit < a.match_bits; bit++) {
+            const bool set = (bin >> bit) & 1u;
+            const uint64_t bm = ballot(set);
+            peers &= set ? bm : ~bm;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : lane;
+        uint32_t base_off = 0;
+        if (valid && rank == 0)
+            base_off = atomicAdd(&offs[bin], (uint32_t)__popcll(peers));
+        // every lane reads its group leader's base offset
+        const uint32_t pos = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(leader << 2), (int)base_off) + rank;
+        if (valid && pos < a.pair_cap)
+            a.pairs[pos] = qv;
+    }
+    wave_sync();
+}
+
+// Publishes a frame's bin offsets (bin_start) and total, and logs a
+// capacity overflow; done by the first scatter workgroup.
+__device__ __forceinline__ void publish_total(const FrameArgs &a, uint32_t total)
+{
+    a.bin_start[a.nbins] = total;
+    a.ctr->pairs_total = total;
+    if (total > a.pair_cap) {
+        a.ctr->error |= kErrPairs;
+        const uint32_t i = atomicAdd(&a.elog->n, 1u);
+        if (i < kErrLogCap) {
+            a.elog->e[i].tag = a.tag;
+            a.elog->e[i].pairs = total;
+        }
+    }
+}
+
 template <class Src>
 __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 {
@@ -594,20 +673,9 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
             }
         }
     }
-    if (u == 0 && lane == 0) {
-        a.bin_start[a.nbins] = carry;
-        a.ctr->pairs_total = carry;
-        if (carry > a.pair_cap) {
-            a.ctr->error |= kErrPairs;
-            const uint32_t i = atomicAdd(&a.elog->n, 1u);
-            if (i < kErrLogCap) {
-                a.elog->e[i].tag = a.tag;
-                a.elog->e[i].pairs = carry;
-            }
-        }
-    }
+    if (u == 0 && lane == 0)
+        publish_total(a, carry);
     wave_sync();  // one wave per workgroup
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
     for (uint32_t base = q0; base < q1; base += 64) {
         const uint32_t q = base + lane;
@@ -625,60 +693,131 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
                 s_bb[64 * k + lane] = bb[k];
             wave_sync();
         }
-        const uint2 cur = s_bb[(base - q0) % kScatterGroup + lane];
-        uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
-        quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
-        // inclusive prefix of np over the wave
-        uint32_t incl = np;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
-            if (lane >= (uint32_t)off)
-                incl += v;
-        }
-        const uint32_t total = lane_value(incl, 63);
-        s_pref[lane] = incl;
-        s_rect[lane][0] = bx0;
-        s_rect[lane][1] = by0;
-        s_rect[lane][2] = bw;
+        scatter_chunk(a, s_bb[(base - q0) % kScatterGroup + lane], base, s_off, s_pref, s_rect, lane);
         wave_sync();  // one wave per workgroup
-        for (uint32_t w = 0; w < total; w += 64) {
-            const uint32_t p = w + lane;
-            const bool valid = p < total;
-            uint32_t bin = 0, qv = 0;
-            if (valid) {
-                // owning quad: first lane whose inclusive prefix exceeds p
-                uint32_t lo = 0, hi = 63;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (s_pref[mid] > p)
-                        hi = mid;
-                    else
-                        lo = mid + 1;
+    }
+}
+
+
+// Binning with four waves per unit (frames of at most kBin4MaxBins bins).
+// Count: the unit's quads are split over the 256 lanes into one LDS
+// histogram.  Scatter: wave w takes the w-th quarter of the unit and counts
+// it into its own histogram; a per-bin prefix over the four quarters, on
+// top of the bin's start and the unit's scanned table entry, gives each wave
+// its own offsets, so the quarters scatter concurrently and every bin list
+// still comes out in ascending quad order.
+constexpr uint32_t kBin4MaxBins = 4096;
+constexpr uint32_t kBin4Waves = 4;
+
+template <class Src>
+__global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
+{
+    extern __shared__ uint32_t s_hist[];
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t t = threadIdx.x, u = blk;
+    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64)
+        s_hist[b] = 0;
+    __syncthreads();
+    const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
+    for (uint32_t base = q0; base < q1; base += kBin4Waves * 64 * kBinPrefetch) {
+        uint2 bb[kBinPrefetch];
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const uint32_t q = base + kBin4Waves * 64 * k + t;
+            bb[k] = make_uint2(0xffffu, 0xffffu);  // no pixel
+            if (q < q1)
+                bb[k] = bbox[q];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            uint32_t bx0, by0, bw, np;
+            if (quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
+                for (uint32_t j = 0; j < np; j++) {
+                    uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
+                    atomicAdd(&s_hist[by * a.nbx + bx], 1u);
                 }
-                uint32_t k = p - (lo ? s_pref[lo - 1] : 0);
-                uint32_t rbw = s_rect[lo][2];
-                bin = (s_rect[lo][1] + k / rbw) * a.nbx + s_rect[lo][0] + k % rbw;
-                qv = base + lo;
             }
-            // lanes holding the same bin: AND over the bits of the bin index
-            uint64_t peers = ballot(valid);
-            for (uint32_t bit = 0; bit < a.match_bits; bit++) {
-                const bool set = (bin >> bit) & 1u;
-                const uint64_t bm = ballot(set);
-                peers &= set ? bm : ~bm;
-            }
-            const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-            const uint32_t leader = peers ? (uint32_t)__builtin_ctzll(peers) : lane;
-            uint32_t base_off = 0;
-            if (valid && rank == 0)
-                base_off = atomicAdd(&s_off[bin], (uint32_t)__popcll(peers));
-            // every lane reads its group leader's base offset
-            const uint32_t pos =
-                (uint32_t)__builtin_amdgcn_ds_bpermute((int)(leader << 2), (int)base_off) + rank;
-            if (valid && pos < a.pair_cap)
-                a.pairs[pos] = qv;
         }
-        wave_sync();  // one wave per workgroup
+    }
+    __syncthreads();
+    uint32_t *row = a.table + (size_t)u * a.nbins;
+    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64)
+        row[b] = s_hist[b];
+}
+
+template <class Src>
+__global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
+{
+    extern __shared__ uint32_t s_offs[];  // [kBin4Waves][nbins]
+    __shared__ uint32_t s_pref[kBin4Waves][64];
+    __shared__ uint32_t s_rect[kBin4Waves][64][3];
+    __shared__ uint32_t s_part[kBin4Waves * 64];
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    const uint2 *__restrict__ bbox = a.bbox;
+    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63, u = blk;
+    const uint32_t nbins = a.nbins;
+    uint32_t *offs = s_offs + wave * nbins;
+    // this wave's quarter of the unit, in groups of 64 quads
+    const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
+    const uint32_t per = (a.unit_quads / kBin4Waves + 63) / 64 * 64;
+    const uint32_t w0 = min(q0 + wave * per, q1), w1 = min(w0 + per, q1);
+    for (uint32_t b = lane; b < nbins; b += 64)
+        offs[b] = 0;
+    wave_sync();
+    for (uint32_t base = w0; base < w1; base += 64) {
+        const uint32_t q = base + lane;
+        uint2 bb = make_uint2(0xffffu, 0xffffu);
+        if (q < w1)
+            bb = bbox[q];
+        uint32_t bx0, by0, bw, np;
+        if (quad_bins(bb, a.bin_shift, bx0, by0, bw, np)) {
+            for (uint32_t j = 0; j < np; j++) {
+                uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
+                atomicAdd(&offs[by * a.nbx + bx], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    // every workgroup takes the exclusive prefix over the bin counts itself
+    // (the first one also publishes it); thread t owns a contiguous run of bins
+    const uint32_t *row = a.table + (size_t)u * nbins;
+    const uint32_t run_len = (nbins + kBin4Waves * 64 - 1) / (kBin4Waves * 64);
+    const uint32_t b0 = min(t * run_len, nbins), b1 = min(b0 + run_len, nbins);
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; b++)
+        sum += a.bin_count[b];
+    s_part[t] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < kBin4Waves * 64; off <<= 1) {
+        const uint32_t v = t >= off ? s_part[t - off] : 0;
+        __syncthreads();
+        s_part[t] += v;
+        __syncthreads();
+    }
+    uint32_t start = t ? s_part[t - 1] : 0;
+    for (uint32_t b = b0; b < b1; b++) {
+        if (u == 0)
+            a.bin_start[b] = start;
+        uint32_t run = start + row[b];
+        for (uint32_t w = 0; w < kBin4Waves; w++) {
+            const uint32_t c = s_offs[w * nbins + b];
+            s_offs[w * nbins + b] = run;
+            run += c;
+        }
+        start += a.bin_count[b];
+    }
+    if (u == 0 && t == kBin4Waves * 64 - 1)
+        publish_total(a, s_part[t]);
+    __syncthreads();
+    for (uint32_t base = w0; base < w1; base += 64) {
+        const uint32_t q = base + lane;
+        uint2 bb = make_uint2(0xffffu, 0xffffu);
+        if (q < w1)
+            bb = bbox[q];
+        scatter_chunk(a, bb, base, offs, s_pref[wave], s_rect[wave], lane);
     }
 }
 
@@ -1729,13 +1868,20 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
         (void)hipEventRecord(ev[1], s);
     if (!bins)
         return hipGetLastError();
-    hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
+    if (a.bin_waves == kBin4Waves)
+        hipLaunchKernelGGL(k_bin_count4<OneFrame>, dim3(a.nunits), dim3(kBin4Waves * 64), a.nbins * 4, s, f);
+    else
+        hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
         (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_bin_scan<OneFrame>, dim3(scan_groups(a.nbins)), dim3(kScanWaves * 64), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_bin_scatter<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
+    if (a.bin_waves == kBin4Waves)
+        hipLaunchKernelGGL(k_bin_scatter4<OneFrame>, dim3(a.nunits), dim3(kBin4Waves * 64),
+                           kBin4Waves * a.nbins * 4, s, f);
+    else
+        hipLaunchKernelGGL(k_bin_scatter<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
         (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
@@ -1857,12 +2003,27 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     hipLaunchKernelGGL(k_frame_begin<FrameMap>, dim3(nf), dim3(256), 0, s, one);
     const FrameMap ms = stage_map(dev, nf, [&](uint32_t f) { return (host[f].n + 255) / 256; });
     hipLaunchKernelGGL(k_setup<FrameMap>, dim3(ms.wg0[nf]), dim3(256), 0, s, ms);
-    const FrameMap mu = stage_map(dev, nf, [&](uint32_t f) { return host[f].nunits; });
-    hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
+    // binning: frames with few bins use the four-wave kernels (one launch
+    // each over those frames), the others the one-wave kernels
+    uint32_t max_bins4 = 0;
+    for (uint32_t f = 0; f < nf; f++)
+        if (host[f].bin_waves == kBin4Waves)
+            max_bins4 = std::max(max_bins4, host[f].nbins);
+    const FrameMap mu = stage_map(dev, nf, [&](uint32_t f) { return host[f].bin_waves == 1 ? host[f].nunits : 0u; });
+    const FrameMap mu4 =
+        stage_map(dev, nf, [&](uint32_t f) { return host[f].bin_waves == kBin4Waves ? host[f].nunits : 0u; });
+    if (mu.wg0[nf])
+        hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
+    if (mu4.wg0[nf])
+        hipLaunchKernelGGL(k_bin_count4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64), max_bins4 * 4, s, mu4);
     const FrameMap mt =
         stage_map(dev, nf, [&](uint32_t f) { return scan_groups(host[f].nbins); });
     hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(kScanWaves * 64), 0, s, mt);
-    hipLaunchKernelGGL(k_bin_scatter<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
+    if (mu.wg0[nf])
+        hipLaunchKernelGGL(k_bin_scatter<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
+    if (mu4.wg0[nf])
+        hipLaunchKernelGGL(k_bin_scatter4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64),
+                           kBin4Waves * max_bins4 * 4, s, mu4);
     static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
     for (int K : kDepths) {
         bool any = false;

@@ -199,7 +199,7 @@ uint32_t log2u(uint32_t x)
 
 // Byte layout of a frame workspace.
 struct Plan {
-    uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, pair_cap, nblk_x, nblk_y,
+    uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks, fb_groups;
     uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
         total;
@@ -217,8 +217,12 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.nbx = (W + bin - 1) / bin;
     p.nby = (H + bin - 1) / bin;
     p.nbins = p.nbx * p.nby;
-    // about 1024 binning units, each a multiple of 64 quads, at least 256
-    uint32_t uq = (uint32_t)std::max<uint64_t>(256, (((uint64_t)n + 1023) / 1024 + 63) / 64 * 64);
+    // Binning units: with at most 4096 bins, four waves share a unit of at
+    // least 512 quads; otherwise one wave takes a unit of at least 256.
+    // Either way there are about 1024 units at most.
+    p.bin_waves = p.nbins <= 4096 ? 4u : 1u;
+    const uint64_t umin = p.bin_waves == 4 ? 512 : 256;
+    uint32_t uq = (uint32_t)std::max<uint64_t>(umin, (((uint64_t)n + 1023) / 1024 + 255) / 256 * 256);
     p.unit_quads = uq;
     p.nunits = std::max<uint32_t>(1, (n + uq - 1) / uq);
     // first guess; an overflow is reported and the next frame is planned larger
@@ -364,6 +368,7 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
     a.nby = plan.nby;
     a.nbins = plan.nbins;
     a.unit_quads = plan.unit_quads;
+    a.bin_waves = plan.bin_waves;
     a.nunits = plan.nunits;
     a.table = reinterpret_cast<uint32_t *>(base + plan.o_table);
     a.bin_start = reinterpret_cast<uint32_t *>(base + plan.o_start);
