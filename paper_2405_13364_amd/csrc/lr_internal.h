@@ -98,8 +98,21 @@ struct ErrLog {
     } e[kErrLogCap];
 };
 
-// Waves per raster workgroup (one bin, one 8x8 block per wave at a time).
-constexpr uint32_t kRasterWaves = 4;
+// Waves per raster workgroup (one bin, one 8x8 block per wave at a time):
+// 4 for a 16-pixel bin (its 4 blocks in one round), 8 for 32 pixels (2
+// rounds of 16 blocks), 16 for 64 pixels (4 rounds of 64 blocks); measured
+// on the 1280x720 and 1920x1080 workloads.
+__host__ __device__ constexpr uint32_t raster_waves(uint32_t bin_shift)
+{
+    return bin_shift <= 4 ? 4u : (bin_shift == 5 ? 8u : 16u);
+}
+
+// The same for a sorter depth: 16-wave workgroups leave 128 VGPRs per lane,
+// too few for the deeper sorters, which keep 8 waves.
+__host__ __device__ constexpr uint32_t raster_waves_for(uint32_t bin_shift, int sorter_depth)
+{
+    return (raster_waves(bin_shift) == 16 && sorter_depth > 12) ? 8u : raster_waves(bin_shift);
+}
 
 // Everything one frame's kernels need (passed by value).
 struct FrameArgs {
@@ -137,7 +150,8 @@ struct FrameArgs {
     uint32_t qcap_blocks;     // blocks per queue stripe: ceil(nblk_x*nblk_y / kQueues)
     uint32_t *fb_queue;       // flagged pixels [kQueues][qcap_blocks * 64]
     // block entries of the raster stage, per (bin, wave) region of the bin's
-    // length at entry (kRasterWaves * bin_start[bin] + wave * bin_count[bin])
+    // length at entry (NW * bin_start[bin] + wave * bin_count[bin], NW the
+    // raster waves per workgroup)
     // ((1 + half_blocks) times those sizes with half-blocks)
     uint32_t *ent_code;       // block depth code
     unsigned long long *ent_mask;  // 64-sample coverage mask

@@ -266,14 +266,12 @@ __device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, int64_t Rx
     flags |= kConvex;
 }
 
-template <class Src>
-__global__ __launch_bounds__(256) void k_setup(Src src)
+// Setup of quad q (Stage 1): writes its record, snapped vertices, bbox and
+// cull reason; returns the reason (VISIBLE = 0).
+__device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
 {
-    uint32_t blk;
-    const FrameArgs &a = *frame_of(src, blk);
-    const uint32_t q = blk * 256 + threadIdx.x;
     uint32_t reason = 0xff;
-    if (q < a.n) {
+    {
         const uint32_t n = a.n;
         double c[4][3];
         for (int k = 0; k < 4; k++) {
@@ -389,6 +387,23 @@ __global__ __launch_bounds__(256) void k_setup(Src src)
         a.bbox[q] = bb;
         a.cull[q] = (uint8_t)reason;
     }
+    return reason;
+}
+
+// Quads per lane of the setup kernel (each workgroup takes 256 quads).
+constexpr uint32_t kSetupQPL = 1;
+
+template <class Src>
+__global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
+{
+    uint32_t blk;
+    const FrameArgs &a = *frame_of(src, blk);
+    uint32_t reasons[kSetupQPL];
+#pragma unroll
+    for (uint32_t k = 0; k < kSetupQPL; k++) {
+        const uint32_t q = blk * 256 + k * (256 / kSetupQPL) + threadIdx.x;
+        reasons[k] = q < a.n ? setup_quad(a, q) : 0xffu;
+    }
     // cull statistics: one atomic per workgroup and reason, striped
     __shared__ uint32_t s_cull[6];
     if (threadIdx.x < 6)
@@ -396,9 +411,12 @@ __global__ __launch_bounds__(256) void k_setup(Src src)
     __syncthreads();
     const uint32_t lane = lane_id();
     for (uint32_t r = 0; r < 6; r++) {
-        uint64_t m = ballot(reason == r);
-        if (m && lane == 0)
-            atomicAdd(&s_cull[r], (uint32_t)__popcll(m));
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kSetupQPL; k++)
+            c += (uint32_t)__popcll(ballot(reasons[k] == r));
+        if (c && lane == 0)
+            atomicAdd(&s_cull[r], c);
     }
     __syncthreads();
     if (threadIdx.x < 6 && s_cull[threadIdx.x])
@@ -1074,15 +1092,15 @@ struct WaveLds {
 };
 
 // A workgroup's window on its bin list: the whole list when it has at most
-// kListCap quads (loaded once for every round of blocks), else one chunk of
-// NW * 64 at a time.
+// list_cap(NW) quads (loaded once for every round of blocks), else one chunk
+// of NW * 64 at a time.
 constexpr uint32_t kListCap = 512;
+__host__ __device__ constexpr uint32_t list_cap(uint32_t nw) { return nw * 64 > kListCap ? nw * 64 : kListCap; }
 template <int NW>
 struct BinChunk {
-    uint32_t q[kListCap];
-    uint2 bb[kListCap];
+    uint32_t q[list_cap(NW)];
+    uint2 bb[list_cap(NW)];
 };
-static_assert(kListCap >= 4 * 64, "a chunk is NW * 64 quads");
 
 struct BlockGeom {
     int px0, py0, px1, py1;  // block pixel rect clipped to the screen
@@ -1542,12 +1560,11 @@ __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t la
     st_frag += wsum;
 }
 
-// Sorted raster: one workgroup of kRasterWaves waves per bin, one 8x8 block
-// per wave per round (16-pixel bins: 1 round; 32: 4; 64: 16).
-template <int K, bool DEBUG, class Src>
-__global__ __launch_bounds__(kRasterWaves * 64) void k_raster(Src src)
+// Sorted raster: one workgroup of NW waves per bin, one 8x8 block per wave
+// per round.
+template <int K, bool DEBUG, class Src, int NW>
+__global__ __launch_bounds__(NW * 64) void k_raster(Src src)
 {
-    constexpr uint32_t NW = kRasterWaves;
     __shared__ BinChunk<NW> C;
     __shared__ WaveLds Lw[NW];
     uint32_t bin;
@@ -1569,7 +1586,7 @@ __global__ __launch_bounds__(kRasterWaves * 64) void k_raster(Src src)
     // entry index bits in a sort key: enough for kSortCap and for ecap
     const uint32_t sb = max(10u, ecap > 1 ? 32 - __builtin_clz(ecap - 1) : 1u);
     WaveLds &L = Lw[wave];
-    const bool cached = cnt <= kListCap;
+    const bool cached = cnt <= list_cap(NW);
     if (cached)
         load_bin_list<NW>(bbox, pairs, C, start, cnt);
     unsigned long long st_ent = 0, st_frag = 0;
@@ -1781,7 +1798,7 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
     const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
     const uint32_t bx_bin = (bin % a.nbx) * bpb, by_bin = (bin / a.nbx) * bpb;
     UnsortedLds &U = Uw[wave];
-    const bool cached = cnt <= kListCap;
+    const bool cached = cnt <= list_cap(NW);
     if (cached)
         load_bin_list<NW>(bbox, pairs, C, start, cnt);
     unsigned long long st_ent = 0, st_frag = 0;
@@ -1863,7 +1880,7 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
     // single frames find their counters zeroed by the previous frame
     if (!a.ctr_next)
         hipLaunchKernelGGL(k_frame_begin<OneFrame>, dim3(1), dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_setup<OneFrame>, dim3((a.n + 255) / 256), dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_setup<OneFrame>, dim3((a.n + 255) / 256), dim3(256 / kSetupQPL), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[1], s);
     if (!bins)
@@ -1902,12 +1919,18 @@ bool sorter_depth_supported(int k)
     return k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 24 || k == 32;
 }
 
-// Raster (one workgroup of kRasterWaves waves per bin), then the exact pass.
+// Raster (one workgroup per bin), then the exact pass.
 template <int K, bool DEBUG>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     const OneFrame f{a};
-    hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s, f);
+    const uint32_t nw = raster_waves_for(a.bin_shift, K);
+    if (nw == 4)
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4>), dim3(a.nbins), dim3(4 * 64), 0, s, f);
+    else if (nw == 8)
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8>), dim3(a.nbins), dim3(8 * 64), 0, s, f);
+    else if constexpr (K <= 12)
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16>), dim3(a.nbins), dim3(16 * 64), 0, s, f);
     if (ev) {
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
@@ -1935,8 +1958,11 @@ template <bool DEBUG>
 static void launch_unsorted(const FrameArgs &a, hipStream_t s)
 {
     const OneFrame f{a};
-    hipLaunchKernelGGL((k_unsorted<kRasterWaves, DEBUG, OneFrame>), dim3(a.nbins), dim3(kRasterWaves * 64), 0, s,
-                       f);
+    switch (raster_waves(a.bin_shift)) {
+    case 4: hipLaunchKernelGGL((k_unsorted<4, DEBUG, OneFrame>), dim3(a.nbins), dim3(4 * 64), 0, s, f); break;
+    case 8: hipLaunchKernelGGL((k_unsorted<8, DEBUG, OneFrame>), dim3(a.nbins), dim3(8 * 64), 0, s, f); break;
+    default: hipLaunchKernelGGL((k_unsorted<16, DEBUG, OneFrame>), dim3(a.nbins), dim3(16 * 64), 0, s, f); break;
+    }
 }
 
 hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s, hipEvent_t *ev)
@@ -1984,9 +2010,14 @@ static FrameMap stage_map(const FrameArgs *dev, uint32_t nf, F &&wg)
 }
 
 template <int K>
-static void launch_raster_group(const FrameMap &m, hipStream_t s)
+static void launch_raster_group(const FrameMap &m, uint32_t nw, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_raster<K, false, FrameMap>), dim3(m.wg0[m.nf]), dim3(kRasterWaves * 64), 0, s, m);
+    if (nw == 4)
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 4>), dim3(m.wg0[m.nf]), dim3(4 * 64), 0, s, m);
+    else if (nw == 8)
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 8>), dim3(m.wg0[m.nf]), dim3(8 * 64), 0, s, m);
+    else if constexpr (K <= 12)
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 16>), dim3(m.wg0[m.nf]), dim3(16 * 64), 0, s, m);
 }
 
 hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *sorter_depth, uint32_t nf,
@@ -2002,7 +2033,7 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     const FrameMap one = stage_map(dev, nf, [](uint32_t) { return 1u; });
     hipLaunchKernelGGL(k_frame_begin<FrameMap>, dim3(nf), dim3(256), 0, s, one);
     const FrameMap ms = stage_map(dev, nf, [&](uint32_t f) { return (host[f].n + 255) / 256; });
-    hipLaunchKernelGGL(k_setup<FrameMap>, dim3(ms.wg0[nf]), dim3(256), 0, s, ms);
+    hipLaunchKernelGGL(k_setup<FrameMap>, dim3(ms.wg0[nf]), dim3(256 / kSetupQPL), 0, s, ms);
     // binning: frames with few bins use the four-wave kernels (one launch
     // each over those frames), the others the one-wave kernels
     uint32_t max_bins4 = 0;
@@ -2025,22 +2056,27 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
         hipLaunchKernelGGL(k_bin_scatter4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64),
                            kBin4Waves * max_bins4 * 4, s, mu4);
     static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
+    static const uint32_t kWaveCounts[] = {4, 8, 16};
     for (int K : kDepths) {
-        bool any = false;
-        for (uint32_t f = 0; f < nf; f++)
-            any = any || sorter_depth[f] == K;
-        if (!any)
-            continue;
-        const FrameMap mr =
-            stage_map(dev, nf, [&](uint32_t f) { return sorter_depth[f] == K ? host[f].nbins : 0u; });
-        switch (K) {
-        case 2: launch_raster_group<2>(mr, s); break;
-        case 4: launch_raster_group<4>(mr, s); break;
-        case 8: launch_raster_group<8>(mr, s); break;
-        case 12: launch_raster_group<12>(mr, s); break;
-        case 16: launch_raster_group<16>(mr, s); break;
-        case 24: launch_raster_group<24>(mr, s); break;
-        default: launch_raster_group<32>(mr, s); break;
+        for (uint32_t nw : kWaveCounts) {
+            auto in_group = [&](uint32_t f) {
+                return sorter_depth[f] == K && raster_waves_for(host[f].bin_shift, K) == nw;
+            };
+            bool any = false;
+            for (uint32_t f = 0; f < nf; f++)
+                any = any || in_group(f);
+            if (!any)
+                continue;
+            const FrameMap mr = stage_map(dev, nf, [&](uint32_t f) { return in_group(f) ? host[f].nbins : 0u; });
+            switch (K) {
+            case 2: launch_raster_group<2>(mr, nw, s); break;
+            case 4: launch_raster_group<4>(mr, nw, s); break;
+            case 8: launch_raster_group<8>(mr, nw, s); break;
+            case 12: launch_raster_group<12>(mr, nw, s); break;
+            case 16: launch_raster_group<16>(mr, nw, s); break;
+            case 24: launch_raster_group<24>(mr, nw, s); break;
+            default: launch_raster_group<32>(mr, nw, s); break;
+            }
         }
     }
     const FrameMap mf = stage_map(dev, nf, [&](uint32_t f) { return kQueues * host[f].fb_groups; });

@@ -254,7 +254,7 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_fb = take((uint64_t)lr::kQueues * p.qcap_blocks * 64 * 4);
     // block entries: a region per (bin, wave) as long as the bin list, twice
     // that with half-blocks
-    const uint64_t ents = (uint64_t)lr::kRasterWaves * p.pair_cap * (half ? 2 : 1);
+    const uint64_t ents = (uint64_t)lr::raster_waves(p.shift) * p.pair_cap * (half ? 2 : 1);
     p.o_ecode = take(ents * 4);
     p.o_emask = take(ents * 8);
     p.o_eid = take(ents * 4);
@@ -663,7 +663,7 @@ lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::Fram
     }
     // everything else the kernels read comes from the frame table
     std::vector<uint64_t> key;
-    key.reserve(2 + 6 * (size_t)nf);
+    key.reserve(2 + 8 * (size_t)nf);
     key.push_back(reinterpret_cast<uint64_t>(dev));
     key.push_back(nf);
     for (uint32_t f = 0; f < nf; f++) {
@@ -671,6 +671,8 @@ lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::Fram
         key.push_back(host[f].nunits);
         key.push_back(host[f].nbins);
         key.push_back(host[f].fb_groups);
+        key.push_back(host[f].bin_shift);  // raster waves per workgroup and binning kernels
+        key.push_back(host[f].bin_waves);
         key.push_back((uint64_t)ks[f]);
     }
     auto it = ctx->graphs.find(key);

@@ -1,6 +1,7 @@
 """Kernel resources checked on the CPU from the gfx950 assembly: no kernel
 spills to scratch memory, and the raster kernels keep to at most 128 VGPRs
-at the sorter depths the tuner uses for light frames (4 waves per SIMD)."""
+at the sorter depths the tuner uses for light frames (4 waves per SIMD),
+with LDS to match."""
 import os
 import re
 import subprocess
@@ -42,7 +43,14 @@ def test_raster_register_budget(kernels):
             assert v["vgpr"] <= 128, (name, v["vgpr"])
 
 
-def test_lds_fits_four_raster_workgroups(kernels):
+def test_raster_lds_allows_sixteen_waves_per_cu(kernels):
+    """A raster workgroup of NW waves must leave room for 16 / NW of them per
+    CU (160 KiB of LDS), so LDS does not cut occupancy below 4 waves/SIMD."""
+    seen = 0
     for name, v in kernels.items():
-        if "k_raster" in name:
-            assert 4 * v["lds"] <= 160 * 1024, (name, v["lds"])
+        m = re.search(r"k_raster.*Li(\d+)EEEvT", name)
+        if m:
+            nw = int(m.group(1))
+            assert (16 // nw) * v["lds"] <= 160 * 1024, (name, nw, v["lds"])
+            seen += 1
+    assert seen > 0
