@@ -131,6 +131,7 @@ struct FrameArgs {
     QuadXY *xy;
     uint2 *bbox;      // (imin | imax << 16, jmin | jmax << 16); culled: (0xffff, 0xffff)
     uint8_t *cull;
+    uint32_t want_xy;  // write snapped vertices of every snapped quad (parity dump); else wide quads only
     // binning
     uint32_t bin_shift;     // log2(bin size)
     uint32_t nbx, nby, nbins;

@@ -308,7 +308,9 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                     xy.X[k] = (int32_t)rint(sx[k] * 256.0);
                     xy.Y[k] = (int32_t)rint(sy[k] * 256.0);
                 }
-                a.xy[q] = xy;
+                // snapped vertices are kept for the fp64 path of wide quads and
+                // for the parity dump
+                bool keep_xy = a.want_xy != 0;
                 int64_t a0 = edge_fn(xy.X[0], xy.Y[0], xy.X[1], xy.Y[1], xy.X[2], xy.Y[2]);
                 int64_t a1 = edge_fn(xy.X[0], xy.Y[0], xy.X[2], xy.Y[2], xy.X[3], xy.Y[3]);
                 if (a0 == 0 && a1 == 0) {
@@ -361,11 +363,19 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                             if (xmax - xmin > kNarrowExtent || ymax - ymin > kNarrowExtent)
                                 flags |= kWide;
                             const int64_t Rx = 256 * imin + 128, Ry = 256 * jmin + 128;
-                            tri_halfplanes(xy.X, xy.Y, 0, 1, 2, Rx, Ry, r.hp, flags, kT0Valid, kT0Swap);
-                            tri_halfplanes(xy.X, xy.Y, 0, 2, 3, Rx, Ry, r.hp + 9, flags, kT1Valid,
-                                           kT1Swap);
+                            // a narrow strictly convex quad needs its four outer
+                            // edges only; the others their triangles' six
                             if (!(flags & kWide))
                                 convex_halfplanes(xy.X, xy.Y, Rx, Ry, r.hp, flags);
+                            if (flags & kConvex) {
+                                for (int k = 12; k < 18; k++)
+                                    r.hp[k] = 0;
+                            } else {
+                                tri_halfplanes(xy.X, xy.Y, 0, 1, 2, Rx, Ry, r.hp, flags, kT0Valid, kT0Swap);
+                                tri_halfplanes(xy.X, xy.Y, 0, 2, 3, Rx, Ry, r.hp + 9, flags, kT1Valid,
+                                               kT1Swap);
+                            }
+                            keep_xy = keep_xy || (flags & kWide) != 0;
                             r.bb_i = (uint32_t)imin | ((uint32_t)imax << 16);
                             r.bb_j = (uint32_t)jmin | ((uint32_t)jmax << 16);
                             r.rgba = a.rgba_in[q];
@@ -382,6 +392,8 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                         }
                     }
                 }
+                if (keep_xy)
+                    a.xy[q] = xy;
             }
         }
         a.bbox[q] = bb;

@@ -1134,6 +1134,7 @@ lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, u
     if (st != LR_OK)
         return st;
     LR_HIP(ctx, hipDeviceSynchronize());
+    a.want_xy = 1;
     LR_HIP(ctx, lr::launch_setup_only(a, ctx->stream));
     LR_HIP(ctx, hipStreamSynchronize(ctx->stream));
     // the next frame expects its counter set zeroed
