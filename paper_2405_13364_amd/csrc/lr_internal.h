@@ -137,7 +137,7 @@ struct FrameArgs {
     uint32_t nbx, nby, nbins;
     uint32_t unit_quads;    // quads per binning unit (multiple of 256)
     uint32_t nunits;
-    uint32_t bin_waves;     // waves per binning workgroup (1, or 4 for at most 4096 bins)
+    uint32_t bin_waves;     // waves per binning workgroup (1, or 4 for at most 8192 bins)
     uint32_t *table;        // [nunits][nbins]
     uint32_t *bin_start;    // [nbins + 1]
     uint32_t *bin_count;    // [nbins]

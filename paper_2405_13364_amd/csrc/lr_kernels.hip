@@ -736,7 +736,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 // top of the bin's start and the unit's scanned table entry, gives each wave
 // its own offsets, so the quarters scatter concurrently and every bin list
 // still comes out in ascending quad order.
-constexpr uint32_t kBin4MaxBins = 4096;
+constexpr uint32_t kBin4MaxBins = 8192;  // 4 x 32 KiB of per-wave offsets
 constexpr uint32_t kBin4Waves = 4;
 
 template <class Src>

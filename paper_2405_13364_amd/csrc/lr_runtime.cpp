@@ -217,13 +217,17 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.nbx = (W + bin - 1) / bin;
     p.nby = (H + bin - 1) / bin;
     p.nbins = p.nbx * p.nby;
-    // Binning units: with at most 4096 bins, four waves share a unit of at
-    // least 512 quads; otherwise one wave takes a unit of at least 256.
-    // Either way there are about 1024 units at most.
-    p.bin_waves = p.nbins <= 4096 ? 4u : 1u;
-    const uint64_t umin = p.bin_waves == 4 ? 512 : 256;
-    uint32_t uq = (uint32_t)std::max<uint64_t>(umin, (((uint64_t)n + 1023) / 1024 + 255) / 256 * 256);
-    p.unit_quads = uq;
+    // Binning units.  With at most 8192 bins four waves share a unit; each
+    // unit's scatter first builds its offsets for every bin, so a unit gets
+    // about nbins / 2 quads (512 to 4096), and there are at most about 1024
+    // units.  More bins: one wave per unit of at least 256 quads.
+    p.bin_waves = p.nbins <= 8192 ? 4u : 1u;
+    uint64_t uq = (((uint64_t)n + 1023) / 1024 + 255) / 256 * 256;
+    if (p.bin_waves == 4)
+        uq = std::max<uint64_t>(uq, std::min<uint64_t>(4096, std::max<uint64_t>(512, (p.nbins / 2 + 511) / 512 * 512)));
+    else
+        uq = std::max<uint64_t>(uq, 256);
+    p.unit_quads = (uint32_t)uq;
     p.nunits = std::max<uint32_t>(1, (n + uq - 1) / uq);
     // first guess; an overflow is reported and the next frame is planned larger
     uint64_t cap = 5ull * n / 2 + 4ull * p.nbins + 65536;
