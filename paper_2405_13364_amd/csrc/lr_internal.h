@@ -78,7 +78,8 @@ static_assert(sizeof(StatStripe) == 128, "one line per stripe");
 struct FrameCounters {
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
-    uint32_t pad[30];
+    uint32_t fb_next;          // next flagged pixel for the exact pass
+    uint32_t pad[29];
     StatStripe stripe[kStripes];
 };
 
@@ -146,7 +147,6 @@ struct FrameArgs {
     uint32_t match_bits;    // bits needed to hold a bin index
     // raster
     uint32_t half_blocks;     // 1: block lists are sorted per 8x4 half-block
-    uint32_t fb_groups;       // exact-pass workgroups per flagged-queue stripe
     uint32_t nblk_x, nblk_y;  // 8x8 blocks
     uint32_t qcap_blocks;     // blocks per queue stripe: ceil(nblk_x*nblk_y / kQueues)
     uint32_t *fb_queue;       // flagged pixels [kQueues][qcap_blocks * 64]
@@ -206,7 +206,5 @@ bool sorter_depth_supported(int k);
 hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *sorter_depth, uint32_t nf,
                         hipStream_t s);
 
-// Workgroups the exact per-pixel pass uses per flagged-queue stripe.
-uint32_t fallback_groups(uint32_t nblocks);
 
 }  // namespace lr

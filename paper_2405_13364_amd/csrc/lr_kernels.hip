@@ -1653,6 +1653,9 @@ __global__ __launch_bounds__(NW * 64) void k_raster(Src src)
 
 constexpr uint32_t kFallbackBuf = 4096;
 constexpr uint32_t kFallbackStep = 4;
+// Workgroups of the exact pass: as many one-wave workgroups with a 32 KiB
+// key buffer as 256 CUs hold at once (5 each).
+constexpr uint32_t kFallbackGrid = 1280;
 
 // The first 112 bytes of a quad record (everything but the fp32 plane) in
 // one go: seven 16-byte loads issued together, so the coverage test and the
@@ -1669,115 +1672,142 @@ __device__ __forceinline__ QuadRec load_rec(const QuadRec *__restrict__ rec, uin
     return r;
 }
 
+// Frames of a launch source, for kernels that walk them in turn.
+__device__ __forceinline__ uint32_t frame_count(const OneFrame &) { return 1; }
+__device__ __forceinline__ const FrameArgs &frame_at(const OneFrame &src, uint32_t) { return src.a; }
+__device__ __forceinline__ uint32_t frame_count(const FrameMap &m) { return m.nf; }
+__device__ __forceinline__ const FrameArgs &frame_at(const FrameMap &m, uint32_t f) { return m.tab[f]; }
+
+// A persistent grid (kFallbackGrid workgroups of one wave) walks the frames
+// in order; in each frame its waves take flagged pixels one at a time from
+// the frame's work counter, so any number of flagged pixels spreads over the
+// whole GPU.
 template <bool DEBUG, class Src>
 __global__ __launch_bounds__(64) void k_fallback(Src src)
 {
     __shared__ unsigned long long s_key[kFallbackBuf];
-    uint32_t blk;
-    const FrameArgs &a = *frame_of(src, blk);
-    const QuadRec *__restrict__ rec = a.rec;
-    const QuadXY *__restrict__ xyp = a.xy;
-    const uint2 *__restrict__ bbox = a.bbox;
-    const uint32_t *__restrict__ pairs = a.pairs;
-    clear_next_counters(a, blk, kQueues * a.fb_groups);
-    if (a.ctr->error & kErrPairs)
-        return;
-    const uint32_t lane = threadIdx.x;
-    const uint32_t sq = blk % kQueues, G = a.fb_groups;
-    const uint32_t count = uniform(a.ctr->stripe[sq].flag_n);
-    for (uint32_t t = blk / kQueues; t < count; t += G) {
-        const uint32_t p = uniform(a.fb_queue[(size_t)sq * a.qcap_blocks * 64 + t]);
-        const int i = (int)(p % a.W), j = (int)(p / a.W);
-        const uint32_t bin = ((uint32_t)j >> a.bin_shift) * a.nbx + ((uint32_t)i >> a.bin_shift);
-        const uint32_t start = uniform(a.bin_start[bin]);
-        const uint32_t cnt = uniform(a.bin_count[bin]);
-        const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
-        float T = 1.0f, R = 0.0f, G2 = 0.0f, B = 0.0f;
-        unsigned long long lo = 0;  // keys <= lo are blended already (real keys are > 0)
-        uint32_t total = 0, done = 0;
-        for (bool more = true; more;) {
-            unsigned long long hi = ~0ull;  // the buffer holds every key in (lo, hi]
-            bool cut = false;
-            uint32_t n = 0, seen = 0;
-            // kFallbackStep chunks of 64 candidates per step: each stage's loads
-            // (list entries, then bboxes, then records) are issued together
-            for (uint32_t base = 0; base < cnt; base += 64 * kFallbackStep) {
-                if (n + 64 * kFallbackStep > kFallbackBuf) {
-                    // keep the lower half of the buffer
-                    wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
-                    n = kFallbackBuf / 2;
-                    hi = s_key[n - 1];
-                    cut = true;
+    const uint32_t blk = blockIdx.x, nblk = gridDim.x, lane = threadIdx.x;
+    for (uint32_t fi = 0; fi < frame_count(src); fi++) {
+        const FrameArgs &a = frame_at(src, fi);
+        const QuadRec *__restrict__ rec = a.rec;
+        const QuadXY *__restrict__ xyp = a.xy;
+        const uint2 *__restrict__ bbox = a.bbox;
+        const uint32_t *__restrict__ pairs = a.pairs;
+        clear_next_counters(a, blk, nblk);
+        if (a.ctr->error & kErrPairs)
+            continue;
+        // the frame's flagged pixels: one queue stripe per lane (kQueues == 64)
+        const uint32_t cq = a.ctr->stripe[lane].flag_n;
+        uint32_t incl = cq;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
+            if (lane >= (uint32_t)off)
+                incl += v;
+        }
+        const uint32_t count = lane_value(incl, 63);
+        for (;;) {
+            uint32_t item = 0;
+            if (lane == 0 && count)
+                item = atomicAdd(&a.ctr->fb_next, 1u);
+            item = uniform(item);
+            if (item >= count)
+                break;
+            // stripe sq holds items [incl[sq - 1], incl[sq])
+            const uint32_t sq = (uint32_t)__popcll(ballot(incl <= item));
+            const uint32_t t = item - (sq ? lane_value(incl, sq - 1) : 0);
+            const uint32_t p = uniform(a.fb_queue[(size_t)sq * a.qcap_blocks * 64 + t]);
+            const int i = (int)(p % a.W), j = (int)(p / a.W);
+            const uint32_t bin = ((uint32_t)j >> a.bin_shift) * a.nbx + ((uint32_t)i >> a.bin_shift);
+            const uint32_t start = uniform(a.bin_start[bin]);
+            const uint32_t cnt = uniform(a.bin_count[bin]);
+            const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
+            float T = 1.0f, R = 0.0f, G2 = 0.0f, B = 0.0f;
+            unsigned long long lo = 0;  // keys <= lo are blended already (real keys are > 0)
+            uint32_t total = 0, done = 0;
+            for (bool more = true; more;) {
+                unsigned long long hi = ~0ull;  // the buffer holds every key in (lo, hi]
+                bool cut = false;
+                uint32_t n = 0, seen = 0;
+                // kFallbackStep chunks of 64 candidates per step: each stage's loads
+                // (list entries, then bboxes, then records) are issued together
+                for (uint32_t base = 0; base < cnt; base += 64 * kFallbackStep) {
+                    if (n + 64 * kFallbackStep > kFallbackBuf) {
+                        // keep the lower half of the buffer
+                        wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
+                        n = kFallbackBuf / 2;
+                        hi = s_key[n - 1];
+                        cut = true;
+                        wave_sync();
+                    }
+                    uint32_t q[kFallbackStep];
+                    bool ov[kFallbackStep];
+    #pragma unroll
+                    for (uint32_t c = 0; c < kFallbackStep; c++) {
+                        const uint32_t l = base + 64 * c + lane;
+                        q[c] = l < cnt ? pairs[start + l] : 0xFFFFFFFFu;
+                    }
+    #pragma unroll
+                    for (uint32_t c = 0; c < kFallbackStep; c++) {
+                        const uint2 bb = q[c] != 0xFFFFFFFFu ? bbox[q[c]] : make_uint2(0xffffu, 0u);
+                        ov[c] = (int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
+                                (int)(bb.y >> 16) >= j;
+                    }
+    #pragma unroll
+                    for (uint32_t c = 0; c < kFallbackStep; c++) {
+                        bool cov = false;
+                        unsigned long long key = 0;
+                        if (ov[c]) {
+                            const QuadRec r = load_rec(rec, q[c]);
+                            if (pixel_coverage(r, xyp, q[c], i, j)) {
+                                cov = true;
+                                const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
+                                                          j - (int)(r.bb_j & 0xffffu));
+                                key = ((unsigned long long)order_code(kf) << 32) | q[c];
+                            }
+                        }
+                        seen += (uint32_t)__popcll(ballot(cov));
+                        const bool keep = cov && key > lo && key <= hi;
+                        const uint64_t m = ballot(keep);
+                        if (keep)
+                            s_key[n + rank_below(m)] = key;
+                        n += (uint32_t)__popcll(m);
+                    }
                     wave_sync();
                 }
-                uint32_t q[kFallbackStep];
-                bool ov[kFallbackStep];
-#pragma unroll
-                for (uint32_t c = 0; c < kFallbackStep; c++) {
-                    const uint32_t l = base + 64 * c + lane;
-                    q[c] = l < cnt ? pairs[start + l] : 0xFFFFFFFFu;
-                }
-#pragma unroll
-                for (uint32_t c = 0; c < kFallbackStep; c++) {
-                    const uint2 bb = q[c] != 0xFFFFFFFFu ? bbox[q[c]] : make_uint2(0xffffu, 0u);
-                    ov[c] = (int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
-                            (int)(bb.y >> 16) >= j;
-                }
-#pragma unroll
-                for (uint32_t c = 0; c < kFallbackStep; c++) {
-                    bool cov = false;
-                    unsigned long long key = 0;
-                    if (ov[c]) {
-                        const QuadRec r = load_rec(rec, q[c]);
-                        if (pixel_coverage(r, xyp, q[c], i, j)) {
-                            cov = true;
-                            const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
-                                                      j - (int)(r.bb_j & 0xffffu));
-                            key = ((unsigned long long)order_code(kf) << 32) | q[c];
-                        }
+                if (total == 0)
+                    total = seen;
+                wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
+                for (uint32_t base = 0; base < n; base += 64) {
+                    const uint32_t e = base + lane;
+                    uint32_t q = 0, c = 0;
+                    if (e < n) {
+                        q = (uint32_t)(s_key[e] & 0xffffffffu);
+                        c = rec[q].rgba;
+                        if (DEBUG && a.dbg_ids && obase + done + e < a.dbg_cap)
+                            a.dbg_ids[obase + done + e] = q;
                     }
-                    seen += (uint32_t)__popcll(ballot(cov));
-                    const bool keep = cov && key > lo && key <= hi;
-                    const uint64_t m = ballot(keep);
-                    if (keep)
-                        s_key[n + rank_below(m)] = key;
-                    n += (uint32_t)__popcll(m);
+                    const uint32_t lim = min(64u, n - base);
+                    for (uint32_t s = 0; s < lim; s++)
+                        blend_ftb(lane_value(c, s), T, R, G2, B);
                 }
+                done += n;
+                if (n)
+                    lo = s_key[n - 1];
+                more = cut;
                 wave_sync();
             }
-            if (total == 0)
-                total = seen;
-            wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
-            for (uint32_t base = 0; base < n; base += 64) {
-                const uint32_t e = base + lane;
-                uint32_t q = 0, c = 0;
-                if (e < n) {
-                    q = (uint32_t)(s_key[e] & 0xffffffffu);
-                    c = rec[q].rgba;
-                    if (DEBUG && a.dbg_ids && obase + done + e < a.dbg_cap)
-                        a.dbg_ids[obase + done + e] = q;
+            if (lane == 0) {
+                add_stat(a.ctr, ST_FRAGMENTS, total);
+                reinterpret_cast<uint32_t *>(a.out)[p] = pack_rgba8(R, G2, B, 1.0f - T);
+                if (DEBUG) {
+                    if (a.dbg_rgba)
+                        reinterpret_cast<float4 *>(a.dbg_rgba)[p] = make_float4(R, G2, B, 1.0f - T);
+                    if (a.dbg_count)
+                        a.dbg_count[p] = total;
                 }
-                const uint32_t lim = min(64u, n - base);
-                for (uint32_t s = 0; s < lim; s++)
-                    blend_ftb(lane_value(c, s), T, R, G2, B);
             }
-            done += n;
-            if (n)
-                lo = s_key[n - 1];
-            more = cut;
             wave_sync();
         }
-        if (lane == 0) {
-            add_stat(a.ctr, ST_FRAGMENTS, total);
-            reinterpret_cast<uint32_t *>(a.out)[p] = pack_rgba8(R, G2, B, 1.0f - T);
-            if (DEBUG) {
-                if (a.dbg_rgba)
-                    reinterpret_cast<float4 *>(a.dbg_rgba)[p] = make_float4(R, G2, B, 1.0f - T);
-                if (a.dbg_count)
-                    a.dbg_count[p] = total;
-            }
-        }
-        wave_sync();
     }
 }
 
@@ -1881,10 +1911,6 @@ __global__ __launch_bounds__(256) void k_transpose_scene(const uint32_t *__restr
 
 // ---------------------------------------------------------------- launches
 
-uint32_t fallback_groups(uint32_t nblocks)
-{
-    return std::min<uint32_t>(32, std::max<uint32_t>(2, (nblocks + 255) / 256));
-}
 
 static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEvent_t *ev, bool bins)
 {
@@ -1947,7 +1973,7 @@ static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
     }
-    hipLaunchKernelGGL((k_fallback<DEBUG, OneFrame>), dim3(kQueues * a.fb_groups), dim3(64), 0, s, f);
+    hipLaunchKernelGGL((k_fallback<DEBUG, OneFrame>), dim3(kFallbackGrid), dim3(64), 0, s, f);
     if (ev)
         (void)hipEventRecord(ev[7], s);
 }
@@ -2091,8 +2117,8 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
             }
         }
     }
-    const FrameMap mf = stage_map(dev, nf, [&](uint32_t f) { return kQueues * host[f].fb_groups; });
-    hipLaunchKernelGGL((k_fallback<false, FrameMap>), dim3(mf.wg0[nf]), dim3(64), 0, s, mf);
+    const FrameMap mf = stage_map(dev, nf, [&](uint32_t) { return 0u; });  // frames walked in turn
+    hipLaunchKernelGGL((k_fallback<false, FrameMap>), dim3(kFallbackGrid), dim3(64), 0, s, mf);
     return hipGetLastError();
 }
 

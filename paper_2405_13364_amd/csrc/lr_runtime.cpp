@@ -200,7 +200,7 @@ uint32_t log2u(uint32_t x)
 // Byte layout of a frame workspace.
 struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
-        match_bits, qcap_blocks, fb_groups;
+        match_bits, qcap_blocks;
     uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
         total;
 };
@@ -254,7 +254,6 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_count = take((uint64_t)p.nbins * 4);
     p.o_pairs = take((uint64_t)p.pair_cap * 4);
     p.qcap_blocks = (p.nblk_x * p.nblk_y + lr::kQueues - 1) / lr::kQueues;
-    p.fb_groups = lr::fallback_groups(p.nblk_x * p.nblk_y);
     p.o_fb = take((uint64_t)lr::kQueues * p.qcap_blocks * 64 * 4);
     // block entries: a region per (bin, wave) as long as the bin list, twice
     // that with half-blocks
@@ -381,7 +380,6 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
     a.pair_cap = plan.pair_cap;
     a.match_bits = plan.match_bits;
     a.half_blocks = plan.half;
-    a.fb_groups = plan.fb_groups;
     a.nblk_x = plan.nblk_x;
     a.nblk_y = plan.nblk_y;
     a.qcap_blocks = plan.qcap_blocks;
@@ -674,7 +672,6 @@ lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::Fram
         key.push_back(host[f].n);
         key.push_back(host[f].nunits);
         key.push_back(host[f].nbins);
-        key.push_back(host[f].fb_groups);
         key.push_back(host[f].bin_shift);  // raster waves per workgroup and binning kernels
         key.push_back(host[f].bin_waves);
         key.push_back((uint64_t)ks[f]);
