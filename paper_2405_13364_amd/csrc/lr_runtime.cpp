@@ -863,6 +863,7 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
     ctx->timing = (c.flags & LR_FLAG_TIMING) != 0;
     ctx->use_graphs = (c.flags & LR_FLAG_NO_GRAPH) == 0;
     ctx->max_slots = c.batch_slots;
+    ctx->slots.reserve(8);  // slot addresses stay fixed (at most 8 slots)
     bool ok = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming) == hipSuccess;
     for (uint32_t i = 0; i < kTabRing; i++)
         ok = ok && hipEventCreateWithFlags(&ctx->tab_ev[i], hipEventDisableTiming) == hipSuccess;
