@@ -104,17 +104,29 @@ __device__ __forceinline__ float frag_key(double A, double B, double C0, int di,
 
 __device__ __forceinline__ uint32_t order_code(float k) { return ~__float_as_uint(k); }
 
-// Front-to-back blend step (fp32), shared by every sorted path so that their
-// results are bit-identical.
-__device__ __forceinline__ void blend_ftb(uint32_t c, float &T, float &R, float &G, float &B)
+// A colour as the blend uses it: alpha and the three channels, each byte /
+// 255 in fp32.
+__device__ __forceinline__ float4 decode_rgba(uint32_t c)
 {
     const float s = 1.0f / 255.0f;
-    float a = (float)(c >> 24) * s;
-    float w = T * a;
-    R = fmaf(w, (float)(c & 255u) * s, R);
-    G = fmaf(w, (float)((c >> 8) & 255u) * s, G);
-    B = fmaf(w, (float)((c >> 16) & 255u) * s, B);
-    T = T * (1.0f - a);
+    return make_float4((float)(c >> 24) * s, (float)(c & 255u) * s, (float)((c >> 8) & 255u) * s,
+                       (float)((c >> 16) & 255u) * s);
+}
+
+// Front-to-back blend step (fp32) of a decoded colour (x = alpha), shared by
+// every sorted path so that their results are bit-identical.
+__device__ __forceinline__ void blend_ftb_dec(float4 d, float &T, float &R, float &G, float &B)
+{
+    const float w = T * d.x;
+    R = fmaf(w, d.y, R);
+    G = fmaf(w, d.z, G);
+    B = fmaf(w, d.w, B);
+    T = T * (1.0f - d.x);
+}
+
+__device__ __forceinline__ void blend_ftb(uint32_t c, float &T, float &R, float &G, float &B)
+{
+    blend_ftb_dec(decode_rgba(c), T, R, G, B);
 }
 
 // "Over" step of the unsorted baseline (fp32).
@@ -1653,9 +1665,11 @@ __global__ __launch_bounds__(NW * 64) void k_raster(Src src)
 
 constexpr uint32_t kFallbackBuf = 4096;
 constexpr uint32_t kFallbackStep = 4;
-// Workgroups of the exact pass: as many one-wave workgroups with a 32 KiB
-// key buffer as 256 CUs hold at once (5 each).
-constexpr uint32_t kFallbackGrid = 1280;
+// The exact pass runs one workgroup per CU, each with kFallbackWaves waves
+// working on their own pixels with their own 32 KiB key buffer.
+constexpr uint32_t kFallbackWaves = 4;
+constexpr uint32_t kFallbackGrid = 256;
+constexpr size_t kFallbackLds = (size_t)kFallbackWaves * (kFallbackBuf * 8 + 64 * 16);
 
 // The first 112 bytes of a quad record (everything but the fp32 plane) in
 // one go: seven 16-byte loads issued together, so the coverage test and the
@@ -1683,10 +1697,12 @@ __device__ __forceinline__ const FrameArgs &frame_at(const FrameMap &m, uint32_t
 // the frame's work counter, so any number of flagged pixels spreads over the
 // whole GPU.
 template <bool DEBUG, class Src>
-__global__ __launch_bounds__(64) void k_fallback(Src src)
+__global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
 {
-    __shared__ unsigned long long s_key[kFallbackBuf];
-    const uint32_t blk = blockIdx.x, nblk = gridDim.x, lane = threadIdx.x;
+    extern __shared__ unsigned long long s_fb[];  // [kFallbackWaves][kFallbackBuf] keys, then decoded colours
+    const uint32_t blk = blockIdx.x, nblk = gridDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long *s_key = s_fb + (size_t)wave * kFallbackBuf;
+    float4 *s_col = reinterpret_cast<float4 *>(s_fb + (size_t)kFallbackWaves * kFallbackBuf) + wave * 64;
     for (uint32_t fi = 0; fi < frame_count(src); fi++) {
         const FrameArgs &a = frame_at(src, fi);
         const QuadRec *__restrict__ rec = a.rec;
@@ -1786,9 +1802,13 @@ __global__ __launch_bounds__(64) void k_fallback(Src src)
                         if (DEBUG && a.dbg_ids && obase + done + e < a.dbg_cap)
                             a.dbg_ids[obase + done + e] = q;
                     }
+                    // colours decoded by all lanes, then blended in order
+                    s_col[lane] = decode_rgba(c);
+                    wave_sync();
                     const uint32_t lim = min(64u, n - base);
                     for (uint32_t s = 0; s < lim; s++)
-                        blend_ftb(lane_value(c, s), T, R, G2, B);
+                        blend_ftb_dec(s_col[s], T, R, G2, B);
+                    wave_sync();
                 }
                 done += n;
                 if (n)
@@ -1973,7 +1993,8 @@ static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
     }
-    hipLaunchKernelGGL((k_fallback<DEBUG, OneFrame>), dim3(kFallbackGrid), dim3(64), 0, s, f);
+    hipLaunchKernelGGL((k_fallback<DEBUG, OneFrame>), dim3(kFallbackGrid), dim3(kFallbackWaves * 64),
+                       kFallbackLds, s, f);
     if (ev)
         (void)hipEventRecord(ev[7], s);
 }
@@ -2118,7 +2139,8 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
         }
     }
     const FrameMap mf = stage_map(dev, nf, [&](uint32_t) { return 0u; });  // frames walked in turn
-    hipLaunchKernelGGL((k_fallback<false, FrameMap>), dim3(kFallbackGrid), dim3(64), 0, s, mf);
+    hipLaunchKernelGGL((k_fallback<false, FrameMap>), dim3(kFallbackGrid), dim3(kFallbackWaves * 64), kFallbackLds,
+                       s, mf);
     return hipGetLastError();
 }
 
