@@ -48,9 +48,52 @@ __device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t lane)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
 }
 
+// v of lane (this lane ^ m), for a constant power of two m.  Within a row of
+// 16 lanes the exchange is a DPP move (quad permutes for 1 and 2, row
+// rotations for 4 and 8); across rows and halves it is gfx950's
+// permlane16 / permlane32 swap.  All are VALU operations: no LDS round
+// trip, so chains of them (sorting networks, transposes, reductions) carry
+// no LDS latency.  Every lane must be active.
 __device__ __forceinline__ uint32_t shfl_xor(uint32_t v, int m)
 {
-    return (uint32_t)__shfl_xor((int)v, m, 64);
+    const uint32_t lane = lane_id();
+    switch (m) {
+    case 1:
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
+    case 2:
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);  // quad_perm 2,3,0,1
+    case 4: {
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);  // row_ror 4
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xf, 0xf, false);  // row_ror 12
+        return (lane & 4) ? dn : up;
+    }
+    case 8:
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);  // row_ror 8
+    case 16: {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    }
+    case 32: {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+    default:
+        return (uint32_t)__shfl_xor((int)v, m, 64);
+    }
+}
+
+// Inclusive prefix sum over the wave: a Hillis-Steele scan within each row
+// of 16 lanes by DPP row shifts, then the row totals carried across rows by
+// the row broadcasts of lanes 15 and 31.  Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr 1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr 2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr 4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr 8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast 15 -> rows 1, 3
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast 31 -> rows 2, 3
+    return v;
 }
 
 // Transpose a 64x64 bit matrix held one row per lane (lane e holds row e as
@@ -61,12 +104,10 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t m, uint32_t lane)
 {
     uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
     {
-        const bool up = lane & 32;
-        uint32_t recv = shfl_xor(up ? lo : hi, 32);
-        if (up)
-            lo = recv;
-        else
-            hi = recv;
+        // lanes 0-31 take hi from lane + 32's lo, lanes 32-63 lo from lane - 32's hi
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        lo = r[0];
+        hi = r[1];
     }
 #define LR_TRANSPOSE_LEVEL(S, MASK)                                                  \
     {                                                                                \
@@ -606,12 +647,7 @@ __device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uin
     uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
     quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
     // inclusive prefix of np over the wave
-    uint32_t incl = np;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
-        if (lane >= (uint32_t)off)
-            incl += v;
-    }
+    const uint32_t incl = wave_incl_scan(np);
     const uint32_t total = lane_value(incl, 63);
     s_pref[lane] = incl;
     s_rect[lane][0] = bx0;
@@ -700,12 +736,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
             const uint32_t b = b0 + 64 * k + lane;
-            uint32_t incl = c[k];
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
-                if (lane >= (uint32_t)off)
-                    incl += v;
-            }
+            const uint32_t incl = wave_incl_scan(c[k]);
             const uint32_t start = carry + incl - c[k];
             carry += lane_value(incl, 63);
             if (b < a.nbins) {
@@ -923,86 +954,157 @@ __device__ __forceinline__ uint32_t shift_in_sign(uint32_t acc, int v)
     return __builtin_amdgcn_alignbit(acc, (uint32_t)v, 31);
 }
 
-// Coverage of one quad over the 64 samples of an 8x8 block, computed by one
-// lane (bit 8*y + x for pixel (px0 + x, py0 + y)), exact under the top-left
-// rule.  Narrow quads step their integer edge values E = a*di + b*dj - t
-// across the block (sample inside an edge iff E >= 0; |a*di + b*dj| < 2^30
-// and |t| < 2^30 for narrow quads, so E never overflows): four edges for a
-// convex quad, the two triangles' six otherwise.  Each row is walked from
-// x = 7 down so the sign bits land in order.
-__device__ uint64_t lane_block_mask(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q, int px0, int py0)
+// Coverage of one 8-sample row by a narrow quad, exact under the top-left
+// rule: e[h] holds the integer edge value E = a*di + b*dj - t of half-plane
+// h at the row's last sample (x = 7) and a[h] its step in x; the values are
+// stepped from x = 7 down so the sign bits land in order, bit x set when
+// the sample is inside (E >= 0 on every edge of a convex quad's four, or of
+// one of the two triangles' three).  |a*di + b*dj| < 2^30 and |t| < 2^30
+// for narrow quads, so E never overflows.
+template <int NE>
+__device__ __forceinline__ uint32_t row_walk(const int *a, const int *e0)
 {
-    const uint32_t flags = r.flags;
-    if (flags & kWide)
-        return wide_block_mask(flags, xyp[q], px0, py0);
-    const int di = px0 - (int)(r.bb_i & 0xffffu);
-    const int dj = py0 - (int)(r.bb_j & 0xffffu);
-    uint32_t lo = 0, hi = 0;
-    if (flags & kConvex) {
-        int a[4], b[4], row[4];
+    int e[NE];
 #pragma unroll
-        for (int h = 0; h < 4; h++) {
-            a[h] = r.hp[3 * h];
-            b[h] = r.hp[3 * h + 1];
-            row[h] = a[h] * (di + 7) + b[h] * dj - r.hp[3 * h + 2];  // value at x = 7
+    for (int h = 0; h < NE; h++)
+        e[h] = e0[h];
+    uint32_t bits = 0;
+#pragma unroll
+    for (int x = 0; x < 8; x++) {
+        if constexpr (NE == 4) {
+            bits = shift_in_sign(bits, e[0] | e[1] | e[2] | e[3]);  // 1: outside some edge
+            asm volatile("" : "+v"(e[0]), "+v"(e[1]), "+v"(e[2]), "+v"(e[3]));
+        } else {
+            // outside iff both triangles have a negative edge value
+            bits = shift_in_sign(bits, (e[0] | e[1] | e[2]) & (e[3] | e[4] | e[5]));
+            asm volatile("" : "+v"(e[0]), "+v"(e[1]), "+v"(e[2]), "+v"(e[3]), "+v"(e[4]), "+v"(e[5]));
         }
-#pragma unroll 1
-        for (int y = 0; y < 8; y++) {
-            int e0 = row[0], e1 = row[1], e2 = row[2], e3 = row[3];
-            uint32_t bits = 0;
 #pragma unroll
-            for (int x = 0; x < 8; x++) {
-                bits = shift_in_sign(bits, e0 | e1 | e2 | e3);  // 1: outside some edge
-                e0 -= a[0];
-                e1 -= a[1];
-                e2 -= a[2];
-                e3 -= a[3];
-                asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3));
+        for (int h = 0; h < NE; h++)
+            e[h] -= a[h];
+    }
+    return ~bits & 0xffu;
+}
+
+// A wave's scratch for the coverage masks of one batch.
+struct RowWork {
+    uint16_t item[512];           // (candidate << 3) | row, candidate by candidate
+    unsigned long long mask[64];  // candidate masks, filled one row byte at a time
+};
+
+__device__ __forceinline__ int lane_int(int v, uint32_t src_lane)
+{
+    return __builtin_amdgcn_ds_bpermute((int)(src_lane << 2), v);
+}
+
+// Row passes up to which a batch spreads its rows over the lanes; denser
+// batches (large quads, most rows covered) walk eight rows per candidate.
+constexpr uint32_t kRowPasses = 4;
+
+// Coverage masks of a batch of m candidates (lane e < m: quad cand[e]) over
+// the 8x8 block at (px0, py0), bit 8y + x for pixel (px0 + x, py0 + y).
+// Only the rows that a candidate's bbox meets can be covered.  When those
+// (candidate, row) pairs fill at most kRowPasses waves' worth, they are
+// listed and spread over the lanes, one row walk each, with each
+// candidate's edge values fetched from its own lane; otherwise every
+// candidate's lane walks the eight rows itself.  A wide quad (rare) is done
+// sample by sample by its own lane.  Returns lane e's mask.
+__device__ __forceinline__ uint64_t batch_masks(const QuadRec *__restrict__ rec, const QuadXY *__restrict__ xyp,
+                                const uint32_t *cand, RowWork &W, uint32_t m, int px0, int py0, uint32_t lane)
+{
+    // candidate lane: per half-plane h the step a, the row step b and the
+    // value at (x = 7, y = 0) of the block
+    int ca[6], cb[6], cv[6];
+    uint32_t q = 0, nr = 0, y0 = 0, cvx = 1;
+    bool wide = false;
+#pragma unroll
+    for (int h = 0; h < 6; h++)
+        ca[h] = cb[h] = cv[h] = 0;
+    if (lane < m) {
+        q = cand[lane];
+        const QuadRec &r = rec[q];
+        wide = (r.flags & kWide) != 0;
+        cvx = (r.flags & kConvex) ? 1u : 0u;
+        if (!wide) {
+            const int di = px0 + 7 - (int)(r.bb_i & 0xffffu);
+            const int dj = py0 - (int)(r.bb_j & 0xffffu);
+            const int ne = cvx ? 4 : 6;
+#pragma unroll
+            for (int h = 0; h < 6; h++) {
+                if (h < ne) {
+                    ca[h] = r.hp[3 * h];
+                    cb[h] = r.hp[3 * h + 1];
+                    cv[h] = ca[h] * di + cb[h] * dj - r.hp[3 * h + 2];
+                }
             }
-            bits = ~bits & 0xffu;
-            if (y < 4)
-                lo |= bits << (8 * y);
-            else
-                hi |= bits << (8 * (y - 4));
-#pragma unroll
-            for (int h = 0; h < 4; h++)
-                row[h] += b[h];
-        }
-    } else {
-        int a[6], b[6], row[6];
-#pragma unroll
-        for (int h = 0; h < 6; h++) {
-            a[h] = r.hp[3 * h];
-            b[h] = r.hp[3 * h + 1];
-            row[h] = a[h] * (di + 7) + b[h] * dj - r.hp[3 * h + 2];
-        }
-#pragma unroll 1
-        for (int y = 0; y < 8; y++) {
-            int e0 = row[0], e1 = row[1], e2 = row[2], e3 = row[3], e4 = row[4], e5 = row[5];
-            uint32_t bits = 0;
-#pragma unroll
-            for (int x = 0; x < 8; x++) {
-                // outside iff both triangles have a negative edge value
-                bits = shift_in_sign(bits, (e0 | e1 | e2) & (e3 | e4 | e5));
-                e0 -= a[0];
-                e1 -= a[1];
-                e2 -= a[2];
-                e3 -= a[3];
-                e4 -= a[4];
-                e5 -= a[5];
-                asm volatile("" : "+v"(e0), "+v"(e1), "+v"(e2), "+v"(e3), "+v"(e4), "+v"(e5));
-            }
-            bits = ~bits & 0xffu;
-            if (y < 4)
-                lo |= bits << (8 * y);
-            else
-                hi |= bits << (8 * (y - 4));
-#pragma unroll
-            for (int h = 0; h < 6; h++)
-                row[h] += b[h];
+            // the bbox meets the block, so rows y0..y1 are within 0..7
+            const int y1 = min((int)(r.bb_j >> 16) - py0, 7);
+            y0 = (uint32_t)max(-dj, 0);
+            nr = y1 >= (int)y0 ? (uint32_t)y1 - y0 + 1 : 0u;
         }
     }
-    return (uint64_t)lo | ((uint64_t)hi << 32);
+    // exclusive prefix of the row counts (at most 8: four bit planes)
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 4; b++) {
+        const uint64_t bm = ballot(((nr >> b) & 1u) != 0);
+        pre += rank_below(bm) << b;
+        tot += (uint32_t)__popcll(bm) << b;
+    }
+    const bool any6 = ballot(nr != 0 && !cvx) != 0;
+    uint64_t mk = 0;
+    if (tot > kRowPasses * 64) {
+        if (nr) {
+            uint32_t lo = 0, hi = 0;
+#pragma unroll 1
+            for (uint32_t y = 0; y < 8; y++) {
+                int e[6];
+#pragma unroll
+                for (int h = 0; h < 6; h++)
+                    e[h] = cv[h] + cb[h] * (int)y;
+                const uint32_t bits = cvx ? row_walk<4>(ca, e) : row_walk<6>(ca, e);
+                if (y < 4)
+                    lo |= bits << (8 * y);
+                else
+                    hi |= bits << (8 * (y - 4));
+            }
+            mk = (uint64_t)lo | ((uint64_t)hi << 32);
+        }
+    } else if (tot) {
+        if (nr)
+            W.mask[lane] = 0;
+        for (uint32_t k = 0; k < nr; k++)
+            W.item[pre + k] = (uint16_t)((lane << 3) | (y0 + k));
+        wave_sync();
+        uint8_t *rows = reinterpret_cast<uint8_t *>(W.mask);
+        for (uint32_t base = 0; base < tot; base += 64) {
+            const uint32_t i = base + lane;
+            const uint32_t it = i < tot ? W.item[i] : 0u, c = it >> 3, y = it & 7u;
+            // every lane takes part in the fetches
+            int a[6], e[6];
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                a[h] = lane_int(ca[h], c);
+                e[h] = lane_int(cv[h], c) + lane_int(cb[h], c) * (int)y;
+            }
+            if (any6) {
+#pragma unroll
+                for (int h = 4; h < 6; h++) {
+                    a[h] = lane_int(ca[h], c);
+                    e[h] = lane_int(cv[h], c) + lane_int(cb[h], c) * (int)y;
+                }
+            }
+            const bool c4 = !any6 || lane_int((int)cvx, c) != 0;
+            if (i < tot)
+                rows[8 * c + y] = (uint8_t)(c4 ? row_walk<4>(a, e) : row_walk<6>(a, e));
+        }
+        wave_sync();
+        if (nr)
+            mk = W.mask[lane];
+    }
+    if (wide)
+        mk = wide_block_mask(rec[q].flags, xyp[q], px0, py0);
+    return mk;
 }
 
 // Single-sample coverage (one lane, one quad), same rule.
@@ -1106,13 +1208,20 @@ union WaveKeys {
 static_assert(sizeof(FastEntries) <= sizeof(uint32_t) * kSortCap, "fast entries alias the key array");
 
 // Per-wave LDS of the sorted raster: candidate batch, sort keys of the
-// current slice (also the slicing histogram) or the fast entries, phase-3
-// staging in sorted order.
+// current slice (also the slicing histogram) or the fast entries, and the
+// phase-3 staging in sorted order, whose space the coverage pass of each
+// phase-1 batch borrows.
+struct WalkStage {
+    Stage st[64];
+    uint32_t sid[64];
+};
 struct WaveLds {
     uint32_t cand[128];
     WaveKeys k;
-    Stage stage[64];
-    uint32_t sid[64];
+    union {
+        WalkStage w;  // phase 3
+        RowWork rw;   // phase 1: coverage masks of a batch
+    } s;
 };
 
 // A workgroup's window on its bin list: the whole list when it has at most
@@ -1355,11 +1464,11 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
     uint64_t m0 = 0, m1 = 0;  // entries: m0 (whole block, or rows 0-3), m1 (rows 4-7)
     uint32_t q = 0, c0 = 0, c1 = 0;
     const QuadRec *rp = rec;
+    const uint64_t mk = batch_masks(rec, xyp, L.cand, L.s.rw, m, g.px0, g.py0, lane) & g.onmask;
     if (lane < m) {
         q = L.cand[lane];
         rp = rec + q;
         const QuadRec &r = *rp;
-        const uint64_t mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
         m0 = half ? (mk & 0xFFFFFFFFull) : mk;
         m1 = half ? (mk & ~0xFFFFFFFFull) : 0;
         if (m0)
@@ -1416,9 +1525,9 @@ __device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec
             st.C0 = r.C0;
             st.ij = (r.bb_i & 0xffffu) | (r.bb_j << 16);
             st.rgba = r.rgba;
-            L.stage[lane] = st;
+            L.s.w.st[lane] = st;
             if (DEBUG)
-                L.sid[lane] = q;
+                L.s.w.sid[lane] = q;
         }
         wave_sync();
         uint64_t col = transpose64(m, lane);
@@ -1427,10 +1536,10 @@ __device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec
         while (col) {
             const uint32_t k = (uint32_t)__builtin_ctzll(col);
             col &= col - 1;
-            const Stage st = L.stage[k];
+            const Stage st = L.s.w.st[k];
             const float kf =
                 frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
-            ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.sid[k] : 0);
+            ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.s.w.sid[k] : 0);
             if (ps.flagged)
                 col = 0;
         }
@@ -1468,9 +1577,9 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
     if (lane < n) {
         const uint32_t slot = key & ((1u << sb) - 1);
         m = L.k.f.mask[slot];
-        L.stage[lane] = L.k.f.st[slot];
+        L.s.w.st[lane] = L.k.f.st[slot];
         if (DEBUG)
-            L.sid[lane] = L.k.f.id[slot];
+            L.s.w.sid[lane] = L.k.f.id[slot];
     }
     wave_sync();
     uint64_t col = transpose64(m, lane);
@@ -1479,9 +1588,9 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
     while (col) {
         const uint32_t k = (uint32_t)__builtin_ctzll(col);
         col &= col - 1;
-        const Stage st = L.stage[k];
+        const Stage st = L.s.w.st[k];
         const float kf = frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
-        ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.sid[k] : 0);
+        ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.s.w.sid[k] : 0);
         if (ps.flagged)
             col = 0;
     }
@@ -1587,7 +1696,7 @@ __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t la
 // Sorted raster: one workgroup of NW waves per bin, one 8x8 block per wave
 // per round.
 template <int K, bool DEBUG, class Src, int NW>
-__global__ __launch_bounds__(NW * 64) void k_raster(Src src)
+__global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster(Src src)
 {
     __shared__ BinChunk<NW> C;
     __shared__ WaveLds Lw[NW];
@@ -1714,12 +1823,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
             continue;
         // the frame's flagged pixels: one queue stripe per lane (kQueues == 64)
         const uint32_t cq = a.ctr->stripe[lane].flag_n;
-        uint32_t incl = cq;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
-            if (lane >= (uint32_t)off)
-                incl += v;
-        }
+        const uint32_t incl = wave_incl_scan(cq);
         const uint32_t count = lane_value(incl, 63);
         for (;;) {
             uint32_t item = 0;
@@ -1839,6 +1943,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
 struct UnsortedLds {
     uint32_t cand[128];
     uint32_t col[64];
+    RowWork rw;
 };
 
 template <int NW, bool DEBUG, class Src>
@@ -1871,13 +1976,9 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
         float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
         uint32_t nfrag = 0, ntot = 0;
         scan_bin<NW>(bbox, pairs, C, U, start, cnt, cached, g, [&](uint32_t m) {
-            uint64_t mk = 0;
-            if (lane < m) {
-                const uint32_t q = U.cand[lane];
-                const QuadRec &r = rec[q];
-                mk = lane_block_mask(r, xyp, q, g.px0, g.py0) & g.onmask;
-                U.col[lane] = r.rgba;
-            }
+            const uint64_t mk = batch_masks(rec, xyp, U.cand, U.rw, m, g.px0, g.py0, lane) & g.onmask;
+            if (lane < m)
+                U.col[lane] = rec[U.cand[lane]].rgba;
             ntot += (uint32_t)__popcll(ballot(mk != 0));
             wave_sync();
             uint64_t bits = transpose64(mk, lane);
@@ -1982,12 +2083,15 @@ template <int K, bool DEBUG>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     const OneFrame f{a};
-    const uint32_t nw = raster_waves_for(a.bin_shift, K);
+    // the parity dump keeps one more id per sorter slot: past depth 4 its
+    // kernels do not fit 16 waves' registers and take 8 (the image is the same)
+    constexpr bool wide_dbg = DEBUG && K > 4;
+    const uint32_t nw = min(raster_waves_for(a.bin_shift, K), wide_dbg ? 8u : 16u);
     if (nw == 4)
         hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4>), dim3(a.nbins), dim3(4 * 64), 0, s, f);
     else if (nw == 8)
         hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8>), dim3(a.nbins), dim3(8 * 64), 0, s, f);
-    else if constexpr (K <= 12)
+    else if constexpr (K <= 12 && !wide_dbg)
         hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16>), dim3(a.nbins), dim3(16 * 64), 0, s, f);
     if (ev) {
         (void)hipEventRecord(ev[5], s);
