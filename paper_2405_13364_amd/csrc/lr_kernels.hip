@@ -1001,41 +1001,38 @@ __device__ __forceinline__ int lane_int(int v, uint32_t src_lane)
 // batches (large quads, most rows covered) walk eight rows per candidate.
 constexpr uint32_t kRowPasses = 4;
 
-// Coverage masks of a batch of m candidates (lane e < m: quad cand[e]) over
-// the 8x8 block at (px0, py0), bit 8y + x for pixel (px0 + x, py0 + y).
+// Coverage masks of a batch of candidates (lanes with `has`: quad q, its
+// record r already in registers) over the 8x8 block at (px0, py0), bit
+// 8y + x for pixel (px0 + x, py0 + y).
 // Only the rows that a candidate's bbox meets can be covered.  When those
 // (candidate, row) pairs fill at most kRowPasses waves' worth, they are
 // listed and spread over the lanes, one row walk each, with each
 // candidate's edge values fetched from its own lane; otherwise every
-// candidate's lane walks the eight rows itself.  A wide quad (rare) is done
-// sample by sample by its own lane.  Returns lane e's mask.
-__device__ __forceinline__ uint64_t batch_masks(const QuadRec *__restrict__ rec, const QuadXY *__restrict__ xyp,
-                                const uint32_t *cand, RowWork &W, uint32_t m, int px0, int py0, uint32_t lane)
+// candidate's lane walks the eight rows itself.  The four edges of a convex
+// quad stay in registers; the two more of a triangle pair (rare) are read
+// again from its record.  A wide quad (rarer) is done sample by sample by
+// its own lane.  Returns this lane's mask.
+__device__ __forceinline__ uint64_t batch_masks(const QuadRec &r, bool has, const QuadRec *__restrict__ rec,
+                                                const QuadXY *__restrict__ xyp, uint32_t q, RowWork &W, int px0,
+                                                int py0, uint32_t lane)
 {
-    // candidate lane: per half-plane h the step a, the row step b and the
-    // value at (x = 7, y = 0) of the block
-    int ca[6], cb[6], cv[6];
-    uint32_t q = 0, nr = 0, y0 = 0, cvx = 1;
+    // candidate lane: per edge h < 4 the step a, the row step b and the value
+    // at (x = 7, y = 0) of the block; di, dj of that sample
+    int ca[4] = {0, 0, 0, 0}, cb[4] = {0, 0, 0, 0}, cv[4] = {0, 0, 0, 0};
+    int di = 0, dj = 0;
+    uint32_t nr = 0, y0 = 0, cvx = 1;
     bool wide = false;
-#pragma unroll
-    for (int h = 0; h < 6; h++)
-        ca[h] = cb[h] = cv[h] = 0;
-    if (lane < m) {
-        q = cand[lane];
-        const QuadRec &r = rec[q];
+    if (has) {
         wide = (r.flags & kWide) != 0;
         cvx = (r.flags & kConvex) ? 1u : 0u;
         if (!wide) {
-            const int di = px0 + 7 - (int)(r.bb_i & 0xffffu);
-            const int dj = py0 - (int)(r.bb_j & 0xffffu);
-            const int ne = cvx ? 4 : 6;
+            di = px0 + 7 - (int)(r.bb_i & 0xffffu);
+            dj = py0 - (int)(r.bb_j & 0xffffu);
 #pragma unroll
-            for (int h = 0; h < 6; h++) {
-                if (h < ne) {
-                    ca[h] = r.hp[3 * h];
-                    cb[h] = r.hp[3 * h + 1];
-                    cv[h] = ca[h] * di + cb[h] * dj - r.hp[3 * h + 2];
-                }
+            for (int h = 0; h < 4; h++) {
+                ca[h] = r.hp[3 * h];
+                cb[h] = r.hp[3 * h + 1];
+                cv[h] = ca[h] * di + cb[h] * dj - r.hp[3 * h + 2];
             }
             // the bbox meets the block, so rows y0..y1 are within 0..7
             const int y1 = min((int)(r.bb_j >> 16) - py0, 7);
@@ -1055,14 +1052,31 @@ __device__ __forceinline__ uint64_t batch_masks(const QuadRec *__restrict__ rec,
     uint64_t mk = 0;
     if (tot > kRowPasses * 64) {
         if (nr) {
+            int a6[6], b6[6], v6[6];
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                a6[h] = ca[h];
+                b6[h] = cb[h];
+                v6[h] = cv[h];
+            }
+            a6[4] = a6[5] = b6[4] = b6[5] = v6[4] = v6[5] = 0;
+            if (!cvx) {
+                const int *hp = rec[q].hp;
+#pragma unroll
+                for (int h = 4; h < 6; h++) {
+                    a6[h] = hp[3 * h];
+                    b6[h] = hp[3 * h + 1];
+                    v6[h] = a6[h] * di + b6[h] * dj - hp[3 * h + 2];
+                }
+            }
             uint32_t lo = 0, hi = 0;
 #pragma unroll 1
             for (uint32_t y = 0; y < 8; y++) {
                 int e[6];
 #pragma unroll
                 for (int h = 0; h < 6; h++)
-                    e[h] = cv[h] + cb[h] * (int)y;
-                const uint32_t bits = cvx ? row_walk<4>(ca, e) : row_walk<6>(ca, e);
+                    e[h] = v6[h] + b6[h] * (int)y;
+                const uint32_t bits = cvx ? row_walk<4>(a6, e) : row_walk<6>(a6, e);
                 if (y < 4)
                     lo |= bits << (8 * y);
                 else
@@ -1087,14 +1101,21 @@ __device__ __forceinline__ uint64_t batch_masks(const QuadRec *__restrict__ rec,
                 a[h] = lane_int(ca[h], c);
                 e[h] = lane_int(cv[h], c) + lane_int(cb[h], c) * (int)y;
             }
+            bool c4 = true;
             if (any6) {
+                const uint32_t qc = (uint32_t)lane_int((int)q, c);
+                const int dic = lane_int(di, c), djc = lane_int(dj, c) + (int)y;
+                c4 = lane_int((int)cvx, c) != 0;
+                a[4] = a[5] = e[4] = e[5] = 0;
+                if (i < tot && !c4) {
+                    const int *hp = rec[qc].hp;
 #pragma unroll
-                for (int h = 4; h < 6; h++) {
-                    a[h] = lane_int(ca[h], c);
-                    e[h] = lane_int(cv[h], c) + lane_int(cb[h], c) * (int)y;
+                    for (int h = 4; h < 6; h++) {
+                        a[h] = hp[3 * h];
+                        e[h] = a[h] * dic + hp[3 * h + 1] * djc - hp[3 * h + 2];
+                    }
                 }
             }
-            const bool c4 = !any6 || lane_int((int)cvx, c) != 0;
             if (i < tot)
                 rows[8 * c + y] = (uint8_t)(c4 ? row_walk<4>(a, e) : row_walk<6>(a, e));
         }
@@ -1103,7 +1124,7 @@ __device__ __forceinline__ uint64_t batch_masks(const QuadRec *__restrict__ rec,
             mk = W.mask[lane];
     }
     if (wide)
-        mk = wide_block_mask(rec[q].flags, xyp[q], px0, py0);
+        mk = wide_block_mask(r.flags, xyp[q], px0, py0);
     return mk;
 }
 
@@ -1144,7 +1165,8 @@ __device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t 
     const float inv = 1.0f / cnt;
     const float cx = (float)(px0 - (int)(r.bb_i & 0xffffu)) + sx * inv;
     const float cy = (float)(py0 - (int)(r.bb_j & 0xffffu)) + sy * inv;
-    float k = r.fA * cx + r.fB * cy + r.fC0;
+    // the fp32 plane (the stored fA, fB, fC0 are these same roundings)
+    float k = (float)r.A * cx + (float)r.B * cy + (float)r.C0;
     k = (k > 0.0f) ? k : 0.0f;  // NaN -> 0
     return 0x7F800000u - min(__float_as_uint(k), 0x7F800000u);  // < 2^31
 }
@@ -1424,10 +1446,11 @@ struct PixelSorter {
 };
 
 // Phase 1 of the sorted path for one batch: each lane takes a candidate,
-// builds its coverage mask of the block and, if not empty, its block key;
-// non-empty entries go to the wave's global entry region at slot n + rank,
-// and the first kSortCap also to the LDS sort keys (key bits above the slot
-// index).  kmin / kmax track the key range.
+// its coverage mask of the block comes from batch_masks and, if not empty,
+// the lane builds its block key; non-empty entries take slot n + rank, on
+// chip while the block has at most kFast of them and in the wave's global
+// entry region beyond, and the first kSortCap also go to the LDS sort keys
+// (key bits above the slot index).
 //
 // With half-blocks, the rows 0-3 and 4-7 of a mask become separate entries,
 // each keyed at the centroid of its own samples: one sort then orders both
@@ -1459,16 +1482,20 @@ __device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32
 __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *__restrict__ rec,
                                              const QuadXY *__restrict__ xyp, WaveLds &L, uint32_t m,
                                              const BlockGeom &g, uint32_t lane, uint32_t ebase, uint32_t sb,
-                                             bool half, uint32_t &n, uint32_t &kmin, uint32_t &kmax)
+                                             bool half, uint32_t &n)
 {
     uint64_t m0 = 0, m1 = 0;  // entries: m0 (whole block, or rows 0-3), m1 (rows 4-7)
     uint32_t q = 0, c0 = 0, c1 = 0;
-    const QuadRec *rp = rec;
-    const uint64_t mk = batch_masks(rec, xyp, L.cand, L.s.rw, m, g.px0, g.py0, lane) & g.onmask;
-    if (lane < m) {
+    // the candidate's whole record, loaded at once (one memory latency for
+    // the masks, the block keys and the entries)
+    QuadRec r;
+    const bool has = lane < m;
+    if (has) {
         q = L.cand[lane];
-        rp = rec + q;
-        const QuadRec &r = *rp;
+        r = rec[q];
+    }
+    const uint64_t mk = batch_masks(r, has, rec, xyp, q, L.s.rw, g.px0, g.py0, lane) & g.onmask;
+    if (has) {
         m0 = half ? (mk & 0xFFFFFFFFull) : mk;
         m1 = half ? (mk & ~0xFFFFFFFFull) : 0;
         if (m0)
@@ -1487,17 +1514,9 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
         a.ent_id[ebase + lane] = L.k.f.id[lane];
     }
     if (m0)
-        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, *rp, to_global);
+        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, r, to_global);
     if (m1)
-        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, *rp, to_global);
-    uint32_t mn = min(m0 ? c0 : 0xFFFFFFFFu, m1 ? c1 : 0xFFFFFFFFu);
-    uint32_t mx = max(m0 ? c0 : 0u, m1 ? c1 : 0u);
-    for (int off = 32; off > 0; off >>= 1) {
-        mn = min(mn, shfl_xor(mn, off));
-        mx = max(mx, shfl_xor(mx, off));
-    }
-    kmin = min(kmin, mn);
-    kmax = max(kmax, mx);
+        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, r, to_global);
     n += n0 + (uint32_t)__popcll(b1);
 }
 
@@ -1551,6 +1570,10 @@ __device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec
 // over lane indices, exchanges by cross-lane permutes).
 __device__ __forceinline__ uint32_t wave_sort_reg(uint32_t v, uint32_t lane)
 {
+    // an opaque copy of the lane index: the network's per-step lane masks are
+    // then formed where they are used instead of being hoisted to the kernel
+    // start, where they would hold 21 scalar register pairs for its lifetime
+    asm volatile("" : "+v"(lane));
 #pragma unroll
     for (uint32_t k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -1606,9 +1629,19 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
 // more than kSortCap entries.
 template <int K, bool DEBUG>
 __device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds &L, uint32_t n,
-                            uint32_t ebase, uint32_t sb, uint32_t kmin, uint32_t kmax, const BlockGeom &g,
-                            uint32_t lane, PixelSorter<K, DEBUG> &ps)
+                            uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
 {
+    // the key range of the block's entries
+    uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
+    for (uint32_t e = lane; e < n; e += 64) {
+        const uint32_t c = a.ent_code[ebase + e];
+        kmin = min(kmin, c);
+        kmax = max(kmax, c);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        kmin = min(kmin, shfl_xor(kmin, off));
+        kmax = max(kmax, shfl_xor(kmax, off));
+    }
     const uint32_t span = kmax - kmin;  // < 2^31
     const uint32_t bits = span ? 32 - __builtin_clz(span) : 1;
     const uint32_t hs = bits > 8 ? bits - 8 : 0;  // bucket = (code - kmin) >> hs, in [0, 256)
@@ -1668,7 +1701,7 @@ __device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec,
 // queue, and the wave's running statistics.
 template <int K, bool DEBUG>
 __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps,
-                             uint32_t entries, unsigned long long &st_ent, unsigned long long &st_frag)
+                             uint32_t entries)
 {
     if (g.on && !ps.flagged)
         ps.flush(a, g.on);
@@ -1689,8 +1722,13 @@ __device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t la
     uint32_t wsum = write ? ps.nfrag : 0;
     for (int off = 32; off > 0; off >>= 1)
         wsum += shfl_xor(wsum, off);
-    st_ent += entries;
-    st_frag += wsum;
+    // added per block: per-wave totals would hold registers through the walk
+    if (lane == 0) {
+        if (entries)
+            add_stat(a.ctr, ST_ENTRIES, entries);
+        if (wsum)
+            add_stat(a.ctr, ST_FRAGMENTS, wsum);
+    }
 }
 
 // Sorted raster: one workgroup of NW waves per bin, one 8x8 block per wave
@@ -1722,14 +1760,13 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
     const bool cached = cnt <= list_cap(NW);
     if (cached)
         load_bin_list<NW>(bbox, pairs, C, start, cnt);
-    unsigned long long st_ent = 0, st_frag = 0;
     const uint32_t nrounds = (nb + NW - 1) / NW;
     for (uint32_t ri = 0; ri < nrounds; ri++) {
         const uint32_t k = ri * NW + wave;
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
-        uint32_t n = 0, kmin = 0xFFFFFFFFu, kmax = 0;
+        uint32_t n = 0;
         scan_bin<NW>(bbox, pairs, C, L, start, cnt, cached, g, [&](uint32_t m) {
-            sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, half, n, kmin, kmax);
+            sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, half, n);
         });
         if (g.active) {
             PixelSorter<K, DEBUG> ps;
@@ -1744,7 +1781,7 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
                 } else {
                     if (lane == 0)
                         atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
-                    if (!walk_sliced<K, DEBUG>(a, rec, L, n, ebase, sb, kmin, kmax, g, lane, ps)) {
+                    if (!walk_sliced<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps)) {
                         // no slice fits: the exact path takes the block
                         ps.flagged = true;
                         if (lane == 0)
@@ -1752,14 +1789,8 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
                     }
                 }
             }
-            finish_block<K, DEBUG>(a, g, lane, ps, n, st_ent, st_frag);
+            finish_block<K, DEBUG>(a, g, lane, ps, n);
         }
-    }
-    if (lane == 0) {
-        if (st_ent)
-            add_stat(a.ctr, ST_ENTRIES, st_ent);
-        if (st_frag)
-            add_stat(a.ctr, ST_FRAGMENTS, st_frag);
     }
 }
 
@@ -1976,9 +2007,16 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
         float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
         uint32_t nfrag = 0, ntot = 0;
         scan_bin<NW>(bbox, pairs, C, U, start, cnt, cached, g, [&](uint32_t m) {
-            const uint64_t mk = batch_masks(rec, xyp, U.cand, U.rw, m, g.px0, g.py0, lane) & g.onmask;
-            if (lane < m)
-                U.col[lane] = rec[U.cand[lane]].rgba;
+            QuadRec r;
+            uint32_t q = 0;
+            const bool has = lane < m;
+            if (has) {
+                q = U.cand[lane];
+                r = rec[q];
+            }
+            const uint64_t mk = batch_masks(r, has, rec, xyp, q, U.rw, g.px0, g.py0, lane) & g.onmask;
+            if (has)
+                U.col[lane] = r.rgba;
             ntot += (uint32_t)__popcll(ballot(mk != 0));
             wave_sync();
             uint64_t bits = transpose64(mk, lane);
