@@ -240,20 +240,37 @@ __device__ __forceinline__ void add_stat(FrameCounters *c, uint32_t stat, unsign
 
 // ------------------------------------------------------------------- setup
 
-__device__ __forceinline__ int64_t edge_fn(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t px,
-                                           int64_t py)
+// Integer geometry of snapped vertices in fp64.  A guarded vertex lies
+// within 32768 px of the origin, so its sub-pixel coordinates are integers
+// below 2^23 in magnitude, differences of them below 2^24, and every
+// product below and difference of products below 2^50: all exact in fp64,
+// whose multiply runs at full rate where a 64-bit integer multiply takes
+// several quarter-rate ones.  The values are the integer ones.
+__device__ __forceinline__ double edge_fn(double ax, double ay, double bx, double by, double px, double py)
 {
     return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
 }
 
-// Half-planes of triangle (ia, ib, ic) relative to sample R = (Rx, Ry).
-__device__ void tri_halfplanes(const int32_t *X, const int32_t *Y, int ia, int ib, int ic, int64_t Rx,
-                               int64_t Ry, int32_t *hp, uint32_t &flags, uint32_t valid_bit,
-                               uint32_t swap_bit)
+// Threshold t of an edge from (sx, sy) along (dx, dy) for the pixel-centre
+// sample R: with E the edge function in sub-pixel units, a sample is inside
+// iff E(S) >= bias (0 on top-left edges, 1 otherwise), and E(S) = E(R) +
+// 256 (a di + b dj), so t = ceil((bias - E(R)) / 256), clamped to int32.
+__device__ __forceinline__ int32_t edge_threshold(double sx, double sy, double dx, double dy, double Rx, double Ry)
 {
-    int64_t vx[3] = {X[ia], X[ib], X[ic]}, vy[3] = {Y[ia], Y[ib], Y[ic]};
-    int64_t area2 = edge_fn(vx[0], vy[0], vx[1], vy[1], vx[2], vy[2]);
-    if (area2 == 0) {
+    const bool top_left = (dy < 0.0) || (dy == 0.0 && dx > 0.0);
+    const double er = dx * (Ry - sy) - dy * (Rx - sx);
+    const double t = ceil(((top_left ? 0.0 : 1.0) - er) * (1.0 / 256.0));
+    return (int32_t)fmin(fmax(t, (double)INT32_MIN), (double)INT32_MAX);
+}
+
+// Half-planes of triangle (ia, ib, ic) relative to sample R = (Rx, Ry).
+__device__ void tri_halfplanes(const int32_t *X, const int32_t *Y, int ia, int ib, int ic, double Rx, double Ry,
+                               int32_t *hp, uint32_t &flags, uint32_t valid_bit, uint32_t swap_bit)
+{
+    double vx[3] = {(double)X[ia], (double)X[ib], (double)X[ic]};
+    double vy[3] = {(double)Y[ia], (double)Y[ib], (double)Y[ic]};
+    const double area2 = edge_fn(vx[0], vy[0], vx[1], vy[1], vx[2], vy[2]);
+    if (area2 == 0.0) {
         for (int e = 0; e < 3; e++) {
             hp[3 * e] = 0;
             hp[3 * e + 1] = 0;
@@ -262,37 +279,38 @@ __device__ void tri_halfplanes(const int32_t *X, const int32_t *Y, int ia, int i
         return;
     }
     flags |= valid_bit;
-    if (area2 < 0) {
+    if (area2 < 0.0) {
         flags |= swap_bit;
-        int64_t tx = vx[1], ty = vy[1];
-        vx[1] = vx[2]; vy[1] = vy[2];
-        vx[2] = tx; vy[2] = ty;
+        const double tx = vx[1], ty = vy[1];
+        vx[1] = vx[2];
+        vy[1] = vy[2];
+        vx[2] = tx;
+        vy[2] = ty;
     }
     for (int e = 0; e < 3; e++) {
-        int64_t sx = vx[e], sy = vy[e], ex = vx[(e + 1) % 3], ey = vy[(e + 1) % 3];
-        int64_t dx = ex - sx, dy = ey - sy;
-        bool top_left = (dy < 0) || (dy == 0 && dx > 0);
-        int64_t er = dx * (Ry - sy) - dy * (Rx - sx);
-        int64_t num = (top_left ? 0 : 1) - er;
-        int64_t t = -((-num) >> 8);  // ceil(num / 256)
-        if (t > INT32_MAX) t = INT32_MAX;
-        if (t < INT32_MIN) t = INT32_MIN;
+        const double sx = vx[e], sy = vy[e];
+        const double dx = vx[(e + 1) % 3] - sx, dy = vy[(e + 1) % 3] - sy;
         hp[3 * e] = (int32_t)(-dy);
         hp[3 * e + 1] = (int32_t)dx;
-        hp[3 * e + 2] = (int32_t)t;
+        hp[3 * e + 2] = edge_threshold(sx, sy, dx, dy, Rx, Ry);
     }
 }
 
 // A strictly convex quad (all four corner turns of one sign) gets its four
 // outer edges, oriented to positive area, in hp[0..11] and kConvex.
-__device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, int64_t Rx, int64_t Ry, int32_t *hp,
+__device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, double Rx, double Ry, int32_t *hp,
                                   uint32_t &flags)
 {
+    double fx[4], fy[4];
+    for (int k = 0; k < 4; k++) {
+        fx[k] = (double)X[k];
+        fy[k] = (double)Y[k];
+    }
     int sgn[4];
     for (int k = 0; k < 4; k++) {
         const int p = k, q = (k + 1) & 3, r = (k + 2) & 3;
-        const int64_t t = edge_fn(X[p], Y[p], X[q], Y[q], X[r], Y[r]);
-        sgn[k] = (t > 0) - (t < 0);
+        const double t = edge_fn(fx[p], fy[p], fx[q], fy[q], fx[r], fy[r]);
+        sgn[k] = (t > 0.0) - (t < 0.0);
     }
     const bool pos = sgn[0] > 0 && sgn[1] > 0 && sgn[2] > 0 && sgn[3] > 0;
     const bool neg = sgn[0] < 0 && sgn[1] < 0 && sgn[2] < 0 && sgn[3] < 0;
@@ -303,16 +321,10 @@ __device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, int64_t Rx
         // positive orientation: P0 P1 P2 P3, or reversed P0 P3 P2 P1
         const int s0 = pos ? e : (4 - e) & 3;
         const int s1 = pos ? (e + 1) & 3 : (3 - e) & 3;
-        const int64_t sx = X[s0], sy = Y[s0], dx = (int64_t)X[s1] - sx, dy = (int64_t)Y[s1] - sy;
-        const bool top_left = (dy < 0) || (dy == 0 && dx > 0);
-        const int64_t er = dx * (Ry - sy) - dy * (Rx - sx);
-        const int64_t num = (top_left ? 0 : 1) - er;
-        int64_t t = -((-num) >> 8);  // ceil(num / 256)
-        if (t > INT32_MAX) t = INT32_MAX;
-        if (t < INT32_MIN) t = INT32_MIN;
+        const double sx = fx[s0], sy = fy[s0], dx = fx[s1] - sx, dy = fy[s1] - sy;
         h[3 * e] = (int32_t)(-dy);
         h[3 * e + 1] = (int32_t)dx;
-        h[3 * e + 2] = (int32_t)t;
+        h[3 * e + 2] = edge_threshold(sx, sy, dx, dy, Rx, Ry);
     }
     for (int k = 0; k < 12; k++)
         hp[k] = h[k];
@@ -364,24 +376,27 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                 // snapped vertices are kept for the fp64 path of wide quads and
                 // for the parity dump
                 bool keep_xy = a.want_xy != 0;
-                int64_t a0 = edge_fn(xy.X[0], xy.Y[0], xy.X[1], xy.Y[1], xy.X[2], xy.Y[2]);
-                int64_t a1 = edge_fn(xy.X[0], xy.Y[0], xy.X[2], xy.Y[2], xy.X[3], xy.Y[3]);
-                if (a0 == 0 && a1 == 0) {
+                const double X0 = xy.X[0], Y0 = xy.Y[0], X1 = xy.X[1], Y1 = xy.Y[1];
+                const double X2 = xy.X[2], Y2 = xy.Y[2], X3 = xy.X[3], Y3 = xy.Y[3];
+                const double a0 = edge_fn(X0, Y0, X1, Y1, X2, Y2);
+                const double a1 = edge_fn(X0, Y0, X2, Y2, X3, Y3);
+                if (a0 == 0.0 && a1 == 0.0) {
                     reason = DEGENERATE;
                 } else {
-                    int64_t xmin = xy.X[0], xmax = xy.X[0], ymin = xy.Y[0], ymax = xy.Y[0];
+                    // |X|, |Y| < 2^23: 32-bit integer arithmetic is exact here
+                    int32_t xmin = xy.X[0], xmax = xy.X[0], ymin = xy.Y[0], ymax = xy.Y[0];
                     for (int k = 1; k < 4; k++) {
-                        xmin = min(xmin, (int64_t)xy.X[k]);
-                        xmax = max(xmax, (int64_t)xy.X[k]);
-                        ymin = min(ymin, (int64_t)xy.Y[k]);
-                        ymax = max(ymax, (int64_t)xy.Y[k]);
+                        xmin = min(xmin, xy.X[k]);
+                        xmax = max(xmax, xy.X[k]);
+                        ymin = min(ymin, xy.Y[k]);
+                        ymax = max(ymax, xy.Y[k]);
                     }
-                    int64_t imin = (xmin - 128 + 255) >> 8, imax = (xmax - 128) >> 8;
-                    int64_t jmin = (ymin - 128 + 255) >> 8, jmax = (ymax - 128) >> 8;
-                    imin = max(imin, (int64_t)0);
-                    jmin = max(jmin, (int64_t)0);
-                    imax = min(imax, (int64_t)a.W - 1);
-                    jmax = min(jmax, (int64_t)a.H - 1);
+                    int32_t imin = (xmin - 128 + 255) >> 8, imax = (xmax - 128) >> 8;
+                    int32_t jmin = (ymin - 128 + 255) >> 8, jmax = (ymax - 128) >> 8;
+                    imin = max(imin, 0);
+                    jmin = max(jmin, 0);
+                    imax = min(imax, (int32_t)a.W - 1);
+                    jmax = min(jmax, (int32_t)a.H - 1);
                     if (imin > imax || jmin > jmax) {
                         reason = NO_SAMPLE;
                     } else {
@@ -415,7 +430,7 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                             uint32_t flags = 0;
                             if (xmax - xmin > kNarrowExtent || ymax - ymin > kNarrowExtent)
                                 flags |= kWide;
-                            const int64_t Rx = 256 * imin + 128, Ry = 256 * jmin + 128;
+                            const double Rx = 256.0 * imin + 128.0, Ry = 256.0 * jmin + 128.0;
                             // a narrow strictly convex quad needs its four outer
                             // edges only; the others their triangles' six
                             if (!(flags & kWide))
