@@ -651,40 +651,38 @@ __device__ __forceinline__ void clear_next_counters(const FrameArgs &a, uint32_t
 constexpr uint32_t kScatterGroup = 512;
 
 // Scatters the pairs of one group of 64 consecutive quads (lane l holds the
-// bbox of quad base + l) into their bin lists: pair p of the group belongs to
-// the first lane whose inclusive prefix of pair counts exceeds p; lanes whose
-// pairs share a bin take consecutive slots in lane order from one LDS atomic
-// on offs[bin], so every bin list stays in ascending quad order.
+// bbox of quad base + l) into their bin lists, 64 pairs at a time: the
+// group's pairs are numbered quad by quad (exclusive prefix of the pair
+// counts), each quad's lane marks the window slots of its own pairs, and
+// each lane then takes the pair of its slot; lanes whose pairs share a bin
+// take consecutive slots in lane order from one LDS atomic on offs[bin], so
+// every bin list stays in ascending quad order.
 __device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
-                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t lane)
+                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane)
 {
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
     quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
-    // inclusive prefix of np over the wave
+    // exclusive prefix of np over the wave: the chunk's pair pre .. pre + np - 1
+    // belong to this lane's quad
     const uint32_t incl = wave_incl_scan(np);
-    const uint32_t total = lane_value(incl, 63);
-    s_pref[lane] = incl;
+    const uint32_t total = lane_value(incl, 63), pre = incl - np;
+    s_pref[lane] = pre;
     s_rect[lane][0] = bx0;
     s_rect[lane][1] = by0;
     s_rect[lane][2] = bw;
-    wave_sync();
     for (uint32_t w = 0; w < total; w += 64) {
+        // owners of the window's 64 pairs, marked by the quads' lanes
+        for (uint32_t p = max(pre, w); p < min(pre + np, w + 64); p++)
+            s_own[p - w] = lane;
+        wave_sync();
         const uint32_t p = w + lane;
         const bool valid = p < total;
         uint32_t bin = 0, qv = 0;
         if (valid) {
-            // owning quad: first lane whose inclusive prefix exceeds p
-            uint32_t lo = 0, hi = 63;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi) >> 1;
-                if (s_pref[mid] > p)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            uint32_t k = p - (lo ? s_pref[lo - 1] : 0);
-            uint32_t rbw = s_rect[lo][2];
+            const uint32_t lo = s_own[lane];
+            const uint32_t k = p - s_pref[lo];
+            const uint32_t rbw = s_rect[lo][2];
             bin = (s_rect[lo][1] + k / rbw) * a.nbx + s_rect[lo][0] + k % rbw;
             qv = base + lo;
         }
@@ -704,6 +702,7 @@ __device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uin
         const uint32_t pos = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(leader << 2), (int)base_off) + rank;
         if (valid && pos < a.pair_cap)
             a.pairs[pos] = qv;
+        wave_sync();  // the window's owners are read before the next window marks its own
     }
     wave_sync();
 }
@@ -730,6 +729,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
     extern __shared__ uint32_t s_off[];
     __shared__ uint32_t s_pref[64];
     __shared__ uint32_t s_rect[64][3];
+    __shared__ uint32_t s_own[64];
     __shared__ uint2 s_bb[kScatterGroup];
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
@@ -781,7 +781,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
                 s_bb[64 * k + lane] = bb[k];
             wave_sync();
         }
-        scatter_chunk(a, s_bb[(base - q0) % kScatterGroup + lane], base, s_off, s_pref, s_rect, lane);
+        scatter_chunk(a, s_bb[(base - q0) % kScatterGroup + lane], base, s_off, s_pref, s_rect, s_own, lane);
         wave_sync();  // one wave per workgroup
     }
 }
@@ -841,7 +841,8 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
     extern __shared__ uint32_t s_offs[];  // [kBin4Waves][nbins]
     __shared__ uint32_t s_pref[kBin4Waves][64];
     __shared__ uint32_t s_rect[kBin4Waves][64][3];
-    __shared__ uint32_t s_part[kBin4Waves * 64];
+    __shared__ uint32_t s_own[kBin4Waves][64];
+    __shared__ uint32_t s_part[kBin4Waves];
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
     const uint2 *__restrict__ bbox = a.bbox;
@@ -875,37 +876,57 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
     const uint32_t run_len = (nbins + kBin4Waves * 64 - 1) / (kBin4Waves * 64);
     const uint32_t b0 = min(t * run_len, nbins), b1 = min(b0 + run_len, nbins);
     uint32_t sum = 0;
-    for (uint32_t b = b0; b < b1; b++)
-        sum += a.bin_count[b];
-    s_part[t] = sum;
+    for (uint32_t b = b0; b < b1; b += kBinPrefetch) {
+        uint32_t c[kBinPrefetch];
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++)
+            c[k] = b + k < b1 ? a.bin_count[b + k] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++)
+            sum += c[k];
+    }
+    // exclusive prefix of the run sums: within each wave, then over waves
+    const uint32_t incl = wave_incl_scan(sum);
+    if (lane == 63)
+        s_part[wave] = incl;
     __syncthreads();
-    for (uint32_t off = 1; off < kBin4Waves * 64; off <<= 1) {
-        const uint32_t v = t >= off ? s_part[t - off] : 0;
-        __syncthreads();
-        s_part[t] += v;
-        __syncthreads();
+    uint32_t start = incl - sum, total = 0;
+    for (uint32_t w = 0; w < kBin4Waves; w++) {
+        const uint32_t ws = s_part[w];
+        start += w < wave ? ws : 0u;
+        total += ws;
     }
-    uint32_t start = t ? s_part[t - 1] : 0;
-    for (uint32_t b = b0; b < b1; b++) {
-        if (u == 0)
-            a.bin_start[b] = start;
-        uint32_t run = start + row[b];
-        for (uint32_t w = 0; w < kBin4Waves; w++) {
-            const uint32_t c = s_offs[w * nbins + b];
-            s_offs[w * nbins + b] = run;
-            run += c;
+    for (uint32_t b = b0; b < b1; b += kBinPrefetch) {
+        uint32_t c[kBinPrefetch], r[kBinPrefetch];
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            c[k] = b + k < b1 ? a.bin_count[b + k] : 0u;
+            r[k] = b + k < b1 ? row[b + k] : 0u;
         }
-        start += a.bin_count[b];
+#pragma unroll
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            if (b + k < b1) {
+                if (u == 0)
+                    a.bin_start[b + k] = start;
+                uint32_t run = start + r[k];
+                for (uint32_t w = 0; w < kBin4Waves; w++) {
+                    const uint32_t cw = s_offs[w * nbins + b + k];
+                    s_offs[w * nbins + b + k] = run;
+                    run += cw;
+                }
+                start += c[k];
+            }
+        }
     }
-    if (u == 0 && t == kBin4Waves * 64 - 1)
-        publish_total(a, s_part[t]);
+    if (u == 0 && t == 0)
+        publish_total(a, total);
     __syncthreads();
     for (uint32_t base = w0; base < w1; base += 64) {
         const uint32_t q = base + lane;
         uint2 bb = make_uint2(0xffffu, 0xffffu);
         if (q < w1)
             bb = bbox[q];
-        scatter_chunk(a, bb, base, offs, s_pref[wave], s_rect[wave], lane);
+        scatter_chunk(a, bb, base, offs, s_pref[wave], s_rect[wave], s_own[wave], lane);
     }
 }
 
