@@ -52,6 +52,26 @@ def wide_scene():
     return scenes.small(700, 500, 40, 21, side=(200.0, 1500.0), z=(1.0, 3.0), alpha=(0.2, 0.6))
 
 
+def general_quads(W=80, H=60, n=4000, seed=31, extent=(2.0, 12.0), centre=None):
+    """Fronto-parallel quads whose four corners are drawn independently in a
+    small box: convex, concave and self-intersecting (bow-tie) shapes mixed,
+    so coverage takes both the four-edge and the two-triangle path inside one
+    batch.  With a centre, every quad sits around that point (dense blocks)."""
+    rng = np.random.default_rng(seed)
+    quads = []
+    for _ in range(n):
+        if centre is None:
+            cx, cy = rng.uniform(0.0, W), rng.uniform(0.0, H)
+        else:
+            cx, cy = centre[0] + rng.uniform(-4.0, 4.0), centre[1] + rng.uniform(-4.0, 4.0)
+        e = rng.uniform(*extent)
+        corners = [(cx + rng.uniform(-e, e), cy + rng.uniform(-e, e)) for _ in range(4)]
+        rgb = rng.integers(0, 256, 3)
+        rgba = int(scenes.pack_rgba(int(rgb[0]), int(rgb[1]), int(rgb[2]), int(rng.integers(20, 236))))
+        quads.append((scenes.screen_quad(corners, float(rng.uniform(1.0, 10.0)), W, H), rgba))
+    return scenes.from_quads(quads, W, H, name="general")
+
+
 SCENES = {
     "small": lambda: scenes.small(96, 72, 3000, 11, side=(2.0, 24.0)),
     "ragged": lambda: scenes.small(101, 37, 1500, 12, side=(1.0, 30.0)),
@@ -61,6 +81,8 @@ SCENES = {
     "hand": hand_scene,
     "wide": wide_scene,
     "gauss": lambda: scenes.small(160, 120, 20000, 15, side=(1.0, 20.0), gaussian=True, alpha=(0.05, 0.5)),
+    "general": lambda: general_quads(),
+    "general_dense": lambda: general_quads(64, 48, 900, 32, extent=(2.0, 14.0), centre=(28.0, 20.0)),
 }
 
 
@@ -173,7 +195,7 @@ def test_invariance_over_sorter_depth_and_bins(lr):
     assert flagged[(8, 32, 2)] >= flagged[(8, 32, 32)]
 
 
-@pytest.mark.parametrize("name", ["gauss", "c1", "ragged", "wide"])
+@pytest.mark.parametrize("name", ["gauss", "c1", "ragged", "wide", "general", "general_dense"])
 def test_half_block_parity(lr, name):
     """8x4 half-block sort keys: counts, order and colour against the oracle."""
     sc = SCENES[name]()
