@@ -31,8 +31,7 @@ struct alignas(128) QuadRec {
     uint32_t rgba;    //                                      80
     uint32_t flags;   // kWide | triangle bits                84
     double A, B, C0;  // reciprocal-depth plane (fp64)        88..111
-    float fA, fB, fC0;// the same rounded to fp32 (block keys) 112..123
-    uint32_t pad;     //                                      124
+    uint32_t pad[4];  //                                      112..127
 };
 static_assert(sizeof(QuadRec) == 128, "QuadRec must be one 128-byte line");
 

@@ -451,10 +451,8 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                             r.A = A;
                             r.B = B;
                             r.C0 = C0;
-                            r.fA = (float)A;
-                            r.fB = (float)B;
-                            r.fC0 = (float)C0;
-                            r.pad = 0;
+                            for (int k = 0; k < 4; k++)
+                                r.pad[k] = 0;
                             a.rec[q] = r;
                             bb = make_uint2(r.bb_i, r.bb_j);
                         }
@@ -573,11 +571,15 @@ __host__ __device__ __forceinline__ uint32_t scan_groups(uint32_t nbins) { retur
 
 // Bin scan over units.  A workgroup owns 64 bins (one per lane) and walks
 // their whole columns of table[u][b]; its 16 waves split the units.  Pass 1
-// sums each wave's share, the shares' exclusive prefix gives each wave its
-// base, and pass 2 rewrites the column as exclusive prefixes over units; the
-// column total is the bin's count.  (The prefix over bins is taken by the
-// scatter, which needs it first.)
+// sums each wave's share, each lane adds up the shares of the waves before
+// its own for its base, and pass 2 rewrites the column as exclusive prefixes
+// over units; the column total is the bin's count.  (The prefix over bins is
+// taken by the scatter, which needs it first.)
 constexpr uint32_t kScanWaves = 16;
+
+// Column values a lane keeps in registers between the two passes (when its
+// wave's share of the units is no longer, pass 2 reads nothing again).
+constexpr uint32_t kScanKeep = 32;
 
 template <class Src>
 __global__ __launch_bounds__(kScanWaves * 64) void k_bin_scan(Src src)
@@ -590,44 +592,63 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_bin_scan(Src src)
     const bool on = b < a.nbins;
     const uint32_t per = (a.nunits + kScanWaves - 1) / kScanWaves;
     const uint32_t u0 = min(wave * per, a.nunits), u1 = min(u0 + per, a.nunits);
+    const bool kept = per <= kScanKeep;
+    uint32_t keep[kScanKeep];
     uint32_t sum = 0;
     if (on) {
-        // loads of a group are issued before they are summed
-        for (uint32_t g = u0; g < u1; g += 16) {
-            uint32_t v[16];
+        if (kept) {
 #pragma unroll
-            for (int k = 0; k < 16; k++)
-                v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+            for (uint32_t k = 0; k < kScanKeep; k++)
+                keep[k] = (u0 + k < u1) ? a.table[(size_t)(u0 + k) * a.nbins + b] : 0u;
 #pragma unroll
-            for (int k = 0; k < 16; k++)
-                sum += v[k];
+            for (uint32_t k = 0; k < kScanKeep; k++)
+                sum += keep[k];
+        } else {
+            // loads of a group are issued before they are summed
+            for (uint32_t g = u0; g < u1; g += 16) {
+                uint32_t v[16];
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+#pragma unroll
+                for (int k = 0; k < 16; k++)
+                    sum += v[k];
+            }
         }
     }
     s_share[wave][lane] = sum;
     __syncthreads();
-    if (wave == 0) {
-        uint32_t run = 0;
-        for (uint32_t w = 0; w < kScanWaves; w++) {
-            const uint32_t v = s_share[w][lane];
-            s_share[w][lane] = run;
-            run += v;
-        }
-        if (on)
-            a.bin_count[b] = run;
+    // this wave's base: the shares of the waves before it; the total is the
+    // bin's count
+    uint32_t run = 0, total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kScanWaves; w++) {
+        const uint32_t v = s_share[w][lane];
+        run += w < wave ? v : 0u;
+        total += v;
     }
-    __syncthreads();
+    if (on && wave == 0)
+        a.bin_count[b] = total;
     if (on) {
-        uint32_t run = s_share[wave][lane];
-        for (uint32_t g = u0; g < u1; g += 16) {
-            uint32_t v[16];
+        if (kept) {
 #pragma unroll
-            for (int k = 0; k < 16; k++)
-                v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+            for (uint32_t k = 0; k < kScanKeep; k++) {
+                if (u0 + k < u1)
+                    a.table[(size_t)(u0 + k) * a.nbins + b] = run;
+                run += keep[k];
+            }
+        } else {
+            for (uint32_t g = u0; g < u1; g += 16) {
+                uint32_t v[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
-                if (g + k < u1)
-                    a.table[(size_t)(g + k) * a.nbins + b] = run;
-                run += v[k];
+                for (int k = 0; k < 16; k++)
+                    v[k] = (g + k < u1) ? a.table[(size_t)(g + k) * a.nbins + b] : 0;
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (g + k < u1)
+                        a.table[(size_t)(g + k) * a.nbins + b] = run;
+                    run += v[k];
+                }
             }
         }
     }
@@ -1201,7 +1222,7 @@ __device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t 
     const float inv = 1.0f / cnt;
     const float cx = (float)(px0 - (int)(r.bb_i & 0xffffu)) + sx * inv;
     const float cy = (float)(py0 - (int)(r.bb_j & 0xffffu)) + sy * inv;
-    // the fp32 plane (the stored fA, fB, fC0 are these same roundings)
+    // the plane rounded to fp32
     float k = (float)r.A * cx + (float)r.B * cy + (float)r.C0;
     k = (k > 0.0f) ? k : 0.0f;  // NaN -> 0
     return 0x7F800000u - min(__float_as_uint(k), 0x7F800000u);  // < 2^31
