@@ -28,12 +28,17 @@ RULES_PATH = os.path.join(HERE, "tuning.json")
 BINS = (16, 32, 64)
 BLOCKS = (8, 4)
 DEPTHS = (4, 8, 12, 16, 24, 32)
+# The online tuner also tries depth 2.  It pays only on frames whose pixels
+# hold a couple of fragments; a rule chosen on a class's sample frames would
+# also apply it to denser frames of the class, whose extra flagged pixels
+# cost more than the shallower sorter saves (measured on the mixed batch).
+ONLINE_DEPTHS = (2,) + DEPTHS
 # quads-per-pixel bucket upper bounds and the value sampled in each bucket
 QPP_BUCKETS = ((0.01, 0.005), (0.05, 0.022), (0.15, 0.08), (0.3, 0.2), (0.6, 0.4), (1.2, 0.8), (1e9, 2.0))
 
 
-def tunings():
-    return list(itertools.product(BINS, DEPTHS, BLOCKS))
+def tunings(depths=DEPTHS):
+    return list(itertools.product(BINS, depths, BLOCKS))
 
 
 def sample_frames(W: int, H: int, qpp: float, seed: int):
@@ -106,7 +111,7 @@ def tune_frame(ctx, h, cam, W: int, H: int, reps: int = 10, candidates=None):
     sorter_depth, block_h) and the table of times."""
     times = {}
     sc = type("F", (), {"width": W, "height": H, "camera": cam})
-    for tune in candidates or tunings():
+    for tune in candidates or tunings(ONLINE_DEPTHS):
         times[tune] = time_frame(ctx, h, sc, tune, reps)
     best = min(times, key=times.get)
     return best, times
