@@ -331,9 +331,10 @@ __device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, double Rx,
     flags |= kConvex;
 }
 
-// Setup of quad q (Stage 1): writes its record, snapped vertices, bbox and
-// cull reason; returns the reason (VISIBLE = 0).
-__device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
+// Setup of quad q (Stage 1): writes its snapped vertices, bbox and cull
+// reason, leaves the record of a visible quad in r (the caller stores it);
+// returns the reason (VISIBLE = 0).
+__device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q, QuadRec &r)
 {
     uint32_t reason = 0xff;
     {
@@ -426,7 +427,6 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                             reason = EDGE_ON;
                         } else {
                             reason = VISIBLE;
-                            QuadRec r;
                             uint32_t flags = 0;
                             if (xmax - xmin > kNarrowExtent || ymax - ymin > kNarrowExtent)
                                 flags |= kWide;
@@ -451,9 +451,6 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
                             r.A = A;
                             r.B = B;
                             r.C0 = C0;
-                            for (int k = 0; k < 4; k++)
-                                r.pad[k] = 0;
-                            a.rec[q] = r;
                             bb = make_uint2(r.bb_i, r.bb_j);
                         }
                     }
@@ -471,22 +468,66 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q)
 // Quads per lane of the setup kernel (each workgroup takes 256 quads).
 constexpr uint32_t kSetupQPL = 1;
 
+// The workgroup's 256 records are contiguous in HBM (rec is indexed by quad).
+// A lane storing its own 128-byte record would issue eight stores whose lanes
+// sit 128 bytes apart, 64 partial lines each; instead the records are staged
+// in LDS and written as consecutive 16-byte chunks, one full line per eight
+// lanes.  In LDS, chunk c of row t sits at slot c ^ (t & 7), so the staging
+// writes of neighbouring rows fall in different banks.  Rows of culled quads
+// are written as zeros (nothing reads them).
+constexpr uint32_t kRecChunks = sizeof(QuadRec) / 16;
+
 template <class Src>
 __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
 {
+    static_assert(kSetupQPL == 1, "record staging assumes one quad per lane");
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
+    __shared__ uint4 s_rec[256 * kRecChunks];
     uint32_t reasons[kSetupQPL];
+    {
+        const uint32_t t = threadIdx.x;
+        const uint32_t q = blk * 256 + t;
+        QuadRec r;
+        reasons[0] = q < a.n ? setup_quad(a, q, r) : 0xffu;
+        uint4 ch[kRecChunks];
+        if (reasons[0] == VISIBLE) {
+            ch[0] = make_uint4(r.hp[0], r.hp[1], r.hp[2], r.hp[3]);
+            ch[1] = make_uint4(r.hp[4], r.hp[5], r.hp[6], r.hp[7]);
+            ch[2] = make_uint4(r.hp[8], r.hp[9], r.hp[10], r.hp[11]);
+            ch[3] = make_uint4(r.hp[12], r.hp[13], r.hp[14], r.hp[15]);
+            ch[4] = make_uint4(r.hp[16], r.hp[17], r.bb_i, r.bb_j);
+            const unsigned long long ua = __double_as_longlong(r.A);
+            const unsigned long long ub = __double_as_longlong(r.B);
+            const unsigned long long uc = __double_as_longlong(r.C0);
+            ch[5] = make_uint4(r.rgba, r.flags, (uint32_t)ua, (uint32_t)(ua >> 32));
+            ch[6] = make_uint4((uint32_t)ub, (uint32_t)(ub >> 32), (uint32_t)uc, (uint32_t)(uc >> 32));
+        } else {
 #pragma unroll
-    for (uint32_t k = 0; k < kSetupQPL; k++) {
-        const uint32_t q = blk * 256 + k * (256 / kSetupQPL) + threadIdx.x;
-        reasons[k] = q < a.n ? setup_quad(a, q) : 0xffu;
+            for (uint32_t c = 0; c < 7; c++)
+                ch[c] = make_uint4(0, 0, 0, 0);
+        }
+        ch[7] = make_uint4(0, 0, 0, 0);  // pad
+#pragma unroll
+        for (uint32_t c = 0; c < kRecChunks; c++)
+            s_rec[t * kRecChunks + (c ^ (t & 7))] = ch[c];
     }
     // cull statistics: one atomic per workgroup and reason, striped
     __shared__ uint32_t s_cull[6];
     if (threadIdx.x < 6)
         s_cull[threadIdx.x] = 0;
     __syncthreads();
+    {
+        const uint32_t q0 = blk * 256;
+        const uint32_t rows = q0 < a.n ? min(256u, a.n - q0) : 0u;
+        uint4 *dst = reinterpret_cast<uint4 *>(a.rec + q0);
+#pragma unroll
+        for (uint32_t i = 0; i < kRecChunks; i++) {
+            const uint32_t idx = i * 256 + threadIdx.x, row = idx / kRecChunks, c = idx % kRecChunks;
+            if (row < rows)
+                dst[idx] = s_rec[row * kRecChunks + (c ^ (row & 7))];
+        }
+    }
     const uint32_t lane = lane_id();
     for (uint32_t r = 0; r < 6; r++) {
         uint32_t c = 0;
