@@ -72,17 +72,18 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, stage):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary, and
+    the tuning the counters were taken on, if they were taken on the current
+    kernel source; else (None, None)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return None, None
     entry = t.get(workload, {}).get(stage)
     if not entry or entry.get("kernel_source_sha") != kernel_source_hash():
-        return None
-    return entry.get("bytes_per_launch")
+        return None, None
+    return entry.get("bytes_per_launch"), entry.get("tuning")
 
 
 def cpu_baseline(sc, min_seconds):
@@ -363,6 +364,7 @@ def main():
     achieved = nbytes / (avg_us[dom] * 1e-6) / 1e9
     hbm = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 5), "algorithmic_bytes": int(nbytes)}
+    traffic, traffic_tuning = measured_traffic(args.workload, dom)
     if dom == "raster":
         # the raster is bound by VALU issue, not by HBM: its roofline is the
         # ALU one, with the HBM view beside it
@@ -370,11 +372,11 @@ def main():
         a_ops = ops / (avg_us[dom] * 1e-6) / 1e12
         roofline = {"bound": "alu", "achieved": round(a_ops, 3), "peak": round(ALU_PEAK_TOPS, 2),
                     "unit": "T lane-op/s", "frac": round(a_ops / ALU_PEAK_TOPS, 5),
-                    "traffic": measured_traffic(args.workload, dom),
+                    "traffic": traffic, "traffic_tuning": traffic_tuning,
                     "kernel": KERNELS[dom], "kernel_avg_us": round(avg_us[dom], 3),
                     "algorithmic_lane_ops": int(ops), "hbm_view": hbm}
     else:
-        roofline = dict(hbm, traffic=measured_traffic(args.workload, dom), kernel=KERNELS[dom],
+        roofline = dict(hbm, traffic=traffic, traffic_tuning=traffic_tuning, kernel=KERNELS[dom],
                         kernel_avg_us=round(avg_us[dom], 3))
 
     res = {
