@@ -33,6 +33,15 @@ def behind_camera(W, H, n, seed):
     return scenes.Scene(v=v, rgba=sc.rgba, width=W, height=H, camera=sc.camera, name="behind")
 
 
+def partly_culled(W, H, n, seed):
+    """Every third quad behind the near plane: culled and visible quads
+    interleave within each setup workgroup."""
+    sc = scenes.small(W, H, n, seed, side=(2.0, 20.0))
+    v = sc.v.copy()
+    v[::3, :, 2] = -np.abs(v[::3, :, 2]) - 1.0
+    return scenes.Scene(v=v, rgba=sc.rgba, width=W, height=H, camera=sc.camera, name="partly_culled")
+
+
 def sweep_cases():
     cases = [
         # more than 8192 bins at bin 16: the one-wave count and scatter kernels
@@ -44,6 +53,11 @@ def sweep_cases():
                                                   alpha=(0.1, 0.4)), (64, 12, 4)),
         ("all_culled", lambda: behind_camera(123, 77, 300, 43), (32, 8, 8)),
         ("one_quad", lambda: scenes.small(50, 40, 1, 44, side=(10.0, 30.0)), (32, 2, 8)),
+        # setup stages a workgroup's 256 records and stores them together: a
+        # last workgroup holding one quad, whole workgroups, and culled rows
+        ("setup_tail_row", lambda: scenes.small(200, 150, 513, 47, side=(2.0, 20.0)), (32, 8, 8)),
+        ("setup_whole_groups", lambda: scenes.small(200, 150, 512, 48, side=(2.0, 20.0)), (32, 4, 4)),
+        ("setup_partly_culled", lambda: partly_culled(200, 150, 700, 49), (16, 8, 8)),
         ("general_bin16", lambda: general_quads(150, 90, 3000, 45, extent=(1.0, 20.0)), (16, 24, 8)),
         ("general_bin64", lambda: general_quads(150, 90, 3000, 46, extent=(1.0, 20.0)), (64, 32, 4)),
     ]
