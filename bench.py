@@ -1,11 +1,15 @@
-"""Benchmark: exact order-independent transparency of the 1280x720 quad
-workload on one MI355X.
+"""Benchmark: exact order-independent transparency of quad scenes on one
+MI355X.
 
 A step is one whole frame of the path -- setup, binning, sorted
-rasterization (block sort + per-pixel sorter), dense-block pass and exact
-per-pixel pass -- over a scene resident in HBM.  The unsorted compute blend
-(the "1.00" reference of the paper's comparison) is timed the same way on the
-same GPU.  Prints one JSON line.
+rasterization (block sort + per-pixel sorter, depth slices for dense blocks)
+and the exact per-pixel pass -- over a scene resident in HBM.  The headline
+frame is the 1920x1080 one with 1M quads in a Gaussian cloud (106 M
+fragments), at the tuning the library's rule table picks for it.  The
+unsorted compute blend (the "1.00" reference of the paper's comparison) is
+timed the same way on the same GPU.  Side legs: the 1280x720 200k-quad frame
+(rule table and online-tuned), a 64-frame mixed batch and the serving loop.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -86,22 +90,45 @@ def measured_traffic(workload, stage):
     return entry.get("bytes_per_launch"), entry.get("tuning")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sc, min_seconds):
+    """The oracle (test infrastructure, untuned) on the host: whole frames on
+    all the cores this process may use (row bands, at most 16 threads), then
+    one whole frame on one core."""
     import oracle
     oracle.build(force=False)
+    threads = oracle.default_threads()
     reps, t0, total = 0, time.perf_counter(), 0
     ref = None
     while True:
-        res = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False)
+        res = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False, threads=threads)
         reps += 1
         total += res["total"]
         ref = res
         if time.perf_counter() - t0 >= min_seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": round(total / dt / 1e6, 3), "unit": "Mfrags/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full {sc.width}x{sc.height} frame(s) of the bench workload, single thread, "
-                      f"{dt:.1f} s"}, ref
+    t1 = time.perf_counter()
+    one = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False, threads=1)
+    dt1 = time.perf_counter() - t1
+    return {"value": round(total / dt / 1e6, 3), "unit": "Mfrags/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} full {sc.width}x{sc.height} frame(s) of the bench workload on {threads} threads "
+                      f"({dt:.1f} s), then 1 full frame on 1 thread ({dt1:.1f} s)",
+            "all_cores": {"cores": threads, "value": round(total / dt / 1e6, 3),
+                          "frames_per_s": round(reps / dt, 4)},
+            "one_core": {"cores": 1, "value": round(one["total"] / dt1 / 1e6, 3),
+                         "frames_per_s": round(1.0 / dt1, 4)},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}, ref
 
 
 def time_steps(torch, fn, steps, warmup):
@@ -263,17 +290,112 @@ def serving_leg(torch, lucidraster, scenes, rules, n_scenes, n_req, log):
     return res
 
 
+def frame_leg(torch, lucidraster, autotune, sc, workload, tune, tuning_note, steps, warmup, arena):
+    """Sorted and unsorted frame times of one workload at one tuning, and the
+    dominant kernel's roofline from a pass with events between stages."""
+    W, H = sc.width, sc.height
+    b, k, bh = tune
+    ctx = lucidraster.Context(arena_bytes=arena, bin_size=b, sorter_depth=k, block_h=bh)
+    h = ctx.upload(sc.v, sc.rgba)
+    out = ctx.new_image(W, H)
+    # first frame sizes the workspace (and re-plans bin capacity if needed)
+    ctx.render(h, sc.camera, W, H, out=out)
+    st = ctx.stats()
+    log(f"{workload}: {st['fragments']} fragments, {st['bin_pairs']} bin pairs, {st['block_entries']} block "
+        f"entries, {st['flagged_pixels']} flagged pixels, {st['dense_blocks']} blocks in depth slices")
+    sorted_fn = lambda: ctx.render(h, sc.camera, W, H, out=out, check=False)
+    log(f"{workload}: timing sorted render, {warmup} warmup + {steps} steps")
+    ms = time_steps(torch, sorted_fn, steps, warmup) / steps
+    ctx.sync()
+    per = step_latencies(torch, sorted_fn, steps)
+    ctx.sync()
+    st = ctx.stats()
+    frags = st["fragments"]
+    log(f"{workload}: timing unsorted compute blend")
+    out_u = ctx.new_image(W, H)
+    unsorted_fn = lambda: ctx.render_unsorted(h, sc.camera, W, H, out=out_u, check=False)
+    ms_u = time_steps(torch, unsorted_fn, steps, warmup) / steps
+    ctx.sync()
+    per_u = step_latencies(torch, unsorted_fn, steps)
+    ctx.sync()
+    ctx.close()
+
+    # per-stage times: HIP events recorded on the launch stream around every
+    # stage of each timed frame (a separate pass: the events themselves add
+    # time between kernels, so the frame times above are measured without them)
+    log(f"{workload}: timing stages")
+    ctx_t = lucidraster.Context(arena_bytes=arena, bin_size=b, sorter_depth=k, block_h=bh, timing=True)
+    h_t = ctx_t.upload(sc.v, sc.rgba)
+    ctx_t.render(h_t, sc.camera, W, H, out=out)
+    time_steps(torch, lambda: ctx_t.render(h_t, sc.camera, W, H, out=out, check=False), steps, warmup)
+    ctx_t.sync()
+    stage = ctx_t.stage_times(steps)  # the timed frames
+    ctx_t.close()
+    ms_staged = float(stage[:, 7].mean()) / 1e3
+    names = lucidraster.STAGES[:7]
+    avg_us = {nm: float(stage[:, i].mean()) for i, nm in enumerate(names) if nm != "unused"}
+    dom = max(avg_us, key=avg_us.get)
+    if algorithmic_bytes(dom, sc.n, st["visible"], st["bin_pairs"], W, H) is None:
+        dom = "raster"
+    nbytes = algorithmic_bytes(dom, sc.n, st["visible"], st["bin_pairs"], W, H)
+    achieved = nbytes / (avg_us[dom] * 1e-6) / 1e9
+    hbm = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 5), "algorithmic_bytes": int(nbytes)}
+    traffic, traffic_tuning = measured_traffic(workload, dom)
+    if traffic is not None and traffic_tuning != f"bin {b}, K {k}, 8x{bh}":
+        traffic, traffic_tuning = None, None
+    if dom == "raster":
+        # the raster is bound by VALU issue, not by HBM: its roofline is the
+        # ALU one, with the HBM view beside it
+        ops = algorithmic_lane_ops(frags, st["block_entries"])
+        a_ops = ops / (avg_us[dom] * 1e-6) / 1e12
+        roofline = {"bound": "alu", "achieved": round(a_ops, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                    "unit": "T lane-op/s", "frac": round(a_ops / ALU_PEAK_TOPS, 5),
+                    "traffic": traffic, "traffic_tuning": traffic_tuning,
+                    "kernel": KERNELS[dom], "kernel_avg_us": round(avg_us[dom], 3),
+                    "algorithmic_lane_ops": int(ops), "fragments": int(frags),
+                    "block_entries": int(st["block_entries"]), "bin_pairs": int(st["bin_pairs"]),
+                    "hbm_view": hbm}
+    else:
+        roofline = dict(hbm, traffic=traffic, traffic_tuning=traffic_tuning, kernel=KERNELS[dom],
+                        kernel_avg_us=round(avg_us[dom], 3))
+    return {
+        "ms": ms, "frags": int(frags), "stats": st, "out": out,
+        "line": {
+            "workload": f"{workload}: {WORKLOADS[workload]}", "tuning": f"bin {b}, K {k}, 8x{bh}",
+            "tuning_note": tuning_note, "fragments": int(frags),
+            "ms_per_frame": round(ms, 5), "Mfrags_per_s": round(frags / (ms * 1e-3) / 1e6, 3),
+            "frames_per_s": round(1000.0 / ms, 2),
+            "p50_ms": round(float(np.percentile(per, 50)), 5), "p99_ms": round(float(np.percentile(per, 99)), 5),
+            "unsorted": {"ms_per_step": round(ms_u, 5), "Mfrags_per_s": round(frags / (ms_u * 1e-3) / 1e6, 3),
+                         "frames_per_s": round(1000.0 / ms_u, 2),
+                         "p50_ms": round(float(np.percentile(per_u, 50)), 5),
+                         "p99_ms": round(float(np.percentile(per_u, 99)), 5)},
+            "sorted_over_unsorted": round(ms / ms_u, 3),
+            "stage_us": {kk: round(v, 3) for kk, v in avg_us.items()},
+            "stage_note": "stage times from a pass with HIP events between stages; that pass's frames take "
+                          f"{ms_staged:.4f} ms",
+            "flagged_pixels": int(st["flagged_pixels"]), "sliced_blocks": int(st["dense_blocks"]),
+            "roofline": roofline,
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--bin-size", type=int, default=0, help="0: autotuned (else 32)")
-    ap.add_argument("--sorter-depth", type=int, default=0, help="0: autotuned (else 8)")
-    ap.add_argument("--block-h", type=int, default=0, help="0: autotuned (else 8)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--tuning", default="rules", choices=("rules", "online"),
+                    help="rules: the library's rule table (default); online: fastest tuning timed on the frame")
+    ap.add_argument("--bin-size", type=int, default=0, help="override the tuning's bin size")
+    ap.add_argument("--sorter-depth", type=int, default=0, help="override the tuning's sorter depth")
+    ap.add_argument("--block-h", type=int, default=0, help="override the tuning's block height")
+    ap.add_argument("--cpu-seconds", type=float, default=6.0,
+                    help="minimum seconds of all-core oracle frames (one single-core frame follows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="skip the 1280x720 side leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame mixed batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -291,137 +413,78 @@ def main():
         return
 
     import torch
-    from paper_2405_13364_amd import lucidraster, scenes
+    from paper_2405_13364_amd import autotune, lucidraster, scenes
+
+    rules = autotune.load_rules()
+    arena = 2 << 30
+
+    def pick_tuning(sc, mode):
+        if mode == "online":
+            log(f"{sc.name}: online tuning on the frame")
+            tctx = lucidraster.Context(arena_bytes=arena)
+            th_ = tctx.upload(sc.v, sc.rgba)
+            best, ttimes = autotune.tune_frame(tctx, th_, sc.camera, sc.width, sc.height)
+            tctx.close()
+            return tuple(best), (f"online: fastest of {len(ttimes)} tunings timed on this frame (rule table "
+                                 f"pick {'/'.join(map(str, autotune.resolve(rules, sc.width, sc.height, sc.n)))})")
+        return tuple(autotune.resolve(rules, sc.width, sc.height, sc.n)), "rule table (lr_set_tuning rules)"
 
     log(f"generating workload {args.workload}")
     sc = scenes.scene(args.workload)
-    W, H = sc.width, sc.height
-    from paper_2405_13364_amd import autotune
-    rules = autotune.load_rules()
-    arena = 2 << 30
-    tuning_note = "fixed"
-    if not (args.bin_size and args.sorter_depth and args.block_h):
-        # online tuning: every (bin, sorter depth, block) timed on this frame
-        log("tuning on the workload frame")
-        tctx = lucidraster.Context(arena_bytes=arena)
-        th_ = tctx.upload(sc.v, sc.rgba)
-        best, ttimes = autotune.tune_frame(tctx, th_, sc.camera, W, H)
-        tctx.close()
-        args.bin_size = args.bin_size or best[0]
-        args.sorter_depth = args.sorter_depth or best[1]
-        args.block_h = args.block_h or best[2]
-        tuning_note = ("online: fastest of %d tunings timed on this frame (rule table pick %s)"
-                       % (len(ttimes), "/".join(map(str, autotune.resolve(rules, W, H, sc.n)))))
-    log(f"tuning: bin {args.bin_size}, sorter depth {args.sorter_depth}, block 8x{args.block_h} ({tuning_note})")
-    ctx = lucidraster.Context(arena_bytes=arena, bin_size=args.bin_size, sorter_depth=args.sorter_depth,
-                              block_h=args.block_h)
-    h = ctx.upload(sc.v, sc.rgba)
-    out = ctx.new_image(W, H)
-    # first frame sizes the workspace (and re-plans bin capacity if needed)
-    ctx.render(h, sc.camera, W, H, out=out)
-    st = ctx.stats()
-    log(f"frame: {st['fragments']} fragments, {st['bin_pairs']} bin pairs, {st['block_entries']} block "
-        f"entries, {st['flagged_pixels']} flagged pixels, {st['dense_blocks']} blocks in depth slices")
-
-    sorted_fn = lambda: ctx.render(h, sc.camera, W, H, out=out, check=False)
-    log(f"timing sorted render: {args.warmup} warmup + {args.steps} steps")
-    ms = time_steps(torch, sorted_fn, args.steps, args.warmup) / args.steps
-    ctx.sync()
-    per = step_latencies(torch, sorted_fn, args.steps)
-    ctx.sync()
-    st = ctx.stats()
-    frags = st["fragments"]
-
-    log("timing unsorted compute blend")
-    out_u = ctx.new_image(W, H)
-    unsorted_fn = lambda: ctx.render_unsorted(h, sc.camera, W, H, out=out_u, check=False)
-    ms_u = time_steps(torch, unsorted_fn, args.steps, args.warmup) / args.steps
-    ctx.sync()
-    per_u = step_latencies(torch, unsorted_fn, args.steps)
-    ctx.sync()
-    ctx.close()
-
-    # per-stage times: HIP events recorded on the launch stream around every
-    # stage of each timed frame (a separate pass: the events themselves add
-    # time between kernels, so the headline above is measured without them)
-    log("timing stages")
-    ctx_t = lucidraster.Context(arena_bytes=arena, bin_size=args.bin_size, sorter_depth=args.sorter_depth,
-                                block_h=args.block_h, timing=True)
-    h_t = ctx_t.upload(sc.v, sc.rgba)
-    ctx_t.render(h_t, sc.camera, W, H, out=out)
-    time_steps(torch, lambda: ctx_t.render(h_t, sc.camera, W, H, out=out, check=False), args.steps, args.warmup)
-    ctx_t.sync()
-    stage = ctx_t.stage_times(args.steps)  # the timed frames
-    ms_staged = float(stage[:, 7].mean()) / 1e3
-
-    # dominant kernel of the sorted frame
-    names = lucidraster.STAGES[:7]
-    avg_us = {nm: float(stage[:, i].mean()) for i, nm in enumerate(names) if nm != "unused"}
-    dom = max(avg_us, key=avg_us.get)
-    if algorithmic_bytes(dom, sc.n, st["visible"], st["bin_pairs"], W, H) is None:
-        dom = "raster"
-    nbytes = algorithmic_bytes(dom, sc.n, st["visible"], st["bin_pairs"], W, H)
-    achieved = nbytes / (avg_us[dom] * 1e-6) / 1e9
-    hbm = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 5), "algorithmic_bytes": int(nbytes)}
-    traffic, traffic_tuning = measured_traffic(args.workload, dom)
-    if dom == "raster":
-        # the raster is bound by VALU issue, not by HBM: its roofline is the
-        # ALU one, with the HBM view beside it
-        ops = algorithmic_lane_ops(frags, st["block_entries"])
-        a_ops = ops / (avg_us[dom] * 1e-6) / 1e12
-        roofline = {"bound": "alu", "achieved": round(a_ops, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                    "unit": "T lane-op/s", "frac": round(a_ops / ALU_PEAK_TOPS, 5),
-                    "traffic": traffic, "traffic_tuning": traffic_tuning,
-                    "kernel": KERNELS[dom], "kernel_avg_us": round(avg_us[dom], 3),
-                    "algorithmic_lane_ops": int(ops), "hbm_view": hbm}
-    else:
-        roofline = dict(hbm, traffic=traffic, traffic_tuning=traffic_tuning, kernel=KERNELS[dom],
-                        kernel_avg_us=round(avg_us[dom], 3))
-
+    tune, note = pick_tuning(sc, args.tuning)
+    tune = (args.bin_size or tune[0], args.sorter_depth or tune[1], args.block_h or tune[2])
+    if args.bin_size or args.sorter_depth or args.block_h:
+        note += " with command-line overrides"
+    log(f"tuning: bin {tune[0]}, sorter depth {tune[1]}, block 8x{tune[2]} ({note})")
+    head = frame_leg(torch, lucidraster, autotune, sc, args.workload, tune, note, args.steps, args.warmup, arena)
+    line = head["line"]
+    ms, frags = head["ms"], head["frags"]
     res = {
         "metric": METRIC,
-        "value": round(frags / (ms * 1e-3) / 1e6, 3),
+        "value": line["Mfrags_per_s"],
         "unit": "Mfrags/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 5),
+        "ms_per_step": line["ms_per_frame"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "width": W, "height": H,
-                   "quads": sc.n, "fragments": int(frags), "bin_size": args.bin_size,
-                   "block": f"8x{args.block_h}", "sorter_depth": args.sorter_depth,
-                   "tuning": tuning_note,
+        "config": {"workload": line["workload"], "width": sc.width, "height": sc.height,
+                   "quads": sc.n, "fragments": int(frags), "bin_size": tune[0],
+                   "block": f"8x{tune[2]}", "sorter_depth": tune[1], "tuning": note,
                    "arithmetic": "i32 coverage, f64 depth plane, f32 blend"},
-        "frames_per_s": round(1000.0 / ms, 2),
-        "p50_ms": round(float(np.percentile(per, 50)), 5),
-        "p99_ms": round(float(np.percentile(per, 99)), 5),
-        "unsorted": {"ms_per_step": round(ms_u, 5), "Mfrags_per_s": round(frags / (ms_u * 1e-3) / 1e6, 3),
-                     "frames_per_s": round(1000.0 / ms_u, 2),
-                     "p50_ms": round(float(np.percentile(per_u, 50)), 5),
-                     "p99_ms": round(float(np.percentile(per_u, 99)), 5)},
-        "sorted_over_unsorted": round(ms / ms_u, 3),
+        "frames_per_s": line["frames_per_s"],
+        "p50_ms": line["p50_ms"],
+        "p99_ms": line["p99_ms"],
+        "unsorted": line["unsorted"],
+        "sorted_over_unsorted": line["sorted_over_unsorted"],
         "paper_sw_over_hw": 3.30,
-        "stage_us": {k: round(v, 3) for k, v in avg_us.items()},
-        "stage_note": "stage times from a pass with HIP events between stages; that pass's frames take "
-                      f"{ms_staged:.4f} ms",
-        "flagged_pixels": int(st["flagged_pixels"]),
-        "sliced_blocks": int(st["dense_blocks"]),
-        "roofline": roofline,
+        "stage_us": line["stage_us"],
+        "stage_note": line["stage_note"],
+        "flagged_pixels": line["flagged_pixels"],
+        "sliced_blocks": line["sliced_blocks"],
+        "roofline": line["roofline"],
     }
     if not args.no_cpu_baseline:
-        log(f"timing the CPU oracle for about {args.cpu_seconds:.0f} s")
+        log(f"timing the CPU oracle: about {args.cpu_seconds:.0f} s on all cores, then one frame on one core")
         cb, ref = cpu_baseline(sc, args.cpu_seconds)
         res["cpu_baseline"] = cb
-        got = out.cpu().numpy().astype(np.int32)
+        got = head["out"].cpu().numpy().astype(np.int32)
         res["max_lsb_vs_oracle"] = int(np.abs(got - ref["rgba8"].astype(np.int32)).max())
+        res["fragments_equal_oracle"] = bool(ref["total"] == frags)
     else:
         res["cpu_baseline"] = None
-    ctx_t.close()
+    if not args.no_side and args.workload != "c2":
+        side = {}
+        sc2 = scenes.scene("c2")
+        for mode in ("rules", "online"):
+            t2, n2 = pick_tuning(sc2, mode)
+            side[mode] = frame_leg(torch, lucidraster, autotune, sc2, "c2", t2, n2, args.steps, args.warmup,
+                                   arena)["line"]
+        res["side_c2"] = side
     if not args.no_batch:
         log("64-frame mixed batch")
         res["batch"] = mixed_batch_leg(torch, lucidraster, scenes, rules, args.batch_reps, log)

@@ -28,8 +28,8 @@
  *     premultiplied RGBA8 (rounded half up).
  *
  * Memory: the caller owns all device memory.  lr_create takes a device arena
- * the library sub-allocates from (it calls no hipMalloc when an arena is
- * given); render outputs are device pointers.  Every call returns an
+ * the library sub-allocates from (it never calls hipMalloc); render outputs
+ * are device pointers.  Every call returns an
  * lr_status; no exception or abort crosses the ABI; outputs are only written
  * on LR_OK.  Rendering calls are asynchronous on the given HIP stream; errors
  * found by kernels (capacity overflow) are latched in the context and
@@ -78,9 +78,8 @@ typedef struct {
 typedef struct {
     int32_t device;           /* HIP device ordinal */
     void *stream;             /* default hipStream_t for calls given NULL */
-    void *arena;              /* device memory owned by the caller, or NULL */
-    uint64_t arena_bytes;     /* arena size; with arena == NULL the library
-                                 allocates this much once (default 1 GiB) */
+    void *arena;              /* device memory owned by the caller (required) */
+    uint64_t arena_bytes;     /* its size in bytes (at least 1 MiB) */
     uint32_t bin_size;        /* 16, 32 (default) or 64 pixels */
     uint32_t block_h;         /* depth-sort granularity: 8 for 8x8 blocks
                                  (default), 4 for 8x4 half-blocks (Stage 3,
@@ -119,7 +118,8 @@ typedef struct {
 } lr_stats;
 
 /* A request for lr_render_batch.  A zero tuning field takes the first
- * matching rule set by lr_set_tuning, else the context default. */
+ * matching rule set by lr_set_tuning, else the context default.  (Batching is
+ * this library's own addition; each frame is the render of Section 2.) */
 typedef struct {
     lr_scene scene;
     lr_camera camera;
@@ -129,7 +129,22 @@ typedef struct {
     uint32_t sorter_depth;    /* as lr_config.sorter_depth, or 0 */
     uint32_t block_h;         /* 4, 8 or 0 */
     uint32_t reserved;
+    uint32_t *status;         /* NULL, or a device word that receives the
+                                 frame's error bits, stream-ordered after the
+                                 frame's kernels: 0 when the image was
+                                 written, else LR_FRAME_ERR_* bits.  Lets a
+                                 caller that polls completion events find a
+                                 failed frame without a device-wide lr_sync. */
 } lr_request;
+
+/* Error bits of a frame (lr_request.status, lr_stats.error_word). */
+#define LR_FRAME_ERR_CAPACITY 1u  /* its bin lists overflowed: the image was
+                                     not written; lr_sync raises the capacity
+                                     and a second render succeeds */
+#define LR_FRAME_ERR_DENSE 4u     /* a block held more equal-depth entries
+                                     than one on-chip sort; its pixels were
+                                     recomputed by the exact per-pixel sort
+                                     (informational: the image is exact) */
 
 /* A tuning rule: applies to frames of at most max_pixels pixels with at most
  * max_quads_per_pixel quads per pixel (resident quads / (width*height)).
@@ -142,45 +157,55 @@ typedef struct {
     uint32_t reserved;
 } lr_tune_rule;
 
-/* Human-readable name of a status code (static storage). */
+/* Human-readable name of a status code (static storage).  This library's
+ * own error reporting; the paper has no API. */
 const char *lr_status_string(lr_status s);
 
-/* Last error message of the context (or of the process when ctx is NULL). */
+/* Last error message of the context (or of the process when ctx is NULL).
+ * This library's own error reporting. */
 const char *lr_last_error(lr_context ctx);
 
-/* Create a context on cfg->device.  Fails with LR_ERR_INVALID_ARG for a bad
- * config, LR_ERR_DEVICE when HIP is unavailable. */
+/* Create a context on cfg->device over the caller's device arena (the
+ * renderer's state of Section 2: resident scenes and per-frame buffers).
+ * Fails with LR_ERR_INVALID_ARG for a bad config or a NULL arena,
+ * LR_ERR_DEVICE when HIP is unavailable.  *out is written only on LR_OK. */
 lr_status lr_create(const lr_config *cfg, lr_context *out);
 
-/* Wait for the context's work and free its host state (and the arena the
- * library allocated itself, if any).  Caller memory is left untouched. */
+/* Wait for the context's work and free its host state.  Caller memory (the
+ * arena, outputs) is left untouched.  This library's own lifetime call. */
 lr_status lr_destroy(lr_context ctx);
 
-/* Make quads resident on the device (A1 of the path: off the per-frame work).
- * q points to n lr_quad records in host memory (q_on_device == 0) or device
- * memory (q_on_device != 0).  The data is copied and transposed into the
- * arena; q may be freed when the call returns.  1 <= n <= 2^24.  Stream
- * ordered on the context stream. */
+/* Make quads resident on the device: the input of Stage 1 ("Phase 1:
+ * processing input quads"), off the per-frame work.  q points to n lr_quad
+ * records in host memory (q_on_device == 0) or device memory (q_on_device !=
+ * 0).  The data is copied and transposed into the arena (structure of
+ * arrays); the call waits for the copy, so q may be freed or reused when it
+ * returns.  1 <= n <= 2^24; LR_ERR_OUT_OF_MEMORY when the arena is full. */
 lr_status lr_upload_scene(lr_context ctx, const lr_quad *q, uint32_t n, int q_on_device,
                           lr_scene *out);
 
-/* Return a scene's arena space (after the context stream drains). */
+/* Return a scene's arena space (after the device drains).  This library's
+ * own memory management. */
 lr_status lr_release_scene(lr_context ctx, lr_scene scene);
 
 /* Render a scene into out_rgba8 (device, width*height*4 bytes, row-major, top
- * row first, premultiplied RGBA8).  1 <= width, height <= 16384.  Runs on
- * stream (NULL: the context stream) and returns without waiting.  The bin
- * size, block shape and sorter depth come from the first matching tuning rule
- * (lr_set_tuning), else from the context configuration; the image does not
- * depend on them. */
+ * row first, premultiplied RGBA8): the whole pipeline of Section 2 -- setup
+ * (Stage 1), binning (Stage 2), rasterization with the two-stage sort and
+ * front-to-back blending (Stage 3), plus the exact per-pixel pass for pixels
+ * the per-pixel sorter could not order ("Sample blending").
+ * 1 <= width, height <= 16384.  Runs on stream (NULL: the context stream) and
+ * returns without waiting.  The bin size, block shape and sorter depth come
+ * from the first matching tuning rule (lr_set_tuning), else from the context
+ * configuration; the image does not depend on them. */
 lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                     uint32_t height, uint8_t *out_rgba8, void *stream);
 
-/* Same render, plus parity artefacts (each may be NULL):
+/* Same render (Section 2), plus parity artefacts (each may be NULL):
  *   rgba_f32  [H][W][4] fp32 premultiplied colour before rounding;
  *   counts    [H][W] fragments per pixel;
  *   flagged   [H][W] 1 where the per-pixel sorter detected an order
- *             violation (those pixels were recomputed exactly);
+ *             violation (those pixels were recomputed exactly; Stage 3,
+ *             "Sample blending");
  *   order_offsets [W*H+1] (input, e.g. the exclusive scan of counts) and
  *   order_ids [order_cap]: quad ids of each pixel in blend order. */
 lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
@@ -191,7 +216,7 @@ lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, 
 /* The unsorted baseline: the same setup and binning, then per pixel the
  * covering quads blended in quad order with the "over" operator (fp32), as
  * hardware alpha blending would without sorting (Section 3, "Performance
- * results").  rgba_f32 may be NULL. */
+ * results", the hardware reference).  rgba_f32 may be NULL. */
 lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                              uint32_t height, uint8_t *out_rgba8, void *stream, float *rgba_f32);
 
@@ -203,41 +228,49 @@ lr_status lr_render_unsorted(lr_context ctx, lr_scene scene, const lr_camera *ca
  * lr_render of the same request with the same tuning.  The batch uses one of
  * the context's batch workspaces: batches on different streams run
  * concurrently, up to lr_config.batch_slots at a time.  Returns
- * LR_ERR_OUT_OF_MEMORY when one frame alone does not fit the arena. */
+ * LR_ERR_OUT_OF_MEMORY when one frame alone does not fit the arena.
+ * Batching is this library's own addition (each frame is the render of
+ * Section 2); a request's status word, if given, reports its frame's errors. */
 lr_status lr_render_batch(lr_context ctx, const lr_request *reqs, uint32_t n, void *stream);
 
 /* Replace the tuning rules (copied; n = 0 clears them).  Rules are tried in
- * order; max_pixels must be non-zero and the tuning values valid. */
+ * order; max_pixels must be non-zero and the tuning values valid.  Section 4
+ * suggests adapting the bin size to the scene; the rules are this library's
+ * per-frame form of it. */
 lr_status lr_set_tuning(lr_context ctx, const lr_tune_rule *rules, uint32_t n);
 
 /* Device memory one request needs while in flight (its frame workspace,
- * after tuning), for admission control.  Does not allocate. */
+ * after tuning), for admission control.  Does not allocate.  Section 4 names
+ * memory use as the method's cost; admission is this library's own. */
 lr_status lr_request_bytes(lr_context ctx, const lr_request *req, uint64_t *bytes);
 
 /* Wait for all work the context issued; report a latched kernel error
- * (LR_ERR_CAPACITY) and clear it. */
+ * (LR_ERR_CAPACITY) and clear it.  This library's own. */
 lr_status lr_sync(lr_context ctx);
 
-/* Wait, then fill *out with the statistics of the last render. */
+/* Wait, then fill *out with the statistics of the last render (the per-stage
+ * quantities Section 3 reports: samples, stage times).  This library's own. */
 lr_status lr_get_stats(lr_context ctx, lr_stats *out);
 
 /* Per-stage times (microseconds, layout of lr_stats.stage_us) of the last
  * min(max_frames, frames rendered, 1024) frames, oldest first, into
  * us[frame][8]; *n_out receives the number of frames.  Needs a context
- * created with LR_FLAG_TIMING; synchronises. */
+ * created with LR_FLAG_TIMING; synchronises.  The stages are those of
+ * Section 3's timing tables (setup, binning, rasterization). */
 lr_status lr_get_stage_times(lr_context ctx, uint32_t max_frames, float *us, uint32_t *n_out);
 
-/* Parity dump of the setup stage for a render configuration (synchronous).
- * Per quad: X, Y [n][4] snapped vertices; bbox [n][4] (imin, imax, jmin, jmax
- * of a visible quad); plane [n][3] (A, B, C0); cull [n] (0 visible, else the
- * reason as in lr_stats.culled).  Host pointers; any may be NULL. */
+/* Parity dump of the setup stage (Stage 1, Phases 1 and 2) for a render
+ * configuration (synchronous).  Per quad: X, Y [n][4] snapped vertices; bbox
+ * [n][4] (imin, imax, jmin, jmax of a visible quad); plane [n][3] (A, B, C0);
+ * cull [n] (0 visible, else the reason as in lr_stats.culled).  Host
+ * pointers; any may be NULL. */
 lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                          uint32_t height, int32_t *X, int32_t *Y, int32_t *bbox, double *plane,
                          uint8_t *cull);
 
-/* Parity dump of binning (synchronous): per-bin counts [nbins] and, when ids
- * is not NULL, the concatenated per-bin lists of quad ids (ids_cap entries at
- * most; *total receives the number of pairs). */
+/* Parity dump of binning (Stage 2, synchronous): per-bin counts [nbins] and,
+ * when ids is not NULL, the concatenated per-bin lists of quad ids (ids_cap
+ * entries at most; *total receives the number of pairs). */
 lr_status lr_debug_bins(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                         uint32_t height, uint32_t bin_size, uint32_t *counts, uint32_t *ids,
                         uint64_t ids_cap, uint64_t *total);

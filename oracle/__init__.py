@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
+                               "-pthread", "-shared", "-fPIC", "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -61,7 +61,10 @@ def _load():
                                   ctypes.c_uint32, ctypes.c_double, P, P, P, P, P, P, P]
         lib.lro_render.restype = ctypes.c_int64
         lib.lro_render.argtypes = [ctypes.c_uint32, P, P, P, P, P, P, P, P, ctypes.c_uint32,
-                                   ctypes.c_uint32, ctypes.c_int, P, P, P, P, P]
+                                   ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, ctypes.c_uint32]
+        lib.lro_count.restype = ctypes.c_int64
+        lib.lro_count.argtypes = [ctypes.c_uint32, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32, P,
+                                  ctypes.c_uint32]
         lib.lro_pixels.restype = ctypes.c_int64
         lib.lro_pixels.argtypes = [ctypes.c_uint32, P, P, P, P, P, P, P, P, ctypes.c_uint32,
                                    ctypes.c_int, ctypes.c_uint32, P, P, P, P, P, ctypes.c_uint64]
@@ -134,34 +137,55 @@ def setup(v: np.ndarray, camera, W: int, H: int) -> Setup:
     return s
 
 
+def default_threads() -> int:
+    """Worker threads of a whole-frame render: the host cores this process
+    may run on, at most 16 (LR_ORACLE_THREADS overrides)."""
+    env = os.environ.get("LR_ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bool = False,
-           want_order: bool = True, st: Optional[Setup] = None) -> Dict[str, np.ndarray]:
+           want_order: bool = True, st: Optional[Setup] = None,
+           threads: Optional[int] = None) -> Dict[str, np.ndarray]:
     """Whole-frame reference render.  Returns rgba_f64 [H,W,4], rgba8 [H,W,4],
-    count [H,W], order_offsets [W*H+1], order_ids [total], setup."""
+    count [H,W], order_offsets [W*H+1], order_ids [total], setup, and the
+    number of worker threads used (row bands; the result does not depend on
+    it)."""
     lib = _load()
     st = st or setup(v, camera, W, H)
+    threads = default_threads() if threads is None else max(1, int(threads))
     rgba = np.ascontiguousarray(rgba, np.uint32)
     npix = W * H
     out_f = np.zeros((H, W, 4), np.float64)
     out_8 = np.zeros((H, W, 4), np.uint8)
     cnt = np.zeros((H, W), np.uint32)
     n = st.n
-    # first pass for the total so the id buffer can be sized
-    total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
-                           _p(st.cull), _p(rgba), W, H, int(unsorted), _p(out_f), _p(out_8),
-                           _p(cnt), None, None) if n else 0
-    if total < 0:
-        raise MemoryError("oracle render failed")
-    res = {"rgba_f64": out_f, "rgba8": out_8, "count": cnt, "setup": st, "total": int(total)}
+    res = {"rgba_f64": out_f, "rgba8": out_8, "count": cnt, "setup": st, "threads": threads}
     if want_order:
+        # the fragment total sizes the id buffer
+        total = lib.lro_count(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.cull), W, H, _p(cnt),
+                              threads) if n else 0
         off = np.zeros(npix + 1, np.uint64)
         ids = np.zeros(max(int(total), 1), np.uint32)
         if n:
-            lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
-                           _p(st.cull), _p(rgba), W, H, int(unsorted), None, None, _p(cnt),
-                           _p(off), _p(ids))
+            total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
+                                   _p(st.cull), _p(rgba), W, H, int(unsorted), _p(out_f), _p(out_8),
+                                   _p(cnt), _p(off), _p(ids), threads)
         res["order_offsets"] = off
-        res["order_ids"] = ids[:int(total)]
+        res["order_ids"] = ids[:max(int(total), 0)]
+    else:
+        total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
+                               _p(st.cull), _p(rgba), W, H, int(unsorted), _p(out_f), _p(out_8),
+                               _p(cnt), None, None, threads) if n else 0
+    if total < 0:
+        raise MemoryError("oracle render failed")
+    res["total"] = int(total)
     return res
 
 

@@ -47,6 +47,7 @@
  *   unsorted quad index order, "over": C = a c + (1-a) C, al = a + (1-a) al.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -307,27 +308,182 @@ static uint8_t to_u8(double x)
  * order_offsets[W*H+1] and order_ids[...] (fragment quad indices in blend
  * order; pass NULL to skip).  Returns the total number of fragments, or -1 on
  * allocation failure.
+ *
+ * The work is split over `threads` workers (0 or 1: serial) by bands
+ * of kBandRows screen rows taken from a shared counter.  A band's worker
+ * visits every quad, in index order, for the rows of its band only, so every
+ * pixel gets the same fragment list, in the same order, as one serial walk
+ * over the quads; the per-pixel arithmetic is the same code either way.
  */
+#define LRO_BAND_ROWS 8u
+
+typedef struct {
+    /* inputs */
+    uint32_t n, W, H;
+    const int32_t *X, *Y, *bbox;
+    const double *A, *B, *C0;
+    const uint8_t *cull;
+    const uint32_t *rgba;
+    int unsorted;
+    /* outputs and work arrays */
+    double *rgba_f64;
+    uint8_t *rgba8;
+    uint32_t *count;
+    const uint64_t *off;
+    uint64_t *fill;
+    frag_t *fr;
+    uint32_t *order_ids;
+    /* band queue */
+    int phase;              /* 0 count, 1 fill, 2 order and blend */
+    uint32_t nbands;
+    uint32_t next;          /* next band (shared) */
+    pthread_mutex_t mu;
+} lro_job;
+
+static void band_rows(const lro_job *jb, uint32_t band, int32_t *j0, int32_t *j1)
+{
+    *j0 = (int32_t)(band * LRO_BAND_ROWS);
+    *j1 = (int32_t)(band * LRO_BAND_ROWS + LRO_BAND_ROWS - 1);
+    if (*j1 > (int32_t)jb->H - 1)
+        *j1 = (int32_t)jb->H - 1;
+}
+
+/* Pass 1 (count) or pass 2 (fill) over the quads for rows j0..j1. */
+static void band_quads(lro_job *jb, int32_t j0, int32_t j1, int fill_pass)
+{
+    const uint32_t W = jb->W;
+    for (uint32_t q = 0; q < jb->n; q++) {
+        if (jb->cull[q] != LRO_VISIBLE)
+            continue;
+        const int32_t *bb = jb->bbox + 4 * (size_t)q;
+        const int32_t ja = bb[2] > j0 ? bb[2] : j0, jz = bb[3] < j1 ? bb[3] : j1;
+        for (int32_t j = ja; j <= jz; j++)
+            for (int32_t i = bb[0]; i <= bb[1]; i++)
+                if (lro_covers(jb->X + 4 * (size_t)q, jb->Y + 4 * (size_t)q, i, j)) {
+                    size_t p = (size_t)j * W + i;
+                    if (!fill_pass) {
+                        jb->count[p]++;
+                    } else {
+                        float k = lro_key(jb->A[q], jb->B[q], jb->C0[q], bb, i, j);
+                        jb->fr[jb->fill[p]].key = order_key(k, q);
+                        jb->fr[jb->fill[p]].rgba = jb->rgba[q];
+                        jb->fill[p]++;
+                    }
+                }
+    }
+}
+
+/* Pass 3 for the pixels of rows j0..j1: order and blend. */
+static void band_blend(lro_job *jb, int32_t j0, int32_t j1)
+{
+    for (size_t p = (size_t)j0 * jb->W; p < (size_t)(j1 + 1) * jb->W; p++) {
+        frag_t *pf = jb->fr + jb->off[p];
+        uint32_t cnt = jb->count[p];
+        double o[4];
+        if (jb->unsorted) {
+            blend_over(pf, cnt, o);
+        } else {
+            qsort(pf, cnt, sizeof(frag_t), cmp_frag);
+            blend_front_to_back(pf, cnt, o);
+        }
+        for (int ch = 0; ch < 4; ch++) {
+            if (jb->rgba_f64) jb->rgba_f64[4 * p + ch] = o[ch];
+            if (jb->rgba8) jb->rgba8[4 * p + ch] = to_u8(o[ch]);
+        }
+        if (jb->order_ids)
+            for (uint32_t t = 0; t < cnt; t++)
+                jb->order_ids[jb->off[p] + t] = (uint32_t)(pf[t].key & 0xffffffffu);
+    }
+}
+
+static void *band_worker(void *arg)
+{
+    lro_job *jb = (lro_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&jb->mu);
+        uint32_t band = jb->next++;
+        pthread_mutex_unlock(&jb->mu);
+        if (band >= jb->nbands)
+            break;
+        int32_t j0, j1;
+        band_rows(jb, band, &j0, &j1);
+        if (jb->phase == 2)
+            band_blend(jb, j0, j1);
+        else
+            band_quads(jb, j0, j1, jb->phase);
+    }
+    return NULL;
+}
+
+/* Runs one phase over all bands on `threads` workers (the caller is one). */
+static void run_phase(lro_job *jb, int phase, uint32_t threads)
+{
+    jb->phase = phase;
+    jb->next = 0;
+    pthread_t tid[256];
+    uint32_t started = 0;
+    for (uint32_t t = 1; t < threads && t < 256; t++)
+        if (pthread_create(&tid[started], NULL, band_worker, jb) == 0)
+            started++;
+    band_worker(jb);
+    for (uint32_t t = 0; t < started; t++)
+        pthread_join(tid[t], NULL);
+}
+
+static uint32_t pick_threads(uint32_t threads)
+{
+    if (threads == 0)
+        return 1u;
+    return threads > 256 ? 256u : threads;
+}
+
+static void job_init(lro_job *jb, uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
+                     const double *A, const double *B, const double *C0, const uint8_t *cull,
+                     const uint32_t *rgba, uint32_t W, uint32_t H, int unsorted, uint32_t *count)
+{
+    memset(jb, 0, sizeof(*jb));
+    jb->n = n; jb->W = W; jb->H = H;
+    jb->X = X; jb->Y = Y; jb->bbox = bbox;
+    jb->A = A; jb->B = B; jb->C0 = C0;
+    jb->cull = cull; jb->rgba = rgba; jb->unsorted = unsorted;
+    jb->count = count;
+    jb->nbands = (H + LRO_BAND_ROWS - 1) / LRO_BAND_ROWS;
+    pthread_mutex_init(&jb->mu, NULL);
+}
+
+/* Fragments of the frame (pass 1 only): count[H][W] and the total. */
+int64_t lro_count(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
+                  const uint8_t *cull, uint32_t W, uint32_t H, uint32_t *count, uint32_t threads)
+{
+    lro_job jb;
+    job_init(&jb, n, X, Y, bbox, NULL, NULL, NULL, cull, NULL, W, H, 0, count);
+    memset(count, 0, (size_t)W * H * sizeof(uint32_t));
+    run_phase(&jb, 0, pick_threads(threads));
+    pthread_mutex_destroy(&jb.mu);
+    uint64_t total = 0;
+    for (size_t p = 0; p < (size_t)W * H; p++)
+        total += count[p];
+    return (int64_t)total;
+}
+
 int64_t lro_render(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
                    const double *A, const double *B, const double *C0, const uint8_t *cull,
                    const uint32_t *rgba, uint32_t W, uint32_t H, int unsorted, double *rgba_f64,
-                   uint8_t *rgba8, uint32_t *count, uint64_t *order_offsets, uint32_t *order_ids)
+                   uint8_t *rgba8, uint32_t *count, uint64_t *order_offsets, uint32_t *order_ids,
+                   uint32_t threads)
 {
     const size_t npix = (size_t)W * H;
+    threads = pick_threads(threads);
+    lro_job jb;
+    job_init(&jb, n, X, Y, bbox, A, B, C0, cull, rgba, W, H, unsorted, count);
     uint64_t *off = (uint64_t *)calloc(npix + 1, sizeof(uint64_t));
-    if (!off)
+    if (!off) {
+        pthread_mutex_destroy(&jb.mu);
         return -1;
+    }
     memset(count, 0, npix * sizeof(uint32_t));
     /* pass 1: fragment count per pixel */
-    for (uint32_t q = 0; q < n; q++) {
-        if (cull[q] != LRO_VISIBLE)
-            continue;
-        const int32_t *bb = bbox + 4 * (size_t)q;
-        for (int32_t j = bb[2]; j <= bb[3]; j++)
-            for (int32_t i = bb[0]; i <= bb[1]; i++)
-                if (lro_covers(X + 4 * (size_t)q, Y + 4 * (size_t)q, i, j))
-                    count[(size_t)j * W + i]++;
-    }
+    run_phase(&jb, 0, threads);
     for (size_t p = 0; p < npix; p++)
         off[p + 1] = off[p] + count[p];
     const uint64_t total = off[npix];
@@ -335,45 +491,23 @@ int64_t lro_render(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
     uint64_t *fill = (uint64_t *)malloc((npix ? npix : 1) * sizeof(uint64_t));
     if (!fr || !fill) {
         free(off); free(fr); free(fill);
+        pthread_mutex_destroy(&jb.mu);
         return -1;
     }
     memcpy(fill, off, npix * sizeof(uint64_t));
+    jb.off = off;
+    jb.fill = fill;
+    jb.fr = fr;
+    jb.rgba_f64 = rgba_f64;
+    jb.rgba8 = rgba8;
+    jb.order_ids = order_ids;
     /* pass 2: fragments, appended in quad index order */
-    for (uint32_t q = 0; q < n; q++) {
-        if (cull[q] != LRO_VISIBLE)
-            continue;
-        const int32_t *bb = bbox + 4 * (size_t)q;
-        for (int32_t j = bb[2]; j <= bb[3]; j++)
-            for (int32_t i = bb[0]; i <= bb[1]; i++)
-                if (lro_covers(X + 4 * (size_t)q, Y + 4 * (size_t)q, i, j)) {
-                    size_t p = (size_t)j * W + i;
-                    float k = lro_key(A[q], B[q], C0[q], bb, i, j);
-                    fr[fill[p]].key = order_key(k, q);
-                    fr[fill[p]].rgba = rgba[q];
-                    fill[p]++;
-                }
-    }
-    /* per pixel: order and blend */
-    for (size_t p = 0; p < npix; p++) {
-        frag_t *pf = fr + off[p];
-        uint32_t cnt = count[p];
-        double o[4];
-        if (unsorted) {
-            blend_over(pf, cnt, o);
-        } else {
-            qsort(pf, cnt, sizeof(frag_t), cmp_frag);
-            blend_front_to_back(pf, cnt, o);
-        }
-        for (int ch = 0; ch < 4; ch++) {
-            if (rgba_f64) rgba_f64[4 * p + ch] = o[ch];
-            if (rgba8) rgba8[4 * p + ch] = to_u8(o[ch]);
-        }
-    }
+    run_phase(&jb, 1, threads);
+    /* pass 3: per pixel, order and blend */
+    run_phase(&jb, 2, threads);
     if (order_offsets)
         memcpy(order_offsets, off, (npix + 1) * sizeof(uint64_t));
-    if (order_ids)
-        for (uint64_t t = 0; t < total; t++)
-            order_ids[t] = (uint32_t)(fr[t].key & 0xffffffffu);
+    pthread_mutex_destroy(&jb.mu);
     free(fr); free(fill); free(off);
     return (int64_t)total;
 }

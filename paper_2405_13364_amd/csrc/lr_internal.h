@@ -170,6 +170,8 @@ struct FrameArgs {
     const uint32_t *dbg_off;
     uint32_t *dbg_ids;
     uint32_t dbg_cap;
+    // device word receiving the frame's error bits (may be null)
+    uint32_t *status;
 };
 
 // Frames per batched launch: the frame map travels in the kernel arguments.

@@ -1948,6 +1948,9 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
         const uint2 *__restrict__ bbox = a.bbox;
         const uint32_t *__restrict__ pairs = a.pairs;
         clear_next_counters(a, blk, nblk);
+        // every error bit of the frame is set by the earlier kernels
+        if (a.status && blk == 0 && threadIdx.x == 0)
+            *a.status = a.ctr->error;
         if (a.ctr->error & kErrPairs)
             continue;
         // the frame's flagged pixels: one queue stripe per lane (kQueues == 64)

@@ -128,7 +128,6 @@ struct lr_context_s {
     hipStream_t stream = nullptr;
     char *arena = nullptr;
     uint64_t arena_bytes = 0;
-    bool own_arena = false;
     lr_config cfg{};
     Arena alloc;
     std::map<lr_scene, SceneRec> scenes;
@@ -758,6 +757,7 @@ lr_status batch_impl(lr_context ctx, const lr_request *reqs, uint32_t n, hipStre
             const lr_request &r = reqs[i0 + f];
             const Plan &pl = plans[i0 + f];
             fill_args(ctx, ctx->scenes[r.scene], &r.camera, r.out_rgba8, pl, base + o, host[f]);
+            host[f].status = r.status;
             tag_frame(ctx, r.scene, pl, host[f]);
             ks[f] = (int)tunes[i0 + f].k;
             frames.push_back(FrameRef{slot->off + o + pl.o_ctr, pl.n, (int)(slot - ctx->slots.data())});
@@ -826,7 +826,9 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         return fail(nullptr, LR_ERR_INVALID_ARG, "batch_slots must be at most 8");
     if (!lr::sorter_depth_supported((int)c.sorter_depth))
         return fail(nullptr, LR_ERR_INVALID_ARG, "sorter_depth must be one of 2, 4, 8, 12, 16, 24, 32");
-    if (c.arena && c.arena_bytes < (1u << 20))
+    if (!c.arena)
+        return fail(nullptr, LR_ERR_INVALID_ARG, "arena is NULL: the caller provides the device arena");
+    if (c.arena_bytes < (1u << 20))
         return fail(nullptr, LR_ERR_INVALID_ARG, "arena must be at least 1 MiB");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
@@ -845,20 +847,8 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         return hip_fail(nullptr, e, "hipSetDevice");
     }
     ctx->stream = reinterpret_cast<hipStream_t>(c.stream);
-    if (c.arena) {
-        ctx->arena = reinterpret_cast<char *>(c.arena);
-        ctx->arena_bytes = c.arena_bytes;
-    } else {
-        ctx->arena_bytes = c.arena_bytes ? c.arena_bytes : (1ull << 30);
-        void *p = nullptr;
-        e = hipMalloc(&p, ctx->arena_bytes);
-        if (e != hipSuccess) {
-            delete ctx;
-            return fail(nullptr, LR_ERR_OUT_OF_MEMORY, "hipMalloc of the arena failed");
-        }
-        ctx->arena = reinterpret_cast<char *>(p);
-        ctx->own_arena = true;
-    }
+    ctx->arena = reinterpret_cast<char *>(c.arena);
+    ctx->arena_bytes = c.arena_bytes;
     ctx->alloc.init(ctx->arena_bytes);
     ctx->timing = (c.flags & LR_FLAG_TIMING) != 0;
     ctx->use_graphs = (c.flags & LR_FLAG_NO_GRAPH) == 0;
@@ -921,8 +911,6 @@ lr_status lr_destroy(lr_context ctx)
             (void)hipEventDestroy(e);
     if (ctx->host_ctr)
         (void)hipHostFree(ctx->host_ctr);
-    if (ctx->own_arena && ctx->arena)
-        (void)hipFree(ctx->arena);
     delete ctx;
     return LR_OK;
 }
@@ -940,7 +928,11 @@ lr_status lr_upload_scene(lr_context ctx, const lr_quad *q, uint32_t n, int q_on
     float *v = reinterpret_cast<float *>(ctx->arena + off);
     uint32_t *rgba = reinterpret_cast<uint32_t *>(ctx->arena + off + 48ull * n);
     if (q_on_device) {
+        // waits, so q may be freed on return and renders on any stream see
+        // the scene
         hipError_t e = lr::launch_transpose_scene(q, n, v, rgba, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) {
             ctx->alloc.release(off);
             return hip_fail(ctx, e, "scene transpose");

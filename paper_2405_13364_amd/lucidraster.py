@@ -25,6 +25,8 @@ LR_ERR_NOT_FOUND = -5
 LR_ERR_BUSY = -6
 LR_FLAG_TIMING = 1
 LR_FLAG_NO_GRAPH = 2
+LR_FRAME_ERR_CAPACITY = 1
+LR_FRAME_ERR_DENSE = 4
 
 SORTER_DEPTHS = (2, 4, 8, 12, 16, 24, 32)
 BIN_SIZES = (16, 32, 64)
@@ -64,7 +66,8 @@ class Request(ctypes.Structure):
     _fields_ = [("scene", ctypes.c_uint64), ("camera", Camera), ("width", ctypes.c_uint32),
                 ("height", ctypes.c_uint32), ("out_rgba8", ctypes.c_void_p),
                 ("bin_size", ctypes.c_uint32), ("sorter_depth", ctypes.c_uint32),
-                ("block_h", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("block_h", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("status", ctypes.c_void_p)]
 
 
 class TuneRule(ctypes.Structure):
@@ -286,7 +289,7 @@ class Context:
         return res
 
     @staticmethod
-    def _request(req, out_ptr=None) -> Request:
+    def _request(req, out_ptr=None, status_ptr=None) -> Request:
         """(scene, cam, W, H, out[, bin_size[, sorter_depth[, block_h]]]) -> lr_request;
         missing or None tuning fields are 0 (tuning rules, then context defaults)."""
         scene, cam, W, H, out = req[:5]
@@ -299,15 +302,18 @@ class Context:
         r.bin_size = tune[0] or 0
         r.sorter_depth = tune[1] or 0
         r.block_h = tune[2] or 0
+        r.status = status_ptr
         return r
 
-    def render_batch(self, reqs, stream=None, check: bool = True):
+    def render_batch(self, reqs, stream=None, check: bool = True, status=None):
         """Render a list of requests (scene, cam, W, H, out[, bin_size, sorter_depth,
         block_h]) in batched launches.  With check, waits and re-renders once if a
-        capacity was exceeded."""
+        capacity was exceeded.  status: an int32 device tensor of len(reqs)
+        receiving each frame's LR_FRAME_ERR_* bits (stream ordered)."""
         arr = (Request * len(reqs))()
         for k, req in enumerate(reqs):
-            arr[k] = self._request(req)
+            sp = None if status is None else int(status.data_ptr()) + 4 * k
+            arr[k] = self._request(req, status_ptr=sp)
         for attempt in range(2):
             self._check(self.lib.lr_render_batch(self.h, arr, len(reqs), self._stream(stream)), self.h)
             if not check:

@@ -226,3 +226,22 @@ def from_quads(quads: List[Tuple[np.ndarray, int]], width: int, height: int,
     v = np.stack([q[0] for q in quads]).astype(np.float32) if quads else np.zeros((0, 4, 3), np.float32)
     rgba = np.array([q[1] for q in quads], dtype=np.uint32)
     return Scene(v=v, rgba=rgba, width=width, height=height, camera=cam or Camera(), name=name)
+
+
+def twisted(width: int, height: int, n: int, seed: int, extent=(2.0, 10.0),
+            depths=(0.5, 1.0, 20.0, 60.0)) -> Scene:
+    """Non-planar quads: four corners drawn independently around a random
+    centre, each at a view depth drawn from `depths`.  The plane fitted to
+    such a quad can pass behind the camera over part of its screen area, so
+    these frames hold fragments whose depth key is clamped to zero."""
+    rng = np.random.default_rng(seed)
+    quads = []
+    for _ in range(n):
+        cx, cy = rng.uniform(0.0, width), rng.uniform(0.0, height)
+        e = rng.uniform(*extent)
+        corners = [(cx + rng.uniform(-e, e), cy + rng.uniform(-e, e)) for _ in range(4)]
+        zs = [float(z) for z in rng.choice(np.asarray(depths, np.float64), 4)]
+        rgb = rng.integers(0, 256, 3)
+        rgba = int(pack_rgba(int(rgb[0]), int(rgb[1]), int(rgb[2]), int(rng.integers(20, 236))))
+        quads.append((screen_quad(corners, zs, width, height), rgba))
+    return from_quads(quads, width, height, name=f"twisted{width}x{height}n{n}s{seed}")

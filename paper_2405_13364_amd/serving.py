@@ -127,17 +127,27 @@ def token_batch(token) -> int:
 
 class GpuBackend:
     """Drives the library: one torch stream per slot, output buffers pooled
-    per frame size (or kept, for checking), completion by stream events."""
+    per frame size (or kept, for checking), completion by stream events.
 
-    def __init__(self, ctx, slots: int, keep_outputs: bool = False, keep_every: int = 0):
+    Every batch also reports each frame's error bits (lr_request.status) into
+    a device tensor, copied to pinned host memory on the slot's stream before
+    the completion event.  A frame whose bin lists overflowed (its image was
+    not written) is rendered again once its batch is done: the library's
+    capacity hint is raised (lr_sync) and the failed frames are re-submitted
+    on the same slot, so the request completes only with its exact image."""
+
+    def __init__(self, ctx, slots: int, keep_outputs: bool = False, keep_every: int = 0,
+                 max_retries: int = 2):
         import torch
         self.torch = torch
         self.ctx = ctx
         self.streams = [torch.cuda.Stream(device=ctx.device) for _ in range(slots)]
         self.keep = keep_outputs
         self.keep_every = keep_every
+        self.max_retries = max_retries
         self.outputs: Dict[int, object] = {}
         self.pool: Dict[Tuple[int, int], List[object]] = {}
+        self.retried: List[int] = []     # request ids rendered again after a capacity error
         self.t0 = time.perf_counter()
 
     def start_clock(self):
@@ -159,16 +169,50 @@ class GpuBackend:
             return free.pop()
         return self.ctx.new_image(W, H)
 
+    def _launch(self, slot: int, reqs: List[Request], outs: List[object]):
+        torch = self.torch
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            status_dev = torch.empty(len(reqs), dtype=torch.int32, device=f"cuda:{self.ctx.device}")
+            self.ctx.render_batch([(r.scene, r.camera, r.width, r.height, o) + tuple(r.tune)
+                                   for r, o in zip(reqs, outs)], stream=st, check=False, status=status_dev)
+            status_host = torch.empty(len(reqs), dtype=torch.int32, pin_memory=True)
+            status_host.copy_(status_dev, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        return ev, status_dev, status_host
+
     def submit(self, slot: int, reqs: List[Request], batch_id: int):
         outs = [self._image(r.width, r.height, r.rid) for r in reqs]
-        self.ctx.render_batch([(r.scene, r.camera, r.width, r.height, o) + tuple(r.tune)
-                               for r, o in zip(reqs, outs)], stream=self.streams[slot], check=False)
-        ev = self.torch.cuda.Event()
-        ev.record(self.streams[slot])
-        return {"event": ev, "outs": outs, "reqs": reqs, "batch": batch_id}
+        ev, sd, sh = self._launch(slot, reqs, outs)
+        # 'idx': the requests of this token whose frames the last launch covered
+        return {"event": ev, "outs": outs, "reqs": reqs, "batch": batch_id, "slot": slot,
+                "status_dev": sd, "status": sh, "idx": list(range(len(reqs))), "tries": 0}
 
     def done(self, token) -> bool:
-        return token["event"].query()
+        if not token["event"].query():
+            return False
+        from .lucidraster import LR_ERR_CAPACITY, LR_FRAME_ERR_CAPACITY, LRError
+        st = token["status"].numpy()
+        bad = [token["idx"][k] for k in range(len(token["idx"])) if int(st[k]) & LR_FRAME_ERR_CAPACITY]
+        if not bad:
+            return True
+        if token["tries"] >= self.max_retries:
+            raise RuntimeError(f"requests {[token['reqs'][k].rid for k in bad]} overflowed their bin lists "
+                               f"{token['tries'] + 1} times")
+        # raise the capacity hints (waits for the device), then render the
+        # failed frames again on the same slot
+        try:
+            self.ctx.sync()
+        except LRError as e:
+            if e.status != LR_ERR_CAPACITY:
+                raise
+        reqs = [token["reqs"][k] for k in bad]
+        outs = [token["outs"][k] for k in bad]
+        self.retried.extend(r.rid for r in reqs)
+        ev, sd, sh = self._launch(token["slot"], reqs, outs)
+        token.update(event=ev, status_dev=sd, status=sh, idx=bad, tries=token["tries"] + 1)
+        return False
 
     def release(self, token):
         for r, o in zip(token["reqs"], token["outs"]):

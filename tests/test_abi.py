@@ -49,16 +49,16 @@ def test_header_compiles(lang, compiler, tmp_path):
 def test_struct_layouts(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lucidraster.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lr_quad), sizeof(lr_camera),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(lr_quad), sizeof(lr_camera),'
                    ' sizeof(lr_config), sizeof(lr_stats), sizeof(lr_request), offsetof(lr_request, out_rgba8),'
-                   ' offsetof(lr_request, block_h), sizeof(lr_tune_rule));'
+                   ' offsetof(lr_request, block_h), sizeof(lr_tune_rule), offsetof(lr_request, status));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)], text=True).split()]
     want = [52, ctypes.sizeof(lr.Camera), ctypes.sizeof(lr.Config), ctypes.sizeof(lr.Stats),
             ctypes.sizeof(lr.Request), lr.Request.out_rgba8.offset, lr.Request.block_h.offset,
-            ctypes.sizeof(lr.TuneRule)]
+            ctypes.sizeof(lr.TuneRule), lr.Request.status.offset]
     assert got == want
 
 
@@ -71,8 +71,13 @@ def test_status_strings(lib):
 def test_argument_errors_need_no_device(lib):
     h = ctypes.c_void_p()
     assert lib.lr_create(None, ctypes.byref(h)) == lr.LR_ERR_INVALID_ARG
-    for field, bad in [("bin_size", 24), ("sorter_depth", 5), ("block_h", 3), ("batch_slots", 9)]:
-        cfg = lr.Config(device=0, bin_size=32, sorter_depth=8, block_h=8)
+    # the caller owns device memory: no arena is an error, not an allocation
+    cfg = lr.Config(device=0, bin_size=32, sorter_depth=8, block_h=8, arena=None, arena_bytes=1 << 30)
+    assert lib.lr_create(ctypes.byref(cfg), ctypes.byref(h)) == lr.LR_ERR_INVALID_ARG
+    assert b"arena" in lib.lr_last_error(None)
+    for field, bad in [("bin_size", 24), ("sorter_depth", 5), ("block_h", 3), ("batch_slots", 9),
+                       ("arena_bytes", 4096)]:
+        cfg = lr.Config(device=0, bin_size=32, sorter_depth=8, block_h=8, arena=0x10000, arena_bytes=1 << 20)
         setattr(cfg, field, bad)
         assert lib.lr_create(ctypes.byref(cfg), ctypes.byref(h)) == lr.LR_ERR_INVALID_ARG, field
         assert lib.lr_last_error(None)
@@ -90,7 +95,8 @@ def test_context_without_device_reports_device_error(lib):
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    cfg = lr.Config(device=0, bin_size=32, sorter_depth=8, block_h=8)
+    # a non-null arena address: the call gets as far as looking for a device
+    cfg = lr.Config(device=0, bin_size=32, sorter_depth=8, block_h=8, arena=0x10000, arena_bytes=1 << 20)
     h = ctypes.c_void_p()
     assert lib.lr_create(ctypes.byref(cfg), ctypes.byref(h)) == lr.LR_ERR_DEVICE
 

@@ -186,3 +186,28 @@ def test_tuning_rules_and_request_bytes(lr):
         ctx.set_tuning([{"max_pixels": 0, "max_quads_per_pixel": 1.0, "bin_size": 16, "block_h": 4,
                          "sorter_depth": 16}])
     ctx.close()
+
+
+def test_full_size_batch_against_oracle(lr):
+    """Frames of the 64-frame mixed batch at full size (1920x1080 with 165k,
+    301k and 368k quads, 1280x720 with 128k and 227k, and smaller ones), in
+    one batched call at the rule-table tuning: every pixel of every frame
+    against the oracle, and the batch's fragment total."""
+    from paper_2405_13364_amd import autotune
+    seeds = (1017, 1022, 1031, 1033, 1012, 1000, 1003, 1005)
+    frames = [scenes.mixed_scene(s) for s in seeds]
+    assert sum(1 for s in frames if (s.width, s.height) == (1920, 1080) and s.n >= 100_000) >= 3
+    ctx = lr.Context(arena_bytes=8 << 30, tuning=autotune.load_rules())
+    hs = [ctx.upload(s.v, s.rgba) for s in frames]
+    outs = [ctx.new_image(s.width, s.height) for s in frames]
+    ctx.render_batch([(h, s.camera, s.width, s.height, o) for h, s, o in zip(hs, frames, outs)])
+    ctx.render_batch([(h, s.camera, s.width, s.height, o) for h, s, o in zip(hs, frames, outs)])  # graph replay
+    st = ctx.stats()
+    total = 0
+    for s, o, seed in zip(frames, outs, seeds):
+        ref = oracle.render(s.v, s.rgba, s.camera, s.width, s.height, want_order=False)
+        d8 = np.abs(o.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32))
+        assert d8.max(initial=0) <= 1, f"seed {seed}: off by {d8.max()}"
+        total += ref["total"]
+    assert st["fragments"] == total
+    ctx.close()

@@ -83,6 +83,8 @@ SCENES = {
     "gauss": lambda: scenes.small(160, 120, 20000, 15, side=(1.0, 20.0), gaussian=True, alpha=(0.05, 0.5)),
     "general": lambda: general_quads(),
     "general_dense": lambda: general_quads(64, 48, 900, 32, extent=(2.0, 14.0), centre=(28.0, 20.0)),
+    # non-planar quads: fragments whose plane depth is not positive (key 0)
+    "twisted": lambda: scenes.twisted(72, 56, 1500, 41),
 }
 
 
@@ -287,6 +289,131 @@ def test_c2_full_frame(lr):
     ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
     got = gpu_render(lr, ctx_for(lr), sc)
     check_frame(got, ref, "c2")
+
+
+def rule_tuning(sc):
+    """(bin, sorter depth, block height) the library's rule table picks."""
+    from paper_2405_13364_amd import autotune
+    return tuple(autotune.resolve(autotune.load_rules(), sc.width, sc.height, sc.n))
+
+
+_c3_ref = {}
+
+
+def c3_reference():
+    if "ref" not in _c3_ref:
+        sc = scenes.scene("c3")
+        _c3_ref["sc"] = sc
+        _c3_ref["ref"] = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    return _c3_ref["sc"], _c3_ref["ref"]
+
+
+@pytest.mark.parametrize("tune", ["rules", (32, 8, 4)])
+def test_c3_full_frame(lr, tune):
+    """The whole 1920x1080 frame of 1M quads (106 M fragments, up to ~300 per
+    pixel at the centre): every pixel's count, blend order and colour."""
+    sc, ref = c3_reference()
+    b, k, bh = rule_tuning(sc) if tune == "rules" else tune
+    if tune == "rules":
+        assert (b, k, bh) == (16, 8, 8)  # the tuning the benchmark times
+    ctx = lr.Context(arena_bytes=1 << 30, bin_size=b, sorter_depth=k, block_h=bh)
+    got = gpu_render(lr, ctx, sc, order=True)
+    assert int(got["flagged"].sum().item()) > 0  # the exact pass took part
+    check_frame(got, ref, f"c3 bin {b} K {k} 8x{bh}")
+    ctx.close()
+
+
+def test_c3_production_kernels(lr):
+    """The same frame through lr_render (no parity dumps: the kernels the
+    benchmark times) at the rule-table tuning: RGBA8 on every pixel and the
+    fragment statistics against the oracle."""
+    from paper_2405_13364_amd import autotune
+    sc, ref = c3_reference()
+    ctx = lr.Context(arena_bytes=1 << 30, tuning=autotune.load_rules())
+    h = ctx.upload(sc.v, sc.rgba)
+    img = ctx.render(h, sc.camera, sc.width, sc.height)
+    st = ctx.stats()
+    d8 = np.abs(img.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32))
+    assert d8.max() <= 1
+    assert st["fragments"] == ref["total"]
+    assert st["visible"] == ref["setup"].cull_counts()["visible"]
+    assert st["flagged_pixels"] > 0 and st["error_word"] == 0
+    ctx.close()
+
+
+def test_c2b_full_frame(lr):
+    sc = scenes.scene("c2b")
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    ctx = lr.Context(arena_bytes=1 << 30, bin_size=32, sorter_depth=8)
+    got = gpu_render(lr, ctx, sc)
+    check_frame(got, ref, "c2b")
+    ctx.close()
+
+
+def test_equal_depth_stack_takes_the_exact_pass(lr):
+    """1,200 quads at one depth over the same 16x16 pixels: every block holds
+    more equal-key entries than one on-chip sort, so no depth slice fits and
+    the blocks' pixels go to the exact per-pixel sort.  Order is by quad
+    index alone."""
+    W, H = 48, 40
+    rng = np.random.default_rng(77)
+    quads = []
+    for q in range(1200):
+        rgb = rng.integers(0, 256, 3)
+        rgba = int(scenes.pack_rgba(int(rgb[0]), int(rgb[1]), int(rgb[2]), int(rng.integers(5, 60))))
+        quads.append((scenes.screen_quad([(8.1, 8.1), (23.9, 8.1), (23.9, 23.9), (8.1, 23.9)], 4.0, W, H), rgba))
+    sc = scenes.from_quads(quads, W, H, name="equal_depth_stack")
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, W, H)
+    assert int(ref["count"].max()) == 1200
+    for k, bh in [(8, 8), (32, 4)]:
+        ctx = lr.Context(arena_bytes=256 << 20, bin_size=32, sorter_depth=k, block_h=bh)
+        h = ctx.upload(sc.v, sc.rgba)
+        got = ctx.render_debug(h, sc.camera, W, H, order=True)
+        st = ctx.stats()
+        check_frame(got, ref, f"equal-depth stack K {k} 8x{bh}")
+        assert st["error_word"] & lr.LR_FRAME_ERR_DENSE
+        assert st["dense_blocks"] >= 4 and st["flagged_pixels"] == 256
+        ctx.close()
+
+
+@pytest.mark.parametrize("k", [8, 12])
+@pytest.mark.parametrize("name", ["gauss", "c1", "twisted"])
+def test_sixteen_wave_raster_without_dumps(lr, name, k):
+    """Bin 64 at sorter depth 8 or 12 runs the raster with 16 waves per
+    workgroup, a configuration the parity dumps (which keep 8 waves past
+    depth 4) never take: RGBA8 and fragment statistics against the oracle."""
+    sc = SCENES[name]()
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False)
+    ctx = lr.Context(arena_bytes=256 << 20, bin_size=64, sorter_depth=k)
+    h = ctx.upload(sc.v, sc.rgba)
+    img = ctx.render(h, sc.camera, sc.width, sc.height)
+    st = ctx.stats()
+    d8 = np.abs(img.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32))
+    assert d8.max(initial=0) <= 1
+    assert st["fragments"] == ref["total"]
+    ctx.close()
+
+
+def test_upload_from_device_memory(lr):
+    """lr_upload_scene from a device buffer of packed 52-byte quads gives the
+    same image as the host upload; the buffer may be freed on return."""
+    import torch
+    sc = SCENES["gauss"]()
+    ctx = ctx_for(lr)
+    dev = torch.from_numpy(sc.quad_records().view(np.uint8).reshape(-1).copy()).cuda()
+    h_dev = ctx.upload_device(dev)
+    del dev
+    torch.cuda.empty_cache()
+    junk = torch.full((sc.n * 52,), 0xAB, dtype=torch.uint8, device="cuda")  # reuses the freed memory
+    h_host = ctx.upload(sc.v, sc.rgba)
+    a = ctx.render(h_dev, sc.camera, sc.width, sc.height).cpu().numpy()
+    b = ctx.render(h_host, sc.camera, sc.width, sc.height).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False)
+    assert np.abs(a.astype(np.int32) - ref["rgba8"].astype(np.int32)).max() <= 1
+    del junk
+    ctx.release(h_dev)
+    ctx.release(h_host)
 
 
 def test_c3_sampled_pixels(lr):

@@ -28,11 +28,13 @@ MUTANTS = {
     "projection_y_up": ("sy[k] = fma(-f, qy, cy);", "sy[k] = fma(f, qy, cy);"),
     "diagonal_normal_sign": ("p = e1[0] * e2[1]; s = e1[1] * e2[0]; nn[2] = p - s;",
                              "p = e1[0] * e2[1]; s = e1[1] * e2[0]; nn[2] = s - p;"),
+    "key_clamp_dropped": ("    if (!(k > 0.0f))\n        k = 0.0f;\n    return k;", "    return k;"),
     "unsorted_under": ("C[ch] = a * ((double)((c >> (8 * ch)) & 255u) / 255.0) + (1.0 - a) * C[ch];",
                        "C[ch] = (1.0 - a) * ((double)((c >> (8 * ch)) & 255u) / 255.0) + a * C[ch];"),
 }
 
-PINS = ["tests/test_oracle_hand.py", "tests/test_oracle_bruteforce.py", "tests/test_oracle_invariants.py"]
+PINS = ["tests/test_oracle_hand.py", "tests/test_oracle_bruteforce.py", "tests/test_oracle_invariants.py",
+        "tests/test_oracle_keys.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -43,7 +45,7 @@ def test_mutant_is_caught(name, tmp_path):
     mut = tmp_path / "mut.c"
     mut.write_text(src.replace(old, new))
     lib = tmp_path / "libmut.so"
-    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-shared", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-std=c99", "-pthread", "-shared", "-fPIC",
                            "-o", str(lib), str(mut), "-lm"])
     env = dict(os.environ, LR_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + PINS,
