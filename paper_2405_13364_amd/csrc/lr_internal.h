@@ -14,8 +14,9 @@ enum Cull : uint8_t { VISIBLE = 0, NEAR = 1, GUARD = 2, DEGENERATE = 3, NO_SAMPL
 // path.  Bound: |a*di + b*dj| <= 2*ext^2/256 + 16*ext < 2^30 for ext <= 2^18.
 constexpr int32_t kNarrowExtent = 1 << 18;
 
-// Per visible quad, everything the raster stage reads for one candidate, in
-// one 128-byte record (one L2 line, loaded with scalar loads per candidate).
+// Per visible quad, what the raster stage reads, split by when it is read
+// (attributes read together are stored together, as the paper's setup
+// stage does with its per-triangle storages, Stage 1, Phase 2).
 //
 // Half-plane h of triangle T (h = 3T + e) holds (a, b, t): the sample of pixel
 // (imin + di, jmin + dj) is inside edge e iff a*di + b*dj >= t.  A zero-area
@@ -24,16 +25,36 @@ constexpr int32_t kNarrowExtent = 1 << 18;
 // and R the sample of pixel (imin, jmin), E(S) = E(R) + 256 (a di + b dj), and
 // E(S) >= bias (bias 0 on top-left edges, 1 otherwise) iff
 // a di + b dj >= ceil((bias - E(R)) / 256).
-struct alignas(128) QuadRec {
-    int32_t hp[18];   // 6 x (a, b, t)                       bytes 0..71
-    uint32_t bb_i;    // imin | imax << 16                    72
-    uint32_t bb_j;    // jmin | jmax << 16                    76
-    uint32_t rgba;    //                                      80
-    uint32_t flags;   // kWide | triangle bits                84
-    double A, B, C0;  // reciprocal-depth plane (fp64)        88..111
-    uint32_t pad[4];  //                                      112..127
+//
+// CovRec: read for every (block, candidate quad) pair to build the coverage
+// mask: the first four half-planes (all of a convex quad's), bbox, flags,
+// colour.  64 bytes.
+struct alignas(64) CovRec {
+    int32_t hp[12];   // half-planes 0..3 (a, b, t)           bytes 0..47
+    uint32_t bb_i;    // imin | imax << 16                    48
+    uint32_t bb_j;    // jmin | jmax << 16                    52
+    uint32_t flags;   // kWide | kConvex | triangle bits      56
+    uint32_t rgba;    //                                      60
 };
-static_assert(sizeof(QuadRec) == 128, "QuadRec must be one 128-byte line");
+static_assert(sizeof(CovRec) == 64, "CovRec is 64 bytes");
+
+// PlaneRec: read for every non-empty entry and by the per-pixel walk: the
+// reciprocal-depth plane (fp64) relative to the bbox origin, that origin and
+// the colour.  32 bytes.
+struct alignas(32) PlaneRec {
+    double A, B, C0;
+    uint32_t ij;      // imin | jmin << 16
+    uint32_t rgba;
+};
+static_assert(sizeof(PlaneRec) == 32, "PlaneRec is 32 bytes");
+
+// ExtraRec: half-planes 4 and 5, written and read only for quads that are
+// not strictly convex (two triangles of three edges each).
+struct alignas(32) ExtraRec {
+    int32_t hp[6];
+    uint32_t pad[2];
+};
+static_assert(sizeof(ExtraRec) == 32, "ExtraRec is 32 bytes");
 
 constexpr uint32_t kWide = 1u;       // use the fp64 coverage path
 constexpr uint32_t kT0Valid = 2u;    // triangle (P0, P1, P2) has non-zero area
@@ -78,9 +99,13 @@ struct FrameCounters {
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
     uint32_t fb_next;          // next flagged pixel for the exact pass
-    uint32_t pad[29];
+    uint32_t fe_n;             // entries kept for the exact pass (may exceed fe_cap)
+    uint32_t pad[28];
     StatStripe stripe[kStripes];
 };
+
+// blk_ent of a flagged block whose entries were not kept
+constexpr uint32_t kNoEntries = 0xFFFFFFFFu;
 
 constexpr uint32_t kErrPairs = 1u;      // bin lists overflowed their capacity
 constexpr uint32_t kErrDense = 4u;      // a block could not be sliced to fit its list (pixels sent to the exact sort)
@@ -127,7 +152,9 @@ struct FrameArgs {
     double f, cx, cy;
     uint32_t W, H;
     // setup outputs
-    QuadRec *rec;
+    CovRec *cov;
+    PlaneRec *plane;
+    ExtraRec *extra;
     QuadXY *xy;
     uint2 *bbox;      // (imin | imax << 16, jmin | jmax << 16); culled: (0xffff, 0xffff)
     uint8_t *cull;
@@ -156,6 +183,14 @@ struct FrameArgs {
     uint32_t *ent_code;       // block depth code
     unsigned long long *ent_mask;  // 64-sample coverage mask
     uint32_t *ent_id;         // quad index
+    // entries of blocks with flagged pixels, kept for the exact pass: each
+    // block's entries that cover one of its flagged pixels, their masks
+    // restricted to those pixels, and the quad indices
+    unsigned long long *fe_mask;
+    uint32_t *fe_id;
+    uint32_t fe_cap;
+    uint2 *blk_ent;           // per 8x8 block with flagged pixels: (first, count) in fe_*,
+                              // or (kNoEntries, 0) when they did not fit (the bin list is walked)
     FrameCounters *ctr;
     // single frames: the other of the workspace's two counter sets, zeroed by
     // this frame's last kernel for the next frame (null: k_frame_begin zeroes ctr)

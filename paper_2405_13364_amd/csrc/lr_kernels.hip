@@ -331,10 +331,19 @@ __device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, double Rx,
     flags |= kConvex;
 }
 
+// A visible quad's setup results, held in registers; k_setup stores them
+// as the quad's CovRec, PlaneRec and, when it is not strictly convex, its
+// ExtraRec.
+struct QuadSetup {
+    int32_t hp[18];
+    uint32_t bb_i, bb_j, rgba, flags;
+    double A, B, C0;
+};
+
 // Setup of quad q (Stage 1): writes its snapped vertices, bbox and cull
-// reason, leaves the record of a visible quad in r (the caller stores it);
-// returns the reason (VISIBLE = 0).
-__device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q, QuadRec &r)
+// reason, leaves the records of a visible quad in r (the caller stores
+// them); returns the reason (VISIBLE = 0).
+__device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q, QuadSetup &r)
 {
     uint32_t reason = 0xff;
     {
@@ -468,14 +477,17 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q, Q
 // Quads per lane of the setup kernel (each workgroup takes 256 quads).
 constexpr uint32_t kSetupQPL = 1;
 
-// The workgroup's 256 records are contiguous in HBM (rec is indexed by quad).
-// A lane storing its own 128-byte record would issue eight stores whose lanes
-// sit 128 bytes apart, 64 partial lines each; instead the records are staged
-// in LDS and written as consecutive 16-byte chunks, one full line per eight
-// lanes.  In LDS, chunk c of row t sits at slot c ^ (t & 7), so the staging
-// writes of neighbouring rows fall in different banks.  Rows of culled quads
-// are written as zeros (nothing reads them).
-constexpr uint32_t kRecChunks = sizeof(QuadRec) / 16;
+// The workgroup's 256 coverage and plane records are contiguous in HBM
+// (indexed by quad).  A lane storing its own records would issue stores
+// whose lanes sit 64 or 32 bytes apart, partial lines each; instead the
+// records are staged in LDS and written as consecutive 16-byte chunks, whole
+// lines per group of lanes.  In LDS, chunk c of row t sits at slot c ^ (t &
+// (chunks - 1)), so the staging writes of neighbouring rows fall in
+// different banks.  Rows of culled quads are written as zeros (nothing reads
+// them).  The two extra half-planes of a quad that is not strictly convex
+// (rare) are stored by its own lane.
+constexpr uint32_t kCovChunks = sizeof(CovRec) / 16;
+constexpr uint32_t kPlaneChunks = sizeof(PlaneRec) / 16;
 
 template <class Src>
 __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
@@ -483,34 +495,44 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
     static_assert(kSetupQPL == 1, "record staging assumes one quad per lane");
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
-    __shared__ uint4 s_rec[256 * kRecChunks];
+    __shared__ uint4 s_cov[256 * kCovChunks];
+    __shared__ uint4 s_pl[256 * kPlaneChunks];
     uint32_t reasons[kSetupQPL];
     {
         const uint32_t t = threadIdx.x;
         const uint32_t q = blk * 256 + t;
-        QuadRec r;
+        QuadSetup r;
         reasons[0] = q < a.n ? setup_quad(a, q, r) : 0xffu;
-        uint4 ch[kRecChunks];
+        uint4 cc[kCovChunks], pc[kPlaneChunks];
         if (reasons[0] == VISIBLE) {
-            ch[0] = make_uint4(r.hp[0], r.hp[1], r.hp[2], r.hp[3]);
-            ch[1] = make_uint4(r.hp[4], r.hp[5], r.hp[6], r.hp[7]);
-            ch[2] = make_uint4(r.hp[8], r.hp[9], r.hp[10], r.hp[11]);
-            ch[3] = make_uint4(r.hp[12], r.hp[13], r.hp[14], r.hp[15]);
-            ch[4] = make_uint4(r.hp[16], r.hp[17], r.bb_i, r.bb_j);
+            cc[0] = make_uint4(r.hp[0], r.hp[1], r.hp[2], r.hp[3]);
+            cc[1] = make_uint4(r.hp[4], r.hp[5], r.hp[6], r.hp[7]);
+            cc[2] = make_uint4(r.hp[8], r.hp[9], r.hp[10], r.hp[11]);
+            cc[3] = make_uint4(r.bb_i, r.bb_j, r.flags, r.rgba);
             const unsigned long long ua = __double_as_longlong(r.A);
             const unsigned long long ub = __double_as_longlong(r.B);
             const unsigned long long uc = __double_as_longlong(r.C0);
-            ch[5] = make_uint4(r.rgba, r.flags, (uint32_t)ua, (uint32_t)(ua >> 32));
-            ch[6] = make_uint4((uint32_t)ub, (uint32_t)(ub >> 32), (uint32_t)uc, (uint32_t)(uc >> 32));
+            pc[0] = make_uint4((uint32_t)ua, (uint32_t)(ua >> 32), (uint32_t)ub, (uint32_t)(ub >> 32));
+            pc[1] = make_uint4((uint32_t)uc, (uint32_t)(uc >> 32), (r.bb_i & 0xffffu) | (r.bb_j << 16), r.rgba);
+            if (!(r.flags & kConvex)) {
+                uint4 *ex = reinterpret_cast<uint4 *>(a.extra + q);
+                ex[0] = make_uint4(r.hp[12], r.hp[13], r.hp[14], r.hp[15]);
+                ex[1] = make_uint4(r.hp[16], r.hp[17], 0u, 0u);
+            }
         } else {
 #pragma unroll
-            for (uint32_t c = 0; c < 7; c++)
-                ch[c] = make_uint4(0, 0, 0, 0);
-        }
-        ch[7] = make_uint4(0, 0, 0, 0);  // pad
+            for (uint32_t c = 0; c < kCovChunks; c++)
+                cc[c] = make_uint4(0, 0, 0, 0);
 #pragma unroll
-        for (uint32_t c = 0; c < kRecChunks; c++)
-            s_rec[t * kRecChunks + (c ^ (t & 7))] = ch[c];
+            for (uint32_t c = 0; c < kPlaneChunks; c++)
+                pc[c] = make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (uint32_t c = 0; c < kCovChunks; c++)
+            s_cov[t * kCovChunks + (c ^ (t & (kCovChunks - 1)))] = cc[c];
+#pragma unroll
+        for (uint32_t c = 0; c < kPlaneChunks; c++)
+            s_pl[t * kPlaneChunks + (c ^ (t & (kPlaneChunks - 1)))] = pc[c];
     }
     // cull statistics: one atomic per workgroup and reason, striped
     __shared__ uint32_t s_cull[6];
@@ -520,12 +542,19 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
     {
         const uint32_t q0 = blk * 256;
         const uint32_t rows = q0 < a.n ? min(256u, a.n - q0) : 0u;
-        uint4 *dst = reinterpret_cast<uint4 *>(a.rec + q0);
+        uint4 *dc = reinterpret_cast<uint4 *>(a.cov + q0);
 #pragma unroll
-        for (uint32_t i = 0; i < kRecChunks; i++) {
-            const uint32_t idx = i * 256 + threadIdx.x, row = idx / kRecChunks, c = idx % kRecChunks;
+        for (uint32_t i = 0; i < kCovChunks; i++) {
+            const uint32_t idx = i * 256 + threadIdx.x, row = idx / kCovChunks, c = idx % kCovChunks;
             if (row < rows)
-                dst[idx] = s_rec[row * kRecChunks + (c ^ (row & 7))];
+                dc[idx] = s_cov[row * kCovChunks + (c ^ (row & (kCovChunks - 1)))];
+        }
+        uint4 *dp = reinterpret_cast<uint4 *>(a.plane + q0);
+#pragma unroll
+        for (uint32_t i = 0; i < kPlaneChunks; i++) {
+            const uint32_t idx = i * 256 + threadIdx.x, row = idx / kPlaneChunks, c = idx % kPlaneChunks;
+            if (row < rows)
+                dp[idx] = s_pl[row * kPlaneChunks + (c ^ (row & (kPlaneChunks - 1)))];
         }
     }
     const uint32_t lane = lane_id();
@@ -1110,7 +1139,7 @@ constexpr uint32_t kRowPasses = 4;
 // quad stay in registers; the two more of a triangle pair (rare) are read
 // again from its record.  A wide quad (rarer) is done sample by sample by
 // its own lane.  Returns this lane's mask.
-__device__ __forceinline__ uint64_t batch_masks(const QuadRec &r, bool has, const QuadRec *__restrict__ rec,
+__device__ __forceinline__ uint64_t batch_masks(const CovRec &r, bool has, const ExtraRec *__restrict__ extra,
                                                 const QuadXY *__restrict__ xyp, uint32_t q, RowWork &W, int px0,
                                                 int py0, uint32_t lane)
 {
@@ -1159,12 +1188,12 @@ __device__ __forceinline__ uint64_t batch_masks(const QuadRec &r, bool has, cons
             }
             a6[4] = a6[5] = b6[4] = b6[5] = v6[4] = v6[5] = 0;
             if (!cvx) {
-                const int *hp = rec[q].hp;
+                const int *hp = extra[q].hp;
 #pragma unroll
                 for (int h = 4; h < 6; h++) {
-                    a6[h] = hp[3 * h];
-                    b6[h] = hp[3 * h + 1];
-                    v6[h] = a6[h] * di + b6[h] * dj - hp[3 * h + 2];
+                    a6[h] = hp[3 * h - 12];
+                    b6[h] = hp[3 * h - 11];
+                    v6[h] = a6[h] * di + b6[h] * dj - hp[3 * h - 10];
                 }
             }
             uint32_t lo = 0, hi = 0;
@@ -1206,11 +1235,11 @@ __device__ __forceinline__ uint64_t batch_masks(const QuadRec &r, bool has, cons
                 c4 = lane_int((int)cvx, c) != 0;
                 a[4] = a[5] = e[4] = e[5] = 0;
                 if (i < tot && !c4) {
-                    const int *hp = rec[qc].hp;
+                    const int *hp = extra[qc].hp;
 #pragma unroll
                     for (int h = 4; h < 6; h++) {
-                        a[h] = hp[3 * h];
-                        e[h] = a[h] * dic + hp[3 * h + 1] * djc - hp[3 * h + 2];
+                        a[h] = hp[3 * h - 12];
+                        e[h] = a[h] * dic + hp[3 * h - 11] * djc - hp[3 * h - 10];
                     }
                 }
             }
@@ -1227,8 +1256,8 @@ __device__ __forceinline__ uint64_t batch_masks(const QuadRec &r, bool has, cons
 }
 
 // Single-sample coverage (one lane, one quad), same rule.
-__device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *__restrict__ xyp, uint32_t q,
-                                               int px, int py)
+__device__ __forceinline__ bool pixel_coverage(const CovRec &r, const ExtraRec *__restrict__ extra,
+                                               const QuadXY *__restrict__ xyp, uint32_t q, int px, int py)
 {
     if (r.flags & kWide)
         return wide_covers(r.flags, xyp[q], px, py);
@@ -1244,16 +1273,17 @@ __device__ __forceinline__ bool pixel_coverage(const QuadRec &r, const QuadXY *_
     const bool t0 = (__mul24(hp[0], di) + __mul24(hp[1], dj) >= hp[2]) &&
                     (__mul24(hp[3], di) + __mul24(hp[4], dj) >= hp[5]) &&
                     (__mul24(hp[6], di) + __mul24(hp[7], dj) >= hp[8]);
+    const int *ex = extra[q].hp;
     const bool t1 = (__mul24(hp[9], di) + __mul24(hp[10], dj) >= hp[11]) &&
-                    (__mul24(hp[12], di) + __mul24(hp[13], dj) >= hp[14]) &&
-                    (__mul24(hp[15], di) + __mul24(hp[16], dj) >= hp[17]);
+                    (__mul24(ex[0], di) + __mul24(ex[1], dj) >= ex[2]) &&
+                    (__mul24(ex[3], di) + __mul24(ex[4], dj) >= ex[5]);
     return t0 || t1;
 }
 
 // Block key: the quad's depth at the centroid of its covered samples in the
 // block (Stage 3, phase 2), fp32; smaller code = nearer.  A heuristic only:
 // the per-pixel sorter and its exact fallback decide the final order.
-__device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t m, int px0, int py0)
+__device__ __forceinline__ uint32_t block_depth_code(const PlaneRec &r, uint64_t m, int px0, int py0)
 {
     const float cnt = (float)__popcll(m);
     const float sx = (float)(__popcll(m & 0xAAAAAAAAAAAAAAAAull) + 2 * __popcll(m & 0xCCCCCCCCCCCCCCCCull) +
@@ -1261,8 +1291,8 @@ __device__ __forceinline__ uint32_t block_depth_code(const QuadRec &r, uint64_t 
     const float sy = (float)(__popcll(m & 0xFF00FF00FF00FF00ull) + 2 * __popcll(m & 0xFFFF0000FFFF0000ull) +
                              4 * __popcll(m & 0xFFFFFFFF00000000ull));
     const float inv = 1.0f / cnt;
-    const float cx = (float)(px0 - (int)(r.bb_i & 0xffffu)) + sx * inv;
-    const float cy = (float)(py0 - (int)(r.bb_j & 0xffffu)) + sy * inv;
+    const float cx = (float)(px0 - (int)(r.ij & 0xffffu)) + sx * inv;
+    const float cy = (float)(py0 - (int)(r.ij >> 16)) + sy * inv;
     // the plane rounded to fp32
     float k = (float)r.A * cx + (float)r.B * cy + (float)r.C0;
     k = (k > 0.0f) ? k : 0.0f;  // NaN -> 0
@@ -1298,11 +1328,9 @@ __device__ void wave_bitonic_sort(KeyT *keys, uint32_t n, KeyT pad, uint32_t lan
     }
 }
 
-struct Stage {
-    double A, B, C0;
-    uint32_t ij;    // imin | jmin << 16
-    uint32_t rgba;
-};
+// An entry's plane, bbox origin and colour as the per-pixel walk reads them
+// (the quad's PlaneRec).
+using Stage = PlaneRec;
 
 // Entries one on-chip sort takes; longer block lists are cut into slices.
 constexpr uint32_t kSortCap = 1024;
@@ -1555,7 +1583,7 @@ struct PixelSorter {
 // 8x4 halves, and a pixel only sees the entries of its half.
 __device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32_t ebase, uint32_t sb,
                                           uint32_t slot, uint32_t code, uint64_t mask, uint32_t q,
-                                          const QuadRec &r, bool to_global)
+                                          const PlaneRec &pl, bool to_global)
 {
     if (to_global) {
         a.ent_code[ebase + slot] = code;
@@ -1564,42 +1592,37 @@ __device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32
     } else {  // slot < kFast
         L.k.f.code[slot] = code;
         L.k.f.mask[slot] = mask;
-        Stage st;
-        st.A = r.A;
-        st.B = r.B;
-        st.C0 = r.C0;
-        st.ij = (r.bb_i & 0xffffu) | (r.bb_j << 16);
-        st.rgba = r.rgba;
-        L.k.f.st[slot] = st;
+        L.k.f.st[slot] = pl;
         L.k.f.id[slot] = q;
     }
     if (slot < kSortCap)
         L.k.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
 }
 
-__device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *__restrict__ rec,
-                                             const QuadXY *__restrict__ xyp, WaveLds &L, uint32_t m,
-                                             const BlockGeom &g, uint32_t lane, uint32_t ebase, uint32_t sb,
-                                             bool half, uint32_t &n)
+__device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadXY *__restrict__ xyp, WaveLds &L,
+                                             uint32_t m, const BlockGeom &g, uint32_t lane, uint32_t ebase,
+                                             uint32_t sb, bool half, uint32_t &n)
 {
     uint64_t m0 = 0, m1 = 0;  // entries: m0 (whole block, or rows 0-3), m1 (rows 4-7)
     uint32_t q = 0, c0 = 0, c1 = 0;
-    // the candidate's whole record, loaded at once (one memory latency for
-    // the masks, the block keys and the entries)
-    QuadRec r;
+    // the candidate's coverage record and plane, loaded at once (one memory
+    // latency for the masks, the block keys and the entries)
+    CovRec r;
+    PlaneRec pl;
     const bool has = lane < m;
     if (has) {
         q = L.cand[lane];
-        r = rec[q];
+        r = a.cov[q];
+        pl = a.plane[q];
     }
-    const uint64_t mk = batch_masks(r, has, rec, xyp, q, L.s.rw, g.px0, g.py0, lane) & g.onmask;
+    const uint64_t mk = batch_masks(r, has, a.extra, xyp, q, L.s.rw, g.px0, g.py0, lane) & g.onmask;
     if (has) {
         m0 = half ? (mk & 0xFFFFFFFFull) : mk;
         m1 = half ? (mk & ~0xFFFFFFFFull) : 0;
         if (m0)
-            c0 = block_depth_code(r, m0, g.px0, g.py0);
+            c0 = block_depth_code(pl, m0, g.px0, g.py0);
         if (m1)
-            c1 = block_depth_code(r, m1, g.px0, g.py0);
+            c1 = block_depth_code(pl, m1, g.px0, g.py0);
     }
     const uint64_t b0 = ballot(m0 != 0);
     const uint64_t b1 = half ? ballot(m1 != 0) : 0;
@@ -1612,9 +1635,9 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
         a.ent_id[ebase + lane] = L.k.f.id[lane];
     }
     if (m0)
-        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, r, to_global);
+        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, pl, to_global);
     if (m1)
-        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, r, to_global);
+        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, pl, to_global);
     n += n0 + (uint32_t)__popcll(b1);
 }
 
@@ -1623,7 +1646,7 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadRec *
 // lane per pixel walks them in 64-entry segments whose coverage masks are
 // transposed to per-pixel bit sets, feeding each pixel's sorter.
 template <int K, bool DEBUG>
-__device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds &L, uint32_t n,
+__device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n,
                              uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
 {
     wave_sync();
@@ -1635,14 +1658,7 @@ __device__ void walk_entries(const FrameArgs &a, const QuadRec *__restrict__ rec
             const uint32_t slot = ebase + (L.k.key[e] & ((1u << sb) - 1));
             m = a.ent_mask[slot];
             const uint32_t q = a.ent_id[slot];
-            const QuadRec &r = rec[q];
-            Stage st;
-            st.A = r.A;
-            st.B = r.B;
-            st.C0 = r.C0;
-            st.ij = (r.bb_i & 0xffffu) | (r.bb_j << 16);
-            st.rgba = r.rgba;
-            L.s.w.st[lane] = st;
+            L.s.w.st[lane] = a.plane[q];
             if (DEBUG)
                 L.s.w.sid[lane] = q;
         }
@@ -1726,7 +1742,7 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
 // as one sort of the whole list.  Returns false when one bucket alone holds
 // more than kSortCap entries.
 template <int K, bool DEBUG>
-__device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec, WaveLds &L, uint32_t n,
+__device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n,
                             uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
 {
     // the key range of the block's entries
@@ -1789,20 +1805,71 @@ __device__ bool walk_sliced(const FrameArgs &a, const QuadRec *__restrict__ rec,
                 L.k.key[ns + rank_below(bm)] = (((code - lo) >> sh) << sb) | e;
             ns += (uint32_t)__popcll(bm);
         }
-        walk_entries<K, DEBUG>(a, rec, L, ns, ebase, sb, g, lane, ps);
+        walk_entries<K, DEBUG>(a, L, ns, ebase, sb, g, lane, ps);
         b0 = b1;
     }
     return true;
 }
 
+// Keeps, for the exact pass, the block's entries that cover one of its
+// flagged pixels F (the n entries sit in slot order on chip when n <=
+// kFast, else in the wave's global region): masks restricted to F, and quad
+// indices, contiguous at blk_ent[block].  When the frame's capacity for
+// them is used up, the block is marked and the exact pass walks its bin
+// list instead.
+__device__ void keep_flagged_entries(const FrameArgs &a, const WaveLds &L, const BlockGeom &g, uint64_t F,
+                                     uint32_t n, uint32_t ebase, uint32_t lane)
+{
+    const bool fast = n <= kFast;
+    uint32_t total = 0;
+    for (uint32_t e0 = 0; e0 < n; e0 += 64) {
+        const uint32_t e = e0 + lane;
+        uint64_t m = 0;
+        if (e < n)
+            m = (fast ? L.k.f.mask[e] : a.ent_mask[ebase + e]) & F;
+        total += (uint32_t)__popcll(ballot(m != 0));
+    }
+    uint32_t first = 0;
+    if (lane == 0)
+        first = atomicAdd(&a.ctr->fe_n, total);
+    first = lane_value(first, 0);
+    if ((uint64_t)first + total > a.fe_cap) {
+        if (lane == 0)
+            a.blk_ent[g.blk] = make_uint2(kNoEntries, 0u);
+        return;
+    }
+    uint32_t run = first;
+    for (uint32_t e0 = 0; e0 < n; e0 += 64) {
+        const uint32_t e = e0 + lane;
+        uint64_t m = 0;
+        uint32_t q = 0;
+        if (e < n) {
+            m = (fast ? L.k.f.mask[e] : a.ent_mask[ebase + e]) & F;
+            q = fast ? L.k.f.id[e] : a.ent_id[ebase + e];
+        }
+        const uint64_t b = ballot(m != 0);
+        if (m) {
+            a.fe_mask[run + rank_below(b)] = m;
+            a.fe_id[run + rank_below(b)] = q;
+        }
+        run += (uint32_t)__popcll(b);
+    }
+    if (lane == 0)
+        a.blk_ent[g.blk] = make_uint2(first, total);
+}
+
 // Outputs of a finished block: the pixel, flagged pixels to the exact
-// queue, and the wave's running statistics.
+// queue (with the block's entries kept for them), and the wave's running
+// statistics.
 template <int K, bool DEBUG>
-__device__ void finish_block(const FrameArgs &a, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps,
-                             uint32_t entries)
+__device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGeom &g, uint32_t lane,
+                             PixelSorter<K, DEBUG> &ps, uint32_t entries, uint32_t ebase)
 {
     if (g.on && !ps.flagged)
         ps.flush(a, g.on);
+    const uint64_t F = ballot(g.on && ps.flagged);
+    if (F)
+        keep_flagged_entries(a, L, g, F, entries, ebase, lane);
     push_flagged(a, g.on && ps.flagged, g, lane);
     const bool write = g.on && !ps.flagged;
     if (write) {
@@ -1838,7 +1905,6 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
     __shared__ WaveLds Lw[NW];
     uint32_t bin;
     const FrameArgs &a = *frame_of(src, bin);
-    const QuadRec *__restrict__ rec = a.rec;
     const QuadXY *__restrict__ xyp = a.xy;
     const uint2 *__restrict__ bbox = a.bbox;
     const uint32_t *__restrict__ pairs = a.pairs;
@@ -1864,7 +1930,7 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         uint32_t n = 0;
         scan_bin<NW>(bbox, pairs, C, L, start, cnt, cached, g, [&](uint32_t m) {
-            sorted_batch(a, rec, xyp, L, m, g, lane, ebase, sb, half, n);
+            sorted_batch(a, xyp, L, m, g, lane, ebase, sb, half, n);
         });
         if (g.active) {
             PixelSorter<K, DEBUG> ps;
@@ -1875,11 +1941,11 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
                 // entries written by other lanes of this wave are read back below
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 if (n <= kSortCap) {
-                    walk_entries<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps);
+                    walk_entries<K, DEBUG>(a, L, n, ebase, sb, g, lane, ps);
                 } else {
                     if (lane == 0)
                         atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
-                    if (!walk_sliced<K, DEBUG>(a, rec, L, n, ebase, sb, g, lane, ps)) {
+                    if (!walk_sliced<K, DEBUG>(a, L, n, ebase, sb, g, lane, ps)) {
                         // no slice fits: the exact path takes the block
                         ps.flagged = true;
                         if (lane == 0)
@@ -1887,16 +1953,21 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
                     }
                 }
             }
-            finish_block<K, DEBUG>(a, g, lane, ps, n);
+            finish_block<K, DEBUG>(a, L, g, lane, ps, n, ebase);
         }
     }
 }
 
 // --------------------------------------------------------- exact per pixel
 //
-// One wave per flagged pixel: every quad of the pixel's bin is tested on the
-// single sample, covering fragments are sorted by their full (code, index)
-// key in LDS and blended in order.  Pixels deeper than the LDS buffer are
+// One wave per flagged pixel: the candidates are the entries the raster
+// kept for the pixel's block (whose masks already say which quads cover the
+// pixel), or, when the frame ran out of room for them, every quad of the
+// pixel's bin tested on the single sample.  Covering fragments are sorted
+// by their full (code, index) key in LDS and blended in order with the
+// raster's blend routine, so the pixel comes out as an unbounded per-pixel
+// sorter would give it ("Sample blending": the slower exact algorithm for
+// the pixels the fixed-size sorter cannot order).  Pixels deeper than the LDS buffer are
 // done in rounds: each round keeps only keys above the last blended key and,
 // when the buffer fills, sorts it and keeps its lower half (raising an upper
 // cut), so a round blends the smallest keys left, at least half a buffer.
@@ -1909,18 +1980,19 @@ constexpr uint32_t kFallbackWaves = 4;
 constexpr uint32_t kFallbackGrid = 256;
 constexpr size_t kFallbackLds = (size_t)kFallbackWaves * (kFallbackBuf * 8 + 64 * 16);
 
-// The first 112 bytes of a quad record (everything but the fp32 plane) in
-// one go: seven 16-byte loads issued together, so the coverage test and the
-// key wait once per record instead of once per field it branches on.
-__device__ __forceinline__ QuadRec load_rec(const QuadRec *__restrict__ rec, uint32_t q)
+// A record in one go: its 16-byte chunks issued together, so the coverage
+// test and the key wait once per record instead of once per field they
+// branch on.
+template <typename R>
+__device__ __forceinline__ R load_whole(const R *__restrict__ p, uint32_t q)
 {
-    const uint4 *p = reinterpret_cast<const uint4 *>(rec + q);
-    uint4 d[7];
+    const uint4 *c = reinterpret_cast<const uint4 *>(p + q);
+    uint4 d[sizeof(R) / 16];
 #pragma unroll
-    for (int k = 0; k < 7; k++)
-        d[k] = p[k];
-    QuadRec r;
-    __builtin_memcpy(&r, d, sizeof(d));
+    for (uint32_t k = 0; k < sizeof(R) / 16; k++)
+        d[k] = c[k];
+    R r;
+    __builtin_memcpy(&r, d, sizeof(R));
     return r;
 }
 
@@ -1943,7 +2015,6 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
     float4 *s_col = reinterpret_cast<float4 *>(s_fb + (size_t)kFallbackWaves * kFallbackBuf) + wave * 64;
     for (uint32_t fi = 0; fi < frame_count(src); fi++) {
         const FrameArgs &a = frame_at(src, fi);
-        const QuadRec *__restrict__ rec = a.rec;
         const QuadXY *__restrict__ xyp = a.xy;
         const uint2 *__restrict__ bbox = a.bbox;
         const uint32_t *__restrict__ pairs = a.pairs;
@@ -1972,6 +2043,12 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
             const uint32_t bin = ((uint32_t)j >> a.bin_shift) * a.nbx + ((uint32_t)i >> a.bin_shift);
             const uint32_t start = uniform(a.bin_start[bin]);
             const uint32_t cnt = uniform(a.bin_count[bin]);
+            // candidates: the entries the raster kept for the pixel's block
+            // (those covering one of its flagged pixels), else the bin list
+            const uint2 ent = a.blk_ent[((uint32_t)j >> 3) * a.nblk_x + ((uint32_t)i >> 3)];
+            const bool kept = uniform(ent.x) != kNoEntries;
+            const uint32_t ncand = kept ? uniform(ent.y) : cnt;
+            const uint32_t bit = (((uint32_t)j & 7u) << 3) | ((uint32_t)i & 7u);
             const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
             float T = 1.0f, R = 0.0f, G2 = 0.0f, B = 0.0f;
             unsigned long long lo = 0;  // keys <= lo are blended already (real keys are > 0)
@@ -1982,7 +2059,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                 uint32_t n = 0, seen = 0;
                 // kFallbackStep chunks of 64 candidates per step: each stage's loads
                 // (list entries, then bboxes, then records) are issued together
-                for (uint32_t base = 0; base < cnt; base += 64 * kFallbackStep) {
+                for (uint32_t base = 0; base < ncand; base += 64 * kFallbackStep) {
                     if (n + 64 * kFallbackStep > kFallbackBuf) {
                         // keep the lower half of the buffer
                         wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
@@ -1993,27 +2070,40 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                     }
                     uint32_t q[kFallbackStep];
                     bool ov[kFallbackStep];
-    #pragma unroll
-                    for (uint32_t c = 0; c < kFallbackStep; c++) {
-                        const uint32_t l = base + 64 * c + lane;
-                        q[c] = l < cnt ? pairs[start + l] : 0xFFFFFFFFu;
+                    if (kept) {
+                        // the block's kept entries: coverage is the pixel's mask bit
+#pragma unroll
+                        for (uint32_t c = 0; c < kFallbackStep; c++) {
+                            const uint32_t l = base + 64 * c + lane;
+                            const bool in = l < ncand;
+                            const unsigned long long m = in ? a.fe_mask[ent.x + l] : 0ull;
+                            q[c] = in ? a.fe_id[ent.x + l] : 0u;
+                            ov[c] = (m >> bit) & 1ull;
+                        }
+                    } else {
+                        // the bin list: bbox, then exact coverage of the sample
+#pragma unroll
+                        for (uint32_t c = 0; c < kFallbackStep; c++) {
+                            const uint32_t l = base + 64 * c + lane;
+                            q[c] = l < ncand ? pairs[start + l] : 0xFFFFFFFFu;
+                        }
+#pragma unroll
+                        for (uint32_t c = 0; c < kFallbackStep; c++) {
+                            const uint2 bb = q[c] != 0xFFFFFFFFu ? bbox[q[c]] : make_uint2(0xffffu, 0u);
+                            ov[c] = (int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i &&
+                                    (int)(bb.y & 0xffffu) <= j && (int)(bb.y >> 16) >= j;
+                        }
                     }
-    #pragma unroll
-                    for (uint32_t c = 0; c < kFallbackStep; c++) {
-                        const uint2 bb = q[c] != 0xFFFFFFFFu ? bbox[q[c]] : make_uint2(0xffffu, 0u);
-                        ov[c] = (int)(bb.x & 0xffffu) <= i && (int)(bb.x >> 16) >= i && (int)(bb.y & 0xffffu) <= j &&
-                                (int)(bb.y >> 16) >= j;
-                    }
-    #pragma unroll
+#pragma unroll
                     for (uint32_t c = 0; c < kFallbackStep; c++) {
                         bool cov = false;
                         unsigned long long key = 0;
                         if (ov[c]) {
-                            const QuadRec r = load_rec(rec, q[c]);
-                            if (pixel_coverage(r, xyp, q[c], i, j)) {
+                            const PlaneRec pl = load_whole(a.plane, q[c]);
+                            if (kept || pixel_coverage(load_whole(a.cov, q[c]), a.extra, xyp, q[c], i, j)) {
                                 cov = true;
-                                const float kf = frag_key(r.A, r.B, r.C0, i - (int)(r.bb_i & 0xffffu),
-                                                          j - (int)(r.bb_j & 0xffffu));
+                                const float kf = frag_key(pl.A, pl.B, pl.C0, i - (int)(pl.ij & 0xffffu),
+                                                          j - (int)(pl.ij >> 16));
                                 key = ((unsigned long long)order_code(kf) << 32) | q[c];
                             }
                         }
@@ -2034,7 +2124,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                     uint32_t q = 0, c = 0;
                     if (e < n) {
                         q = (uint32_t)(s_key[e] & 0xffffffffu);
-                        c = rec[q].rgba;
+                        c = a.plane[q].rgba;
                         if (DEBUG && a.dbg_ids && obase + done + e < a.dbg_cap)
                             a.dbg_ids[obase + done + e] = q;
                     }
@@ -2085,7 +2175,6 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
     __shared__ UnsortedLds Uw[NW];
     uint32_t bin;
     const FrameArgs &a = *frame_of(src, bin);
-    const QuadRec *__restrict__ rec = a.rec;
     const QuadXY *__restrict__ xyp = a.xy;
     const uint2 *__restrict__ bbox = a.bbox;
     const uint32_t *__restrict__ pairs = a.pairs;
@@ -2108,14 +2197,14 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
         float R = 0.0f, G = 0.0f, B = 0.0f, Al = 0.0f;
         uint32_t nfrag = 0, ntot = 0;
         scan_bin<NW>(bbox, pairs, C, U, start, cnt, cached, g, [&](uint32_t m) {
-            QuadRec r;
+            CovRec r;
             uint32_t q = 0;
             const bool has = lane < m;
             if (has) {
                 q = U.cand[lane];
-                r = rec[q];
+                r = a.cov[q];
             }
-            const uint64_t mk = batch_masks(r, has, rec, xyp, q, U.rw, g.px0, g.py0, lane) & g.onmask;
+            const uint64_t mk = batch_masks(r, has, a.extra, xyp, q, U.rw, g.px0, g.py0, lane) & g.onmask;
             if (has)
                 U.col[lane] = r.rgba;
             ntot += (uint32_t)__popcll(ballot(mk != 0));

@@ -200,8 +200,9 @@ uint32_t log2u(uint32_t x)
 struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks;
-    uint64_t o_rec, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
-        total;
+    uint64_t o_cov, o_plane, o_extra, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
+        o_femask, o_feid, o_blkent, total;
+    uint32_t fe_cap;
 };
 
 Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, uint32_t pair_hint)
@@ -244,7 +245,9 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     // two counter sets first, at the same place for every plan: a single frame
     // uses one and zeroes the other for the next frame
     p.o_ctr = take(2 * sizeof(lr::FrameCounters));
-    p.o_rec = take((uint64_t)n * sizeof(lr::QuadRec));
+    p.o_cov = take((uint64_t)n * sizeof(lr::CovRec));
+    p.o_plane = take((uint64_t)n * sizeof(lr::PlaneRec));
+    p.o_extra = take((uint64_t)n * sizeof(lr::ExtraRec));
     p.o_xy = take((uint64_t)n * sizeof(lr::QuadXY));
     p.o_bbox = take((uint64_t)n * 8);
     p.o_cull = take((uint64_t)n);
@@ -260,6 +263,11 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_ecode = take(ents * 4);
     p.o_emask = take(ents * 8);
     p.o_eid = take(ents * 4);
+    // entries kept for the exact pass (blocks past this capacity walk their bin list)
+    p.fe_cap = std::max<uint32_t>(p.pair_cap, 65536u);
+    p.o_femask = take((uint64_t)p.fe_cap * 8);
+    p.o_feid = take((uint64_t)p.fe_cap * 4);
+    p.o_blkent = take((uint64_t)p.nblk_x * p.nblk_y * 8);
     p.total = o;
     return p;
 }
@@ -341,14 +349,15 @@ lr_status check_frame(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     return LR_OK;
 }
 
-// Frame arguments for a planned frame whose workspace starts at base.
-void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t *out, const Plan &plan,
-               char *base, lr::FrameArgs &a)
+// Frame arguments for a planned frame of the n quads at scene (SoA: 12
+// vertex planes, then the colours) whose workspace starts at base.
+void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *out, const Plan &plan, char *base,
+                lr::ErrLog *elog, lr::FrameArgs &a)
 {
     std::memset(&a, 0, sizeof(a));
-    a.v = reinterpret_cast<const float *>(ctx->arena + sc.off);
-    a.rgba_in = reinterpret_cast<const uint32_t *>(ctx->arena + sc.off + 48ull * sc.n);
-    a.n = sc.n;
+    a.v = reinterpret_cast<const float *>(scene);
+    a.rgba_in = reinterpret_cast<const uint32_t *>(scene + 48ull * n);
+    a.n = n;
     for (int k = 0; k < 3; k++)
         a.pos[k] = cam->pos[k];
     for (int r = 0; r < 3; r++)
@@ -361,7 +370,9 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
     a.cy = 0.5 * (double)plan.H;
     a.W = plan.W;
     a.H = plan.H;
-    a.rec = reinterpret_cast<lr::QuadRec *>(base + plan.o_rec);
+    a.cov = reinterpret_cast<lr::CovRec *>(base + plan.o_cov);
+    a.plane = reinterpret_cast<lr::PlaneRec *>(base + plan.o_plane);
+    a.extra = reinterpret_cast<lr::ExtraRec *>(base + plan.o_extra);
     a.xy = reinterpret_cast<lr::QuadXY *>(base + plan.o_xy);
     a.bbox = reinterpret_cast<uint2 *>(base + plan.o_bbox);
     a.cull = reinterpret_cast<uint8_t *>(base + plan.o_cull);
@@ -386,9 +397,20 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
     a.ent_code = reinterpret_cast<uint32_t *>(base + plan.o_ecode);
     a.ent_mask = reinterpret_cast<unsigned long long *>(base + plan.o_emask);
     a.ent_id = reinterpret_cast<uint32_t *>(base + plan.o_eid);
+    a.fe_mask = reinterpret_cast<unsigned long long *>(base + plan.o_femask);
+    a.fe_id = reinterpret_cast<uint32_t *>(base + plan.o_feid);
+    a.fe_cap = plan.fe_cap;
+    a.blk_ent = reinterpret_cast<uint2 *>(base + plan.o_blkent);
     a.ctr = reinterpret_cast<lr::FrameCounters *>(base + plan.o_ctr);
-    a.elog = ctx->elog;
+    a.elog = elog;
     a.out = out;
+}
+
+// The same for a resident scene of the context.
+void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t *out, const Plan &plan,
+               char *base, lr::FrameArgs &a)
+{
+    fill_frame(ctx->arena + sc.off, sc.n, cam, out, plan, base, ctx->elog, a);
 }
 
 // Tags a frame for the error log.
@@ -1134,10 +1156,12 @@ lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, u
     // the next frame expects its counter set zeroed
     LR_HIP(ctx, hipMemset(a.ctr, 0, sizeof(lr::FrameCounters)));
     const uint32_t n = a.n;
-    std::vector<lr::QuadRec> rec(n);
+    std::vector<lr::CovRec> cov(n);
+    std::vector<lr::PlaneRec> pl(n);
     std::vector<lr::QuadXY> xy(n);
     std::vector<uint8_t> cl(n);
-    LR_HIP(ctx, hipMemcpy(rec.data(), a.rec, (size_t)n * sizeof(lr::QuadRec), hipMemcpyDeviceToHost));
+    LR_HIP(ctx, hipMemcpy(cov.data(), a.cov, (size_t)n * sizeof(lr::CovRec), hipMemcpyDeviceToHost));
+    LR_HIP(ctx, hipMemcpy(pl.data(), a.plane, (size_t)n * sizeof(lr::PlaneRec), hipMemcpyDeviceToHost));
     LR_HIP(ctx, hipMemcpy(xy.data(), a.xy, (size_t)n * sizeof(lr::QuadXY), hipMemcpyDeviceToHost));
     LR_HIP(ctx, hipMemcpy(cl.data(), a.cull, n, hipMemcpyDeviceToHost));
     for (uint32_t i = 0; i < n; i++) {
@@ -1151,15 +1175,15 @@ lr_status lr_debug_setup(lr_context ctx, lr_scene scene, const lr_camera *cam, u
                 Y[4 * (size_t)i + k] = snapped ? xy[i].Y[k] : 0;
         }
         if (bbox) {
-            bbox[4 * (size_t)i + 0] = vis ? (int32_t)(rec[i].bb_i & 0xffff) : 1;
-            bbox[4 * (size_t)i + 1] = vis ? (int32_t)(rec[i].bb_i >> 16) : 0;
-            bbox[4 * (size_t)i + 2] = vis ? (int32_t)(rec[i].bb_j & 0xffff) : 1;
-            bbox[4 * (size_t)i + 3] = vis ? (int32_t)(rec[i].bb_j >> 16) : 0;
+            bbox[4 * (size_t)i + 0] = vis ? (int32_t)(cov[i].bb_i & 0xffff) : 1;
+            bbox[4 * (size_t)i + 1] = vis ? (int32_t)(cov[i].bb_i >> 16) : 0;
+            bbox[4 * (size_t)i + 2] = vis ? (int32_t)(cov[i].bb_j & 0xffff) : 1;
+            bbox[4 * (size_t)i + 3] = vis ? (int32_t)(cov[i].bb_j >> 16) : 0;
         }
         if (plane) {
-            plane[3 * (size_t)i + 0] = vis ? rec[i].A : 0.0;
-            plane[3 * (size_t)i + 1] = vis ? rec[i].B : 0.0;
-            plane[3 * (size_t)i + 2] = vis ? rec[i].C0 : 0.0;
+            plane[3 * (size_t)i + 0] = vis ? pl[i].A : 0.0;
+            plane[3 * (size_t)i + 1] = vis ? pl[i].B : 0.0;
+            plane[3 * (size_t)i + 2] = vis ? pl[i].C0 : 0.0;
         }
         if (cull)
             cull[i] = cl[i];
