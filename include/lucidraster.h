@@ -200,6 +200,25 @@ lr_status lr_release_scene(lr_context ctx, lr_scene scene);
 lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
                     uint32_t height, uint8_t *out_rgba8, void *stream);
 
+/* For callers that cannot allocate device memory during a render: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The same render as lr_render, bit-identical for the same tuning, but its
+ * frame workspace (quad records, bin lists, block entries, counters, the
+ * flagged-pixel queue) lives in a fixed array of 128 MiB that each device
+ * loading the library holds until the process ends; the call allocates
+ * nothing (no hipMalloc, hipFree or arena sub-allocation).  The scene must
+ * already be resident (lr_upload_scene) and out_rgba8 is the caller's.
+ * Returns LR_ERR_OUT_OF_MEMORY, without launching anything, when the frame's
+ * workspace would exceed 128 MiB (a 1280x720 frame of 200k quads at bin 32
+ * fits; lr_request_bytes gives the figure).  Every call on one device, from any
+ * context, shares that array and leaves its contents behind: calls that
+ * overlap on one device race.  Calls of one context are ordered after each
+ * other even on different streams; calls of different contexts on one
+ * device must be ordered by the caller.  Capacity overflows are reported as
+ * for lr_render (the next lr_sync), after which a second call succeeds. */
+lr_status lr_render_noalloc(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                            uint32_t height, uint8_t *out_rgba8, void *stream);
+
 /* Same render (Section 2), plus parity artefacts (each may be NULL):
  *   rgba_f32  [H][W][4] fp32 premultiplied colour before rounding;
  *   counts    [H][W] fragments per pixel;

@@ -98,7 +98,7 @@ struct BatchSlot {
 
 // A frame of the last render call (for statistics).
 struct FrameRef {
-    uint64_t ctr_off;
+    const char *ctr;  // device address of its counter set
     uint64_t quads;
     int slot;  // batch slot holding its counters, -1: the context workspace
 };
@@ -120,6 +120,37 @@ using HintKey = std::tuple<lr_scene, uint32_t, uint32_t, uint32_t>;  // scene, W
 
 // Pinned frame-table buffers in flight at once (host side of the batch table).
 constexpr uint32_t kTabRing = 8;
+
+// Frame workspace of lr_render_noalloc: a fixed device array, so that call
+// allocates nothing.  Each device that loads the library holds its own copy
+// until the process ends.  In host code `scratch` names a host-side stand-in;
+// the device address comes from hipGetSymbolAddress (scratch_address).
+constexpr uint64_t kScratchBytes = 128ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (it is current in lr_create).
+hipError_t scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -164,6 +195,12 @@ struct lr_context_s {
     std::string err;
     std::mutex mu;
     lr::FrameCounters *host_ctr = nullptr;  // pinned
+    // lr_render_noalloc: this device's `scratch` and an event after the last
+    // call of this context that used it
+    char *scratch = nullptr;
+    hipEvent_t scratch_free = nullptr;
+    hipStream_t scratch_stream = nullptr;
+    bool scratch_used = false;
 };
 
 namespace {
@@ -527,8 +564,8 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
     LR_HIP(ctx, hipEventRecord(ctx->ws_free, s));
     ctx->last_stream = s;
     ctx->have_frame = true;
-    ctx->last_frames.assign(1, FrameRef{ctx->ws.off + plan.o_ctr + ctx->ws_set * sizeof(lr::FrameCounters),
-                                        a.n, -1});
+    ctx->last_frames.clear();
+    ctx->last_frames.push_back(FrameRef{reinterpret_cast<const char *>(a.ctr), a.n, -1});
     ctx->ws_set ^= 1u;
     std::memset(&ctx->acc, 0, sizeof(ctx->acc));
     return LR_OK;
@@ -546,7 +583,7 @@ void stage_times(lr_context ctx, uint32_t slot, float *us)
 // Adds one frame's counters to *sum.
 lr_status add_frame_stats(lr_context ctx, const FrameRef &fr, lr_stats *sum)
 {
-    LR_HIP(ctx, hipMemcpy(ctx->host_ctr, ctx->arena + fr.ctr_off, sizeof(lr::FrameCounters),
+    LR_HIP(ctx, hipMemcpy(ctx->host_ctr, fr.ctr, sizeof(lr::FrameCounters),
                           hipMemcpyDeviceToHost));
     const lr::FrameCounters &c = *ctx->host_ctr;
     unsigned long long v[lr::ST_COUNT] = {};
@@ -782,7 +819,7 @@ lr_status batch_impl(lr_context ctx, const lr_request *reqs, uint32_t n, hipStre
             host[f].status = r.status;
             tag_frame(ctx, r.scene, pl, host[f]);
             ks[f] = (int)tunes[i0 + f].k;
-            frames.push_back(FrameRef{slot->off + o + pl.o_ctr, pl.n, (int)(slot - ctx->slots.data())});
+            frames.push_back(FrameRef{base + o + pl.o_ctr, pl.n, (int)(slot - ctx->slots.data())});
             o += (pl.total + 255) & ~uint64_t(255);
         }
         LR_HIP(ctx, hipMemcpyAsync(dev, host, nf * sizeof(lr::FrameArgs), hipMemcpyHostToDevice, s));
@@ -797,7 +834,9 @@ lr_status batch_impl(lr_context ctx, const lr_request *reqs, uint32_t n, hipStre
         slot->stamp = ++ctx->slot_stamp;
         i0 = i1;
     }
-    ctx->last_frames = std::move(frames);
+    // copied, not moved: the vector keeps its capacity (reserved at creation),
+    // so a later single-frame call adds no host allocation
+    ctx->last_frames.assign(frames.begin(), frames.end());
     ctx->have_frame = n > 0;
     return LR_OK;
 }
@@ -880,6 +919,7 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
     for (uint32_t i = 0; i < kTabRing; i++)
         ok = ok && hipEventCreateWithFlags(&ctx->tab_ev[i], hipEventDisableTiming) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ctx->scratch_free, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipHostMalloc((void **)&ctx->host_tab, sizeof(lr::FrameArgs) * lr::kMaxBatch * kTabRing,
                              hipHostMallocDefault) == hipSuccess;
     if (ctx->timing) {
@@ -895,6 +935,16 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
         return fail(nullptr, LR_ERR_DEVICE, "HIP event or pinned allocation failed");
     }
     ctx->tag_keys.assign(kTagRing, HintKey(0, 0, 0, 0));
+    ctx->last_frames.reserve(lr::kMaxBatch);
+    {
+        void *p = nullptr;
+        e = scratch_address(c.device, &p);
+        if (e != hipSuccess) {
+            lr_destroy(ctx);
+            return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
+        }
+        ctx->scratch = static_cast<char *>(p);
+    }
     if (!ctx->alloc.alloc(sizeof(lr::ErrLog), ctx->elog_off)) {
         lr_destroy(ctx);
         return fail(nullptr, LR_ERR_OUT_OF_MEMORY, "arena too small");
@@ -928,6 +978,8 @@ lr_status lr_destroy(lr_context ctx)
         (void)hipHostFree(ctx->host_tab);
     if (ctx->ws_free)
         (void)hipEventDestroy(ctx->ws_free);
+    if (ctx->scratch_free)
+        (void)hipEventDestroy(ctx->scratch_free);
     for (auto &e : ctx->ring)
         if (e)
             (void)hipEventDestroy(e);
@@ -1007,6 +1059,57 @@ lr_status lr_render(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32
     if (!lock.owns_lock())
         return fail(ctx, LR_ERR_BUSY, "context in use by another thread");
     return render_impl(ctx, scene, cam, width, height, out_rgba8, stream, 0, nullptr, frame_tune(ctx, scene, width, height));
+}
+
+lr_status lr_render_noalloc(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,
+                            uint32_t height, uint8_t *out_rgba8, void *stream)
+{
+    if (!ctx)
+        return fail(nullptr, LR_ERR_INVALID_ARG, "context is NULL");
+    std::unique_lock<std::mutex> lock(ctx->mu, std::try_to_lock);
+    if (!lock.owns_lock())
+        return fail(ctx, LR_ERR_BUSY, "context in use by another thread");
+    if (!out_rgba8)
+        return fail(ctx, LR_ERR_INVALID_ARG, "output pointer is NULL");
+    if (!ctx->scratch)
+        return fail(ctx, LR_ERR_DEVICE, "the static scratch of this device was not found");
+    const Tune t = frame_tune(ctx, scene, width, height);
+    Plan plan;
+    lr_status st = check_frame(ctx, scene, cam, width, height, t, plan);
+    if (st != LR_OK)
+        return st;
+    if (plan.total > kScratchBytes)
+        return fail(ctx, LR_ERR_OUT_OF_MEMORY,
+                    "frame workspace of " + std::to_string(plan.total) +
+                        " bytes exceeds the static scratch of lr_render_noalloc (" +
+                        std::to_string(kScratchBytes) + " bytes); use lr_render");
+    lr::FrameArgs a;
+    fill_args(ctx, ctx->scenes.find(scene)->second, cam, out_rgba8, plan, ctx->scratch, a);
+    // no counter set is zeroed ahead: the frame's first kernel clears its own
+    a.ctr = reinterpret_cast<lr::FrameCounters *>(ctx->scratch + plan.o_ctr);
+    a.ctr_next = nullptr;
+    tag_frame(ctx, scene, plan, a);
+    hipStream_t s = pick_stream(ctx, stream);
+    // this context's previous call on another stream may still use scratch
+    if (ctx->scratch_used && ctx->scratch_stream != s)
+        LR_HIP(ctx, hipStreamWaitEvent(s, ctx->scratch_free, 0));
+    hipEvent_t *ev = nullptr;
+    if (ctx->timing) {
+        ev = &ctx->ring[(size_t)ctx->ring_head * 8];
+        ctx->ring_head = (ctx->ring_head + 1) % kRing;
+        ctx->ring_count = std::min(ctx->ring_count + 1, kRing);
+    }
+    hipError_t e = lr::launch_frame(a, (int)t.k, 0, s, ev);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "kernel launch");
+    LR_HIP(ctx, hipEventRecord(ctx->scratch_free, s));
+    ctx->scratch_stream = s;
+    ctx->scratch_used = true;
+    ctx->have_frame = true;
+    ctx->last_frames.clear();
+    ctx->last_frames.push_back(FrameRef{reinterpret_cast<const char *>(a.ctr), a.n, -1});
+    std::memset(&ctx->acc, 0, sizeof(ctx->acc));
+    return LR_OK;
 }
 
 lr_status lr_render_debug(lr_context ctx, lr_scene scene, const lr_camera *cam, uint32_t width,

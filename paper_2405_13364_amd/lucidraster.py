@@ -77,7 +77,7 @@ class TuneRule(ctypes.Structure):
 
 
 EXPORTS = ["lr_status_string", "lr_last_error", "lr_create", "lr_destroy", "lr_upload_scene",
-           "lr_release_scene", "lr_render", "lr_render_debug", "lr_render_unsorted",
+           "lr_release_scene", "lr_render", "lr_render_noalloc", "lr_render_debug", "lr_render_unsorted",
            "lr_render_batch", "lr_set_tuning", "lr_request_bytes", "lr_sync", "lr_get_stats",
            "lr_get_stage_times", "lr_debug_setup", "lr_debug_bins"]
 
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "lr_upload_scene": [CTX, P, U32, ctypes.c_int, ctypes.POINTER(U64)],
         "lr_release_scene": [CTX, U64],
         "lr_render": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P],
+        "lr_render_noalloc": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P],
         "lr_render_debug": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P, P, P, P, P, P, U32],
         "lr_render_unsorted": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P, P],
         "lr_render_batch": [CTX, ctypes.POINTER(Request), U32, P],
@@ -226,6 +227,24 @@ class Context:
         for attempt in range(2):
             self._check(self.lib.lr_render(self.h, scene, ctypes.byref(c), W, H, out.data_ptr(),
                                            self._stream(stream)), self.h)
+            if not check:
+                return out
+            st = self.lib.lr_sync(self.h)
+            if st == LR_ERR_CAPACITY and attempt == 0:
+                continue
+            self._check(st, self.h)
+            return out
+        return out
+
+    def render_noalloc(self, scene: int, cam, W: int, H: int, out=None, stream=None, check: bool = True):
+        """Sorted render whose frame workspace is the library's fixed device
+        array (lr_render_noalloc: the call allocates nothing).  With check,
+        waits and renders once more if a capacity was exceeded."""
+        out = self.new_image(W, H) if out is None else out
+        c = camera_struct(cam)
+        for attempt in range(2):
+            self._check(self.lib.lr_render_noalloc(self.h, scene, ctypes.byref(c), W, H, out.data_ptr(),
+                                                   self._stream(stream)), self.h)
             if not check:
                 return out
             st = self.lib.lr_sync(self.h)

@@ -83,6 +83,7 @@ def test_argument_errors_need_no_device(lib):
         assert lib.lr_last_error(None)
     cam = lr.Camera()
     assert lib.lr_render(None, 1, ctypes.byref(cam), 8, 8, None, None) == lr.LR_ERR_INVALID_ARG
+    assert lib.lr_render_noalloc(None, 1, ctypes.byref(cam), 8, 8, None, None) == lr.LR_ERR_INVALID_ARG
     assert lib.lr_sync(None) == lr.LR_ERR_INVALID_ARG
     assert lib.lr_destroy(None) == lr.LR_ERR_INVALID_ARG
     assert lib.lr_upload_scene(None, None, 0, 0, None) == lr.LR_ERR_INVALID_ARG
