@@ -42,9 +42,10 @@ def tunings(depths=DEPTHS):
 
 
 def sample_frames(W: int, H: int, qpp: float, seed: int):
-    """One frame per base workload shape at this size and density."""
+    """One frame per base workload shape at this size and density (at most
+    1M quads, the largest single-frame workload)."""
     from . import scenes
-    n = int(min(500_000, max(1_000, round(qpp * W * H))))
+    n = int(min(1_000_000, max(1_000, round(qpp * W * H))))
     out = []
     for k, base in enumerate(("c1", "c2", "c3")):
         b = scenes.RECIPES[base]
