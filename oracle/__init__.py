@@ -150,14 +150,23 @@ def default_threads() -> int:
     return max(1, min(n, 16))
 
 
+def _mode(unsorted: bool, cutoff: bool) -> int:
+    if unsorted and cutoff:
+        raise ValueError("the transmittance cutoff applies to the sorted blend only")
+    return 1 if unsorted else (2 if cutoff else 0)
+
+
 def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bool = False,
            want_order: bool = True, st: Optional[Setup] = None,
-           threads: Optional[int] = None) -> Dict[str, np.ndarray]:
+           threads: Optional[int] = None, cutoff: bool = False) -> Dict[str, np.ndarray]:
     """Whole-frame reference render.  Returns rgba_f64 [H,W,4], rgba8 [H,W,4],
     count [H,W], order_offsets [W*H+1], order_ids [total], setup, and the
     number of worker threads used (row bands; the result does not depend on
-    it)."""
+    it).  With cutoff, each pixel stops after the fragment that brings its
+    single-precision transmittance below 2^-20: count, order and total are
+    those of the blended prefixes ("covering" keeps the full total)."""
     lib = _load()
+    mode = _mode(unsorted, cutoff)
     st = st or setup(v, camera, W, H)
     threads = default_threads() if threads is None else max(1, int(threads))
     rgba = np.ascontiguousarray(rgba, np.uint32)
@@ -175,26 +184,39 @@ def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bo
         ids = np.zeros(max(int(total), 1), np.uint32)
         if n:
             total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
-                                   _p(st.cull), _p(rgba), W, H, int(unsorted), _p(out_f), _p(out_8),
+                                   _p(st.cull), _p(rgba), W, H, mode, _p(out_f), _p(out_8),
                                    _p(cnt), _p(off), _p(ids), threads)
+        if total < 0:
+            raise MemoryError("oracle render failed")
+        ids = ids[:int(total)]
+        if mode == 2:
+            # keep each pixel's blended prefix of its full list
+            full = np.diff(off).astype(np.int64)
+            pos = np.arange(int(total), dtype=np.int64) - np.repeat(off[:-1].astype(np.int64), full)
+            ids = ids[pos < np.repeat(cnt.reshape(-1).astype(np.int64), full)]
+            off = np.zeros(npix + 1, np.uint64)
+            off[1:] = np.cumsum(cnt.reshape(-1), dtype=np.uint64)
         res["order_offsets"] = off
-        res["order_ids"] = ids[:max(int(total), 0)]
+        res["order_ids"] = ids
     else:
         total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
-                               _p(st.cull), _p(rgba), W, H, int(unsorted), _p(out_f), _p(out_8),
+                               _p(st.cull), _p(rgba), W, H, mode, _p(out_f), _p(out_8),
                                _p(cnt), None, None, threads) if n else 0
     if total < 0:
         raise MemoryError("oracle render failed")
-    res["total"] = int(total)
+    res["covering"] = int(total)
+    res["total"] = int(cnt.sum(dtype=np.uint64)) if mode == 2 else int(total)
     return res
 
 
 def pixels(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, pix: np.ndarray,
            unsorted: bool = False, want_ids: bool = True,
-           st: Optional[Setup] = None) -> Dict[str, np.ndarray]:
+           st: Optional[Setup] = None, cutoff: bool = False) -> Dict[str, np.ndarray]:
     """Reference result for selected pixels (pix = j*W + i), each computed by
-    testing every quad.  Returns rgba_f64 [k,4], count [k], offsets, ids."""
+    testing every quad.  Returns rgba_f64 [k,4], count [k], offsets, ids
+    (with cutoff: those of the blended prefixes)."""
     lib = _load()
+    mode = _mode(unsorted, cutoff)
     st = st or setup(v, camera, W, H)
     rgba = np.ascontiguousarray(rgba, np.uint32)
     pix = np.ascontiguousarray(pix, np.uint32)
@@ -206,7 +228,7 @@ def pixels(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, pix: np.ndar
     while True:
         ids = np.zeros(cap, np.uint32)
         total = lib.lro_pixels(st.n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B),
-                               _p(st.C0), _p(st.cull), _p(rgba), W, int(unsorted), k, _p(pix),
+                               _p(st.C0), _p(st.cull), _p(rgba), W, mode, k, _p(pix),
                                _p(out_f), _p(cnt), _p(off) if want_ids else None,
                                _p(ids) if want_ids else None, cap)
         if total >= 0:

@@ -45,6 +45,16 @@
  *            T *= 1 - a; output premultiplied (C, 1 - T); RGBA8 is
  *            clamp(floor(255 x + 0.5)).
  *   unsorted quad index order, "over": C = a c + (1-a) C, al = a + (1-a) al.
+ *   cutoff   (optional; Stage 3 "Sample blending" stops a pixel once its
+ *            accumulated alpha passes a threshold) a pixel stops after the
+ *            first fragment that brings its transmittance below 2^-20; the
+ *            colour is still blended in binary64, but that decision is an
+ *            integer one (how many fragments) and is taken in single
+ *            precision as a shader would: a32 = fl(fl(A8) * fl(1/255)),
+ *            T32 = fl(T32 * fl(1 - a32)) from T32 = 1, every fl() binary32
+ *            round to nearest even.  Everything after the stop is left
+ *            out, so the colour differs from the uncut one by less than
+ *            2^-20 per channel.
  */
 #include <math.h>
 #include <pthread.h>
@@ -279,6 +289,34 @@ static void blend_front_to_back(const frag_t *fr, uint32_t cnt, double out[4])
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
 }
 
+/* Transmittance below which a pixel stops, with the cutoff on. */
+#define LRO_CUT_T (1.0f / 1048576.0f)
+
+/* The same blend with the transmittance cutoff; returns how many fragments
+ * (a prefix of fr) were blended. */
+static uint32_t blend_front_to_back_cut(const frag_t *fr, uint32_t cnt, double out[4])
+{
+    double T = 1.0, C[3] = {0.0, 0.0, 0.0};
+    float T32 = 1.0f;
+    const float inv255 = 1.0f / 255.0f;
+    uint32_t k = 0;
+    while (k < cnt) {
+        uint32_t c = fr[k].rgba;
+        double a = (double)(c >> 24) / 255.0;
+        double w = T * a;
+        for (int ch = 0; ch < 3; ch++)
+            C[ch] = C[ch] + w * ((double)((c >> (8 * ch)) & 255u) / 255.0);
+        T = T * (1.0 - a);
+        float a32 = (float)(c >> 24) * inv255;
+        T32 = T32 * (1.0f - a32);
+        k++;
+        if (T32 < LRO_CUT_T)
+            break;
+    }
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
+    return k;
+}
+
 /* "Over" blend in quad index order (the unsorted baseline). */
 static void blend_over(const frag_t *fr, uint32_t cnt, double out[4])
 {
@@ -303,7 +341,7 @@ static uint8_t to_u8(double x)
 
 /*
  * Whole-frame render.  Per pixel it gathers every covering visible quad,
- * orders the fragments (sorted, or quad index order when unsorted != 0) and
+ * orders the fragments (sorted, or quad index order in the unsorted mode) and
  * blends them.  Outputs: rgba_f64[H][W][4], rgba8[H][W][4], count[H][W],
  * order_offsets[W*H+1] and order_ids[...] (fragment quad indices in blend
  * order; pass NULL to skip).  Returns the total number of fragments, or -1 on
@@ -324,7 +362,7 @@ typedef struct {
     const double *A, *B, *C0;
     const uint8_t *cull;
     const uint32_t *rgba;
-    int unsorted;
+    int mode;               /* 0 sorted, 1 unsorted (quad order), 2 sorted with the cutoff */
     /* outputs and work arrays */
     double *rgba_f64;
     uint8_t *rgba8;
@@ -380,11 +418,14 @@ static void band_blend(lro_job *jb, int32_t j0, int32_t j1)
         frag_t *pf = jb->fr + jb->off[p];
         uint32_t cnt = jb->count[p];
         double o[4];
-        if (jb->unsorted) {
+        if (jb->mode == 1) {
             blend_over(pf, cnt, o);
         } else {
             qsort(pf, cnt, sizeof(frag_t), cmp_frag);
-            blend_front_to_back(pf, cnt, o);
+            if (jb->mode == 2)
+                jb->count[p] = cnt = blend_front_to_back_cut(pf, cnt, o);  /* the blended prefix */
+            else
+                blend_front_to_back(pf, cnt, o);
         }
         for (int ch = 0; ch < 4; ch++) {
             if (jb->rgba_f64) jb->rgba_f64[4 * p + ch] = o[ch];
@@ -439,13 +480,13 @@ static uint32_t pick_threads(uint32_t threads)
 
 static void job_init(lro_job *jb, uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
                      const double *A, const double *B, const double *C0, const uint8_t *cull,
-                     const uint32_t *rgba, uint32_t W, uint32_t H, int unsorted, uint32_t *count)
+                     const uint32_t *rgba, uint32_t W, uint32_t H, int mode, uint32_t *count)
 {
     memset(jb, 0, sizeof(*jb));
     jb->n = n; jb->W = W; jb->H = H;
     jb->X = X; jb->Y = Y; jb->bbox = bbox;
     jb->A = A; jb->B = B; jb->C0 = C0;
-    jb->cull = cull; jb->rgba = rgba; jb->unsorted = unsorted;
+    jb->cull = cull; jb->rgba = rgba; jb->mode = mode;
     jb->count = count;
     jb->nbands = (H + LRO_BAND_ROWS - 1) / LRO_BAND_ROWS;
     pthread_mutex_init(&jb->mu, NULL);
@@ -466,16 +507,20 @@ int64_t lro_count(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t 
     return (int64_t)total;
 }
 
+/* mode: 0 sorted, 1 unsorted, 2 sorted with the transmittance cutoff (then
+ * count[] holds the blended prefix of each pixel, order_offsets the bounds of
+ * the full lists and order_ids their prefixes first; the return value stays
+ * the number of covering fragments). */
 int64_t lro_render(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
                    const double *A, const double *B, const double *C0, const uint8_t *cull,
-                   const uint32_t *rgba, uint32_t W, uint32_t H, int unsorted, double *rgba_f64,
+                   const uint32_t *rgba, uint32_t W, uint32_t H, int mode, double *rgba_f64,
                    uint8_t *rgba8, uint32_t *count, uint64_t *order_offsets, uint32_t *order_ids,
                    uint32_t threads)
 {
     const size_t npix = (size_t)W * H;
     threads = pick_threads(threads);
     lro_job jb;
-    job_init(&jb, n, X, Y, bbox, A, B, C0, cull, rgba, W, H, unsorted, count);
+    job_init(&jb, n, X, Y, bbox, A, B, C0, cull, rgba, W, H, mode, count);
     uint64_t *off = (uint64_t *)calloc(npix + 1, sizeof(uint64_t));
     if (!off) {
         pthread_mutex_destroy(&jb.mu);
@@ -518,11 +563,12 @@ int64_t lro_render(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
  * pix[k] = j * W + i.  Outputs per pixel: rgba_f64[k][4], count[k] and, when
  * ids != NULL, offsets[npix+1] / ids[<= ids_cap] in blend order.  Returns
  * the number of fragments over all listed pixels, or -1 when ids_cap is too
- * small or memory runs out.
+ * small or memory runs out.  mode as for lro_render; with the cutoff, counts
+ * and ids are those of the blended prefixes.
  */
 int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t *bbox,
                    const double *A, const double *B, const double *C0, const uint8_t *cull,
-                   const uint32_t *rgba, uint32_t W, int unsorted, uint32_t npix,
+                   const uint32_t *rgba, uint32_t W, int mode, uint32_t npix,
                    const uint32_t *pix, double *rgba_f64, uint32_t *count, uint64_t *offsets,
                    uint32_t *ids, uint64_t ids_cap)
 {
@@ -558,11 +604,14 @@ int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
             cnt++;
         }
         double o[4];
-        if (unsorted) {
+        if (mode == 1) {
             blend_over(fr, cnt, o);
         } else {
             qsort(fr, cnt, sizeof(frag_t), cmp_frag);
-            blend_front_to_back(fr, cnt, o);
+            if (mode == 2)
+                cnt = blend_front_to_back_cut(fr, cnt, o);  /* the blended prefix */
+            else
+                blend_front_to_back(fr, cnt, o);
         }
         for (int ch = 0; ch < 4; ch++)
             rgba_f64[4 * (size_t)k + ch] = o[ch];

@@ -29,12 +29,15 @@ MUTANTS = {
     "diagonal_normal_sign": ("p = e1[0] * e2[1]; s = e1[1] * e2[0]; nn[2] = p - s;",
                              "p = e1[0] * e2[1]; s = e1[1] * e2[0]; nn[2] = s - p;"),
     "key_clamp_dropped": ("    if (!(k > 0.0f))\n        k = 0.0f;\n    return k;", "    return k;"),
+    "cutoff_counts_before_blending": ("        k++;\n        if (T32 < LRO_CUT_T)\n            break;",
+                                      "        if (T32 < LRO_CUT_T)\n            break;\n        k++;"),
+    "cutoff_threshold_too_high": ("#define LRO_CUT_T (1.0f / 1048576.0f)", "#define LRO_CUT_T (1.0f / 65536.0f)"),
     "unsorted_under": ("C[ch] = a * ((double)((c >> (8 * ch)) & 255u) / 255.0) + (1.0 - a) * C[ch];",
                        "C[ch] = (1.0 - a) * ((double)((c >> (8 * ch)) & 255u) / 255.0) + a * C[ch];"),
 }
 
 PINS = ["tests/test_oracle_hand.py", "tests/test_oracle_bruteforce.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_keys.py"]
+        "tests/test_oracle_keys.py", "tests/test_oracle_cutoff.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
