@@ -274,18 +274,22 @@ static int cmp_frag(const void *pa, const void *pb)
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
+/* One front-to-back step: the fragment of colour c under transmittance T. */
+static void blend_step(uint32_t c, double *T, double C[3])
+{
+    double a = (double)(c >> 24) / 255.0;
+    double w = *T * a;
+    for (int ch = 0; ch < 3; ch++)
+        C[ch] = C[ch] + w * ((double)((c >> (8 * ch)) & 255u) / 255.0);
+    *T = *T * (1.0 - a);
+}
+
 /* Front-to-back blend of fragments already in order. */
 static void blend_front_to_back(const frag_t *fr, uint32_t cnt, double out[4])
 {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
-    for (uint32_t k = 0; k < cnt; k++) {
-        uint32_t c = fr[k].rgba;
-        double a = (double)(c >> 24) / 255.0;
-        double w = T * a;
-        for (int ch = 0; ch < 3; ch++)
-            C[ch] = C[ch] + w * ((double)((c >> (8 * ch)) & 255u) / 255.0);
-        T = T * (1.0 - a);
-    }
+    for (uint32_t k = 0; k < cnt; k++)
+        blend_step(fr[k].rgba, &T, C);
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
 }
 
@@ -302,11 +306,7 @@ static uint32_t blend_front_to_back_cut(const frag_t *fr, uint32_t cnt, double o
     uint32_t k = 0;
     while (k < cnt) {
         uint32_t c = fr[k].rgba;
-        double a = (double)(c >> 24) / 255.0;
-        double w = T * a;
-        for (int ch = 0; ch < 3; ch++)
-            C[ch] = C[ch] + w * ((double)((c >> (8 * ch)) & 255u) / 255.0);
-        T = T * (1.0 - a);
+        blend_step(c, &T, C);
         float a32 = (float)(c >> 24) * inv255;
         T32 = T32 * (1.0f - a32);
         k++;
