@@ -97,6 +97,19 @@ typedef struct {
 #define LR_FLAG_TIMING 1u     /* record per-stage times (hipEvents) */
 #define LR_FLAG_NO_GRAPH 2u   /* lr_render_batch launches directly instead
                                  of replaying captured hipGraphs */
+#define LR_FLAG_ALPHA_CUTOFF 4u /* transmittance cutoff, the tolerance-safe
+                                 form of the alpha threshold of Stage 3
+                                 ("Sample blending"): a pixel stops after the
+                                 first fragment (in exact depth order) that
+                                 brings its fp32 transmittance below 2^-20,
+                                 so the colour differs from the full blend by
+                                 less than 2^-20 per channel.  Pixels whose
+                                 transmittance gets there skip the rest of
+                                 their fragments once per-entry depth bounds
+                                 show none of them can come earlier.  Parity
+                                 dumps then report the blended prefix
+                                 (counts, order).  The unsorted baseline
+                                 ignores it. */
 
 /* Statistics of the last render call on the context (for a batch, summed over
  * its frames; error_word is the OR of theirs). */

@@ -183,6 +183,10 @@ struct FrameArgs {
     uint32_t *ent_code;       // block depth code
     unsigned long long *ent_mask;  // 64-sample coverage mask
     uint32_t *ent_id;         // quad index
+    uint32_t *ent_bound;      // with the cutoff: nearest possible order code of the entry's fragments
+    // transmittance cutoff: a pixel stops after the fragment that brings its
+    // fp32 transmittance below 2^-20 (0: exact blend of every fragment)
+    uint32_t alpha_cut;
     // entries of blocks with flagged pixels, kept for the exact pass: each
     // block's entries that cover one of its flagged pixels, their masks
     // restricted to those pixels, and the quad indices

@@ -170,6 +170,26 @@ __device__ __forceinline__ void blend_ftb(uint32_t c, float &T, float &R, float 
     blend_ftb_dec(decode_rgba(c), T, R, G, B);
 }
 
+// Transmittance below which a pixel stops when the cutoff is on (the
+// tolerance-safe form of the alpha threshold of Stage 3, "Sample blending":
+// what is left out weighs less than 2^-20 per channel).
+constexpr float kCutT = 0x1p-20f;
+
+// Front-to-back step with the cutoff: the same arithmetic as blend_ftb_dec
+// until a fragment brings T below kCutT; from then on the pixel is stopped
+// and later fragments blend nothing.  T keeps its value at the stop, so
+// "stopped" is T < kCutT (T starts at 1).
+__device__ __forceinline__ void blend_ftb_cut(float4 d, float &T, float &R, float &G, float &B)
+{
+    const bool stopped = T < kCutT;
+    const float w = stopped ? 0.0f : T * d.x;
+    R = fmaf(w, d.y, R);
+    G = fmaf(w, d.z, G);
+    B = fmaf(w, d.w, B);
+    const float Tn = T * (1.0f - d.x);
+    T = stopped ? T : Tn;
+}
+
 // "Over" step of the unsorted baseline (fp32).
 __device__ __forceinline__ void blend_over(uint32_t c, float &R, float &G, float &B, float &Al)
 {
@@ -1348,6 +1368,7 @@ struct FastEntries {
     unsigned long long mask[kFast];
     Stage st[kFast];
     uint32_t id[kFast];
+    uint32_t bound[kFast];              // with the cutoff: nearest possible order code
 };
 union WaveKeys {
     uint32_t key[kSortCap];
@@ -1365,6 +1386,7 @@ struct WalkStage {
 };
 struct WaveLds {
     uint32_t cand[128];
+    uint32_t seg_after[kSortCap / 64];  // cutoff: smallest bound code after each segment
     WaveKeys k;
     union {
         WalkStage w;  // phase 3
@@ -1500,12 +1522,16 @@ __device__ __forceinline__ void push_flagged(const FrameArgs &a, bool flag, cons
 // Per-pixel state of phase 3: the K-deep sorter (codes ascending, filled
 // with placeholder code 0 that is emitted first and blends nothing), the
 // last emitted code, and the front-to-back blend.
-template <int K, bool DEBUG>
+template <int K, bool DEBUG, bool CUT>
 struct PixelSorter {
     uint32_t qk[K], qc[K], qi[DEBUG ? K : 1];
     uint32_t last, nfrag, npop, obase;
     bool flagged;
+    bool done;     // CUT: stopped, and no fragment left can precede the ones emitted
     float T, R, G, B;
+
+    // CUT: the transmittance is below kCutT: nothing more is blended
+    __device__ __forceinline__ bool stopped() const { return T < kCutT; }
 
     __device__ __forceinline__ void init(uint32_t ob)
     {
@@ -1519,6 +1545,7 @@ struct PixelSorter {
         last = nfrag = npop = 0;
         obase = ob;
         flagged = false;
+        done = false;
         T = 1.0f;
         R = G = B = 0.0f;
     }
@@ -1527,8 +1554,12 @@ struct PixelSorter {
     {
         flagged |= (pk - 1u) < last;  // emitted codes must strictly increase (placeholders excepted)
         last = pk;
-        blend_ftb(pc, T, R, G, B);
-        if (DEBUG && pk != 0) {
+        const bool live = !CUT || !stopped();  // this fragment is blended
+        if (CUT)
+            blend_ftb_cut(decode_rgba(pc), T, R, G, B);
+        else
+            blend_ftb(pc, T, R, G, B);
+        if (DEBUG && pk != 0 && live) {
             if (a.dbg_ids && on && obase + npop < a.dbg_cap)
                 a.dbg_ids[obase + npop] = pi;
             npop++;
@@ -1563,6 +1594,17 @@ struct PixelSorter {
         emit(a, on, pk, pc, pi);
     }
 
+    // every fragment still queued comes strictly after the last emitted one
+    // (placeholders excepted)
+    __device__ __forceinline__ bool queue_after_last() const
+    {
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < K; j++)
+            ok = ok && (qk[j] == 0u || qk[j] > last);
+        return ok;
+    }
+
     __device__ __forceinline__ void flush(const FrameArgs &a, bool on)
     {
 #pragma unroll
@@ -1581,24 +1623,53 @@ struct PixelSorter {
 // With half-blocks, the rows 0-3 and 4-7 of a mask become separate entries,
 // each keyed at the centroid of its own samples: one sort then orders both
 // 8x4 halves, and a pixel only sees the entries of its half.
+template <bool CUT>
 __device__ __forceinline__ void put_entry(const FrameArgs &a, WaveLds &L, uint32_t ebase, uint32_t sb,
                                           uint32_t slot, uint32_t code, uint64_t mask, uint32_t q,
-                                          const PlaneRec &pl, bool to_global)
+                                          const PlaneRec &pl, bool to_global, uint32_t bound)
 {
     if (to_global) {
         a.ent_code[ebase + slot] = code;
         a.ent_mask[ebase + slot] = mask;
         a.ent_id[ebase + slot] = q;
+        if (CUT)
+            a.ent_bound[ebase + slot] = bound;
     } else {  // slot < kFast
         L.k.f.code[slot] = code;
         L.k.f.mask[slot] = mask;
         L.k.f.st[slot] = pl;
         L.k.f.id[slot] = q;
+        if (CUT)
+            L.k.f.bound[slot] = bound;
     }
     if (slot < kSortCap)
         L.k.key[slot] = ((code >> (sb - 1)) << sb) | slot;  // code: 31 bits
 }
 
+// Nearest order code any fragment of an entry can have (with the cutoff):
+// the plane's largest value over the part of the pixel rectangle [i0, i1] x
+// [j0, j1] inside the quad's bbox (an affine function peaks at a corner),
+// rounded to fp32 and raised by one ulp, which bounds every fragment key of
+// the entry from above (their fp64 values differ from the true plane by far
+// less than half an fp32 ulp).  0 (no bound) when that value is not positive.
+__device__ __forceinline__ uint32_t entry_bound_code(const PlaneRec &pl, const CovRec &r, int i0, int i1, int j0,
+                                                     int j1)
+{
+    const int imin = (int)(pl.ij & 0xffffu), jmin = (int)(pl.ij >> 16);
+    i0 = max(i0, imin);
+    i1 = min(i1, (int)(r.bb_i >> 16));
+    j0 = max(j0, jmin);
+    j1 = min(j1, (int)(r.bb_j >> 16));
+    const int di = (pl.A >= 0.0 ? i1 : i0) - imin;
+    const int dj = (pl.B >= 0.0 ? j1 : j0) - jmin;
+    const float k = (float)fma(pl.A, (double)di, fma(pl.B, (double)dj, pl.C0));
+    if (!(k > 1e-30f))
+        return 0u;
+    const uint32_t kb = __float_as_uint(k);
+    return ~(kb >= 0x7F800000u ? 0x7F800000u : kb + 1u);
+}
+
+template <bool CUT>
 __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadXY *__restrict__ xyp, WaveLds &L,
                                              uint32_t m, const BlockGeom &g, uint32_t lane, uint32_t ebase,
                                              uint32_t sb, bool half, uint32_t &n)
@@ -1616,13 +1687,20 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadXY *_
         pl = a.plane[q];
     }
     const uint64_t mk = batch_masks(r, has, a.extra, xyp, q, L.s.rw, g.px0, g.py0, lane) & g.onmask;
+    uint32_t d0 = 0, d1 = 0;  // CUT: entry bounds
     if (has) {
         m0 = half ? (mk & 0xFFFFFFFFull) : mk;
         m1 = half ? (mk & ~0xFFFFFFFFull) : 0;
-        if (m0)
+        if (m0) {
             c0 = block_depth_code(pl, m0, g.px0, g.py0);
-        if (m1)
+            if (CUT)
+                d0 = entry_bound_code(pl, r, g.px0, g.px1, g.py0, half ? g.py0 + 3 : g.py1);
+        }
+        if (m1) {
             c1 = block_depth_code(pl, m1, g.px0, g.py0);
+            if (CUT)
+                d1 = entry_bound_code(pl, r, g.px0, g.px1, g.py0 + 4, g.py1);
+        }
     }
     const uint64_t b0 = ballot(m0 != 0);
     const uint64_t b1 = half ? ballot(m1 != 0) : 0;
@@ -1633,11 +1711,13 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadXY *_
         a.ent_code[ebase + lane] = L.k.f.code[lane];
         a.ent_mask[ebase + lane] = L.k.f.mask[lane];
         a.ent_id[ebase + lane] = L.k.f.id[lane];
+        if (CUT)
+            a.ent_bound[ebase + lane] = L.k.f.bound[lane];
     }
     if (m0)
-        put_entry(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, pl, to_global);
+        put_entry<CUT>(a, L, ebase, sb, n + rank_below(b0), c0, m0, q, pl, to_global, d0);
     if (m1)
-        put_entry(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, pl, to_global);
+        put_entry<CUT>(a, L, ebase, sb, n + n0 + rank_below(b1), c1, m1, q, pl, to_global, d1);
     n += n0 + (uint32_t)__popcll(b1);
 }
 
@@ -1645,12 +1725,47 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadXY *_
 // an index into the wave's global entry region): depth-sort them, then one
 // lane per pixel walks them in 64-entry segments whose coverage masks are
 // transposed to per-pixel bit sets, feeding each pixel's sorter.
-template <int K, bool DEBUG>
-__device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n,
-                             uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
+//
+// With the cutoff, a pixel whose transmittance has dropped below kCutT is
+// done -- it skips the rest of the list -- once no fragment left can come
+// before the ones it emitted: every entry after the current segment
+// (rest_after covers entries walked after this list) has a bound code above
+// its last emitted code, and so has everything still in its queue.  Then
+// the fragments it blended are exactly the first ones of the full order.
+// A wave stops walking when all its pixels are done or flagged.
+template <int K, bool DEBUG, bool CUT>
+__device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t ebase, uint32_t sb,
+                             const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG, CUT> &ps,
+                             uint32_t rest_after = 0xFFFFFFFFu)
 {
     wave_sync();
     wave_bitonic_sort<uint32_t>(L.k.key, n, 0xFFFFFFFFu, lane);
+    // CUT: seg_after[s] is the smallest bound code of the entries after segment s
+    if (CUT) {
+        // segments from the back, four at a time (their loads issued together)
+        const uint32_t nseg = (n + 63) / 64;
+        uint32_t run = rest_after;
+        for (int g4 = (int)((nseg + 3) / 4) - 1; g4 >= 0; g4--) {
+            uint32_t bm[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t e = (uint32_t)(g4 * 4 + k) * 64 + lane;
+                bm[k] = e < n ? a.ent_bound[ebase + (L.k.key[e] & ((1u << sb) - 1))] : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int k = 3; k >= 0; k--) {
+                const uint32_t sg = (uint32_t)(g4 * 4 + k);
+                if (sg < nseg && lane == 0)
+                    L.seg_after[sg] = run;
+                if (sg < nseg) {
+                    uint32_t v = bm[k];
+                    for (int off = 32; off > 0; off >>= 1)
+                        v = min(v, shfl_xor(v, off));
+                    run = min(run, v);
+                }
+            }
+        }
+    }
     for (uint32_t seg = 0; seg < n; seg += 64) {
         const uint32_t e = seg + lane;
         uint64_t m = 0;
@@ -1664,7 +1779,7 @@ __device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n,
         }
         wave_sync();
         uint64_t col = transpose64(m, lane);
-        if (!g.on || ps.flagged)
+        if (!g.on || ps.flagged || ps.done)
             col = 0;
         while (col) {
             const uint32_t k = (uint32_t)__builtin_ctzll(col);
@@ -1677,6 +1792,12 @@ __device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n,
                 col = 0;
         }
         wave_sync();
+        if (CUT) {
+            const uint32_t rest = L.seg_after[seg >> 6];
+            ps.done = ps.done || (ps.stopped() && !ps.flagged && rest > ps.last && ps.queue_after_last());
+            if (!ballot(g.on && !ps.flagged && !ps.done))
+                break;
+        }
     }
 }
 
@@ -1703,9 +1824,9 @@ __device__ __forceinline__ uint32_t wave_sort_reg(uint32_t v, uint32_t lane)
 // Phases 2 and 3 for a block of n <= kFast entries, all on chip: the keys
 // are sorted in registers and each entry's mask, plane and colour come from
 // the fast entries written during phase 1.
-template <int K, bool DEBUG>
+template <int K, bool DEBUG, bool CUT>
 __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t sb, const BlockGeom &g,
-                          uint32_t lane, PixelSorter<K, DEBUG> &ps)
+                          uint32_t lane, PixelSorter<K, DEBUG, CUT> &ps)
 {
     wave_sync();
     uint32_t key = lane < n ? L.k.f.key[lane] : 0xFFFFFFFFu;
@@ -1740,10 +1861,12 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
 // from the global entry region into the LDS keys and walked.  The pixel
 // sorters carry over from slice to slice, so they see the same entry order
 // as one sort of the whole list.  Returns false when one bucket alone holds
-// more than kSortCap entries.
-template <int K, bool DEBUG>
-__device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n,
-                            uint32_t ebase, uint32_t sb, const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG> &ps)
+// more than kSortCap entries.  With the cutoff, each slice is walked knowing
+// the smallest bound code of the slices after it, and the walk ends when
+// every pixel of the block is done or flagged.
+template <int K, bool DEBUG, bool CUT>
+__device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t ebase, uint32_t sb,
+                            const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG, CUT> &ps)
 {
     // the key range of the block's entries
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
@@ -1760,15 +1883,38 @@ __device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n,
     const uint32_t bits = span ? 32 - __builtin_clz(span) : 1;
     const uint32_t hs = bits > 8 ? bits - 8 : 0;  // bucket = (code - kmin) >> hs, in [0, 256)
     uint32_t *hist = L.k.key;  // reused: 256 counters, then the slice keys
-    for (uint32_t b = lane; b < 256; b += 64)
+    uint32_t *bmin = L.k.key + 256;  // CUT: smallest bound code per bucket
+    for (uint32_t b = lane; b < 256; b += 64) {
         hist[b] = 0;
+        if (CUT)
+            bmin[b] = 0xFFFFFFFFu;
+    }
     wave_sync();
-    for (uint32_t e = lane; e < n; e += 64)
-        atomicAdd(&hist[(a.ent_code[ebase + e] - kmin) >> hs], 1u);
+    for (uint32_t e = lane; e < n; e += 64) {
+        const uint32_t bk = (a.ent_code[ebase + e] - kmin) >> hs;
+        atomicAdd(&hist[bk], 1u);
+        if (CUT)
+            atomicMin(&bmin[bk], a.ent_bound[ebase + e]);
+    }
     wave_sync();
-    uint32_t counts[4];
+    uint32_t counts[4], sfx[4];
     for (int k = 0; k < 4; k++)
         counts[k] = hist[lane * 4 + k];  // lane holds buckets 4*lane .. 4*lane+3
+    if (CUT) {
+        // sfx[k]: smallest bound code of the buckets from 4*lane+k on
+        for (int k = 0; k < 4; k++)
+            sfx[k] = bmin[lane * 4 + k];
+        for (int k = 2; k >= 0; k--)
+            sfx[k] = min(sfx[k], sfx[k + 1]);
+        uint32_t run = 0xFFFFFFFFu;
+        for (int l = 63; l >= 0; l--) {
+            const uint32_t v = lane_value(sfx[0], (uint32_t)l);
+            if (lane == (uint32_t)l)
+                for (int k = 0; k < 4; k++)
+                    sfx[k] = min(sfx[k], run);
+            run = min(run, v);
+        }
+    }
     wave_sync();
     // code resolution inside a slice: 32 - sb bits for the (code - lo) part
     const uint32_t room = 32 - sb;
@@ -1805,7 +1951,15 @@ __device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n,
                 L.k.key[ns + rank_below(bm)] = (((code - lo) >> sh) << sb) | e;
             ns += (uint32_t)__popcll(bm);
         }
-        walk_entries<K, DEBUG>(a, L, ns, ebase, sb, g, lane, ps);
+        uint32_t rest = 0xFFFFFFFFu;
+        if (CUT && b1 < 256) {
+            const uint32_t k = b1 & 3u;
+            const uint32_t v = k == 0 ? sfx[0] : (k == 1 ? sfx[1] : (k == 2 ? sfx[2] : sfx[3]));
+            rest = lane_value(v, b1 >> 2);
+        }
+        walk_entries<K, DEBUG, CUT>(a, L, ns, ebase, sb, g, lane, ps, rest);
+        if (CUT && !ballot(g.on && !ps.flagged && !ps.done))
+            break;
         b0 = b1;
     }
     return true;
@@ -1861,9 +2015,9 @@ __device__ void keep_flagged_entries(const FrameArgs &a, const WaveLds &L, const
 // Outputs of a finished block: the pixel, flagged pixels to the exact
 // queue (with the block's entries kept for them), and the wave's running
 // statistics.
-template <int K, bool DEBUG>
+template <int K, bool DEBUG, bool CUT>
 __device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGeom &g, uint32_t lane,
-                             PixelSorter<K, DEBUG> &ps, uint32_t entries, uint32_t ebase)
+                             PixelSorter<K, DEBUG, CUT> &ps, uint32_t entries, uint32_t ebase)
 {
     if (g.on && !ps.flagged)
         ps.flush(a, g.on);
@@ -1879,7 +2033,7 @@ __device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGe
     }
     if (DEBUG && g.on) {
         if (a.dbg_count)
-            a.dbg_count[g.pix] = ps.nfrag;
+            a.dbg_count[g.pix] = CUT ? ps.npop : ps.nfrag;  // with the cutoff: fragments blended
         if (a.dbg_flag)
             a.dbg_flag[g.pix] = ps.flagged ? 1 : 0;
     }
@@ -1898,8 +2052,8 @@ __device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGe
 
 // Sorted raster: one workgroup of NW waves per bin, one 8x8 block per wave
 // per round.
-template <int K, bool DEBUG, class Src, int NW>
-__global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster(Src src)
+template <int K, bool DEBUG, class Src, int NW, bool CUT>
+__global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 12 || (K <= 16 && !CUT))) ? 4 : 2) void k_raster(Src src)
 {
     __shared__ BinChunk<NW> C;
     __shared__ WaveLds Lw[NW];
@@ -1930,22 +2084,22 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
         const BlockGeom g = block_geom(a, bx_bin + k % bpb, by_bin + k / bpb, k < nb, lane);
         uint32_t n = 0;
         scan_bin<NW>(bbox, pairs, C, L, start, cnt, cached, g, [&](uint32_t m) {
-            sorted_batch(a, xyp, L, m, g, lane, ebase, sb, half, n);
+            sorted_batch<CUT>(a, xyp, L, m, g, lane, ebase, sb, half, n);
         });
         if (g.active) {
-            PixelSorter<K, DEBUG> ps;
+            PixelSorter<K, DEBUG, CUT> ps;
             ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
             if (n <= kFast) {
-                walk_fast<K, DEBUG>(a, L, n, sb, g, lane, ps);
+                walk_fast<K, DEBUG, CUT>(a, L, n, sb, g, lane, ps);
             } else {
                 // entries written by other lanes of this wave are read back below
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 if (n <= kSortCap) {
-                    walk_entries<K, DEBUG>(a, L, n, ebase, sb, g, lane, ps);
+                    walk_entries<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps);
                 } else {
                     if (lane == 0)
                         atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
-                    if (!walk_sliced<K, DEBUG>(a, L, n, ebase, sb, g, lane, ps)) {
+                    if (!walk_sliced<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps)) {
                         // no slice fits: the exact path takes the block
                         ps.flagged = true;
                         if (lane == 0)
@@ -1953,7 +2107,7 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && K <= 16) ? 4 : 2) void k_raster
                     }
                 }
             }
-            finish_block<K, DEBUG>(a, L, g, lane, ps, n, ebase);
+            finish_block<K, DEBUG, CUT>(a, L, g, lane, ps, n, ebase);
         }
     }
 }
@@ -2051,11 +2205,13 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
             const uint32_t bit = (((uint32_t)j & 7u) << 3) | ((uint32_t)i & 7u);
             const uint32_t obase = (DEBUG && a.dbg_off) ? a.dbg_off[p] : 0;
             float T = 1.0f, R = 0.0f, G2 = 0.0f, B = 0.0f;
+            const bool cut = a.alpha_cut != 0;
             unsigned long long lo = 0;  // keys <= lo are blended already (real keys are > 0)
             uint32_t total = 0, done = 0;
+            uint32_t blended = 0;
             for (bool more = true; more;) {
                 unsigned long long hi = ~0ull;  // the buffer holds every key in (lo, hi]
-                bool cut = false;
+                bool cut_round = false;  // the buffer overflowed: keys above hi wait for a later round
                 uint32_t n = 0, seen = 0;
                 // kFallbackStep chunks of 64 candidates per step: each stage's loads
                 // (list entries, then bboxes, then records) are issued together
@@ -2065,7 +2221,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                         wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
                         n = kFallbackBuf / 2;
                         hi = s_key[n - 1];
-                        cut = true;
+                        cut_round = true;
                         wave_sync();
                     }
                     uint32_t q[kFallbackStep];
@@ -2119,27 +2275,35 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                 if (total == 0)
                     total = seen;
                 wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
-                for (uint32_t base = 0; base < n; base += 64) {
+                for (uint32_t base = 0; base < n && !(cut && T < kCutT); base += 64) {
                     const uint32_t e = base + lane;
                     uint32_t q = 0, c = 0;
                     if (e < n) {
                         q = (uint32_t)(s_key[e] & 0xffffffffu);
                         c = a.plane[q].rgba;
-                        if (DEBUG && a.dbg_ids && obase + done + e < a.dbg_cap)
-                            a.dbg_ids[obase + done + e] = q;
                     }
                     // colours decoded by all lanes, then blended in order
                     s_col[lane] = decode_rgba(c);
                     wave_sync();
                     const uint32_t lim = min(64u, n - base);
-                    for (uint32_t s = 0; s < lim; s++)
-                        blend_ftb_dec(s_col[s], T, R, G2, B);
+                    uint32_t nb = lim;  // fragments of this group blended
+                    if (cut) {
+                        nb = 0;
+                        for (uint32_t s = 0; s < lim && !(T < kCutT); s++, nb++)
+                            blend_ftb_cut(s_col[s], T, R, G2, B);
+                    } else {
+                        for (uint32_t s = 0; s < lim; s++)
+                            blend_ftb_dec(s_col[s], T, R, G2, B);
+                    }
+                    if (DEBUG && a.dbg_ids && lane < nb && obase + done + e < a.dbg_cap)
+                        a.dbg_ids[obase + done + e] = q;
+                    blended += nb;
                     wave_sync();
                 }
                 done += n;
                 if (n)
                     lo = s_key[n - 1];
-                more = cut;
+                more = cut_round && !(cut && T < kCutT);
                 wave_sync();
             }
             if (lane == 0) {
@@ -2149,7 +2313,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                     if (a.dbg_rgba)
                         reinterpret_cast<float4 *>(a.dbg_rgba)[p] = make_float4(R, G2, B, 1.0f - T);
                     if (a.dbg_count)
-                        a.dbg_count[p] = total;
+                        a.dbg_count[p] = cut ? blended : total;
                 }
             }
             wave_sync();
@@ -2307,20 +2471,21 @@ bool sorter_depth_supported(int k)
 }
 
 // Raster (one workgroup per bin), then the exact pass.
-template <int K, bool DEBUG>
+template <int K, bool DEBUG, bool CUT>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     const OneFrame f{a};
-    // the parity dump keeps one more id per sorter slot: past depth 4 its
-    // kernels do not fit 16 waves' registers and take 8 (the image is the same)
-    constexpr bool wide_dbg = DEBUG && K > 4;
+    // the parity dump keeps one more id per sorter slot: past depth 4 (and
+    // with the cutoff) its kernels do not fit 16 waves' registers and take 8
+    // (the image is the same)
+    constexpr bool wide_dbg = DEBUG && (K > 4 || CUT);
     const uint32_t nw = min(raster_waves_for(a.bin_shift, K), wide_dbg ? 8u : 16u);
     if (nw == 4)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4>), dim3(a.nbins), dim3(4 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4, CUT>), dim3(a.nbins), dim3(4 * 64), 0, s, f);
     else if (nw == 8)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8>), dim3(a.nbins), dim3(8 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8, CUT>), dim3(a.nbins), dim3(8 * 64), 0, s, f);
     else if constexpr (K <= 12 && !wide_dbg)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16>), dim3(a.nbins), dim3(16 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16, CUT>), dim3(a.nbins), dim3(16 * 64), 0, s, f);
     if (ev) {
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
@@ -2331,17 +2496,17 @@ static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
         (void)hipEventRecord(ev[7], s);
 }
 
-template <bool DEBUG>
+template <bool DEBUG, bool CUT>
 static void launch_sorted_k(const FrameArgs &a, int k, hipStream_t s, hipEvent_t *ev)
 {
     switch (k) {
-    case 2: launch_sorted<2, DEBUG>(a, s, ev); break;
-    case 4: launch_sorted<4, DEBUG>(a, s, ev); break;
-    case 8: launch_sorted<8, DEBUG>(a, s, ev); break;
-    case 12: launch_sorted<12, DEBUG>(a, s, ev); break;
-    case 16: launch_sorted<16, DEBUG>(a, s, ev); break;
-    case 24: launch_sorted<24, DEBUG>(a, s, ev); break;
-    default: launch_sorted<32, DEBUG>(a, s, ev); break;
+    case 2: launch_sorted<2, DEBUG, CUT>(a, s, ev); break;
+    case 4: launch_sorted<4, DEBUG, CUT>(a, s, ev); break;
+    case 8: launch_sorted<8, DEBUG, CUT>(a, s, ev); break;
+    case 12: launch_sorted<12, DEBUG, CUT>(a, s, ev); break;
+    case 16: launch_sorted<16, DEBUG, CUT>(a, s, ev); break;
+    case 24: launch_sorted<24, DEBUG, CUT>(a, s, ev); break;
+    default: launch_sorted<32, DEBUG, CUT>(a, s, ev); break;
     }
 }
 
@@ -2375,9 +2540,14 @@ hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipS
             (void)hipEventRecord(ev[7], s);
         }
     } else if (dbg) {
-        launch_sorted_k<true>(a, sorter_depth, s, ev);
+        if (a.alpha_cut)
+            launch_sorted_k<true, true>(a, sorter_depth, s, ev);
+        else
+            launch_sorted_k<true, false>(a, sorter_depth, s, ev);
+    } else if (a.alpha_cut) {
+        launch_sorted_k<false, true>(a, sorter_depth, s, ev);
     } else {
-        launch_sorted_k<false>(a, sorter_depth, s, ev);
+        launch_sorted_k<false, false>(a, sorter_depth, s, ev);
     }
     return hipGetLastError();
 }
@@ -2400,15 +2570,15 @@ static FrameMap stage_map(const FrameArgs *dev, uint32_t nf, F &&wg)
     return m;
 }
 
-template <int K>
+template <int K, bool CUT>
 static void launch_raster_group(const FrameMap &m, uint32_t nw, hipStream_t s)
 {
     if (nw == 4)
-        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 4>), dim3(m.wg0[m.nf]), dim3(4 * 64), 0, s, m);
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 4, CUT>), dim3(m.wg0[m.nf]), dim3(4 * 64), 0, s, m);
     else if (nw == 8)
-        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 8>), dim3(m.wg0[m.nf]), dim3(8 * 64), 0, s, m);
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 8, CUT>), dim3(m.wg0[m.nf]), dim3(8 * 64), 0, s, m);
     else if constexpr (K <= 12)
-        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 16>), dim3(m.wg0[m.nf]), dim3(16 * 64), 0, s, m);
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 16, CUT>), dim3(m.wg0[m.nf]), dim3(16 * 64), 0, s, m);
 }
 
 hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *sorter_depth, uint32_t nf,
@@ -2450,23 +2620,39 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     static const uint32_t kWaveCounts[] = {4, 8, 16};
     for (int K : kDepths) {
         for (uint32_t nw : kWaveCounts) {
-            auto in_group = [&](uint32_t f) {
-                return sorter_depth[f] == K && raster_waves_for(host[f].bin_shift, K) == nw;
-            };
-            bool any = false;
-            for (uint32_t f = 0; f < nf; f++)
-                any = any || in_group(f);
-            if (!any)
-                continue;
-            const FrameMap mr = stage_map(dev, nf, [&](uint32_t f) { return in_group(f) ? host[f].nbins : 0u; });
-            switch (K) {
-            case 2: launch_raster_group<2>(mr, nw, s); break;
-            case 4: launch_raster_group<4>(mr, nw, s); break;
-            case 8: launch_raster_group<8>(mr, nw, s); break;
-            case 12: launch_raster_group<12>(mr, nw, s); break;
-            case 16: launch_raster_group<16>(mr, nw, s); break;
-            case 24: launch_raster_group<24>(mr, nw, s); break;
-            default: launch_raster_group<32>(mr, nw, s); break;
+            for (uint32_t cut = 0; cut < 2; cut++) {
+                auto in_group = [&](uint32_t f) {
+                    return sorter_depth[f] == K && raster_waves_for(host[f].bin_shift, K) == nw &&
+                           (host[f].alpha_cut != 0) == (cut != 0);
+                };
+                bool any = false;
+                for (uint32_t f = 0; f < nf; f++)
+                    any = any || in_group(f);
+                if (!any)
+                    continue;
+                const FrameMap mr =
+                    stage_map(dev, nf, [&](uint32_t f) { return in_group(f) ? host[f].nbins : 0u; });
+                if (cut) {
+                    switch (K) {
+                    case 2: launch_raster_group<2, true>(mr, nw, s); break;
+                    case 4: launch_raster_group<4, true>(mr, nw, s); break;
+                    case 8: launch_raster_group<8, true>(mr, nw, s); break;
+                    case 12: launch_raster_group<12, true>(mr, nw, s); break;
+                    case 16: launch_raster_group<16, true>(mr, nw, s); break;
+                    case 24: launch_raster_group<24, true>(mr, nw, s); break;
+                    default: launch_raster_group<32, true>(mr, nw, s); break;
+                    }
+                } else {
+                    switch (K) {
+                    case 2: launch_raster_group<2, false>(mr, nw, s); break;
+                    case 4: launch_raster_group<4, false>(mr, nw, s); break;
+                    case 8: launch_raster_group<8, false>(mr, nw, s); break;
+                    case 12: launch_raster_group<12, false>(mr, nw, s); break;
+                    case 16: launch_raster_group<16, false>(mr, nw, s); break;
+                    case 24: launch_raster_group<24, false>(mr, nw, s); break;
+                    default: launch_raster_group<32, false>(mr, nw, s); break;
+                    }
+                }
             }
         }
     }

@@ -191,6 +191,7 @@ struct lr_context_s {
     std::vector<hipEvent_t> ring;  // kRing * 8
     uint32_t ring_head = 0, ring_count = 0;
     bool timing = false;
+    bool cut = false;  // LR_FLAG_ALPHA_CUTOFF
     bool have_frame = false;
     std::string err;
     std::mutex mu;
@@ -238,13 +239,15 @@ struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks;
     uint64_t o_cov, o_plane, o_extra, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
-        o_femask, o_feid, o_blkent, total;
+        o_femask, o_feid, o_blkent, o_ebound, total;
     uint32_t fe_cap;
+    uint32_t cut;  // transmittance cutoff: entries carry a bound code
 };
 
-Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, uint32_t pair_hint)
+Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, uint32_t pair_hint, uint32_t cut)
 {
     Plan p{};
+    p.cut = cut;
     p.n = n;
     p.W = W;
     p.H = H;
@@ -300,6 +303,7 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_ecode = take(ents * 4);
     p.o_emask = take(ents * 8);
     p.o_eid = take(ents * 4);
+    p.o_ebound = cut ? take(ents * 4) : 0;
     // entries kept for the exact pass (blocks past this capacity walk their bin list)
     p.fe_cap = std::max<uint32_t>(p.pair_cap, 65536u);
     p.o_femask = take((uint64_t)p.fe_cap * 8);
@@ -379,7 +383,7 @@ lr_status check_frame(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
         return fail(ctx, LR_ERR_INVALID_ARG, "sorter depth must be one of 2, 4, 8, 12, 16, 24, 32");
     if (!std::isfinite(cam->fov_y) || !(cam->fov_y > 0.0f) || !(cam->fov_y < 3.14159f))
         return fail(ctx, LR_ERR_INVALID_ARG, "fov_y must be in (0, pi)");
-    plan = make_plan(it->second.n, W, H, t.bin, t.half, pair_hint(ctx, scene, W, H, t.bin));
+    plan = make_plan(it->second.n, W, H, t.bin, t.half, pair_hint(ctx, scene, W, H, t.bin), ctx->cut ? 1u : 0u);
     if (plan.nbins > kMaxBins)
         return fail(ctx, LR_ERR_INVALID_ARG,
                     "too many bins for this frame size (at most 16384; use a larger bin size)");
@@ -434,6 +438,8 @@ void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *ou
     a.ent_code = reinterpret_cast<uint32_t *>(base + plan.o_ecode);
     a.ent_mask = reinterpret_cast<unsigned long long *>(base + plan.o_emask);
     a.ent_id = reinterpret_cast<uint32_t *>(base + plan.o_eid);
+    a.ent_bound = plan.cut ? reinterpret_cast<uint32_t *>(base + plan.o_ebound) : nullptr;
+    a.alpha_cut = plan.cut;
     a.fe_mask = reinterpret_cast<unsigned long long *>(base + plan.o_femask);
     a.fe_id = reinterpret_cast<uint32_t *>(base + plan.o_feid);
     a.fe_cap = plan.fe_cap;
@@ -733,6 +739,7 @@ lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::Fram
         key.push_back(host[f].bin_shift);  // raster waves per workgroup and binning kernels
         key.push_back(host[f].bin_waves);
         key.push_back((uint64_t)ks[f]);
+        key.push_back(host[f].alpha_cut);
     }
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
@@ -913,6 +920,7 @@ lr_status lr_create(const lr_config *cfg, lr_context *out)
     ctx->alloc.init(ctx->arena_bytes);
     ctx->timing = (c.flags & LR_FLAG_TIMING) != 0;
     ctx->use_graphs = (c.flags & LR_FLAG_NO_GRAPH) == 0;
+    ctx->cut = (c.flags & LR_FLAG_ALPHA_CUTOFF) != 0;
     ctx->max_slots = c.batch_slots;
     ctx->slots.reserve(8);  // slot addresses stay fixed (at most 8 slots)
     bool ok = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming) == hipSuccess;

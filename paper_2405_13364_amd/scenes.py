@@ -174,6 +174,9 @@ RECIPES: Dict[str, Recipe] = {
     # 1920x1080, 1M quads in a Gaussian cloud (sigma 0.15 screen), 1-30 px,
     # alpha U[0.05, 0.5]: hundreds of layers at the centre
     "c3": Recipe(1920, 1080, 1_000_000, 2, True, 0.15, (1.0, 10.0), (1.0, 30.0), (0.05, 0.5)),
+    # the same cloud with alpha U[0.8, 1.0]: mostly opaque layers, where the
+    # transmittance cutoff (the paper's alpha threshold experiments) pays
+    "c3o": Recipe(1920, 1080, 1_000_000, 2, True, 0.15, (1.0, 10.0), (1.0, 30.0), (0.8, 1.0)),
 }
 
 RESOLUTIONS: List[Tuple[int, int]] = [(256, 256), (640, 480), (1280, 720), (1920, 1080)]
