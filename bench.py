@@ -38,6 +38,8 @@ WORKLOADS = {
     "c3": "1920x1080, 1M quads 1-30 px in a Gaussian cloud (sigma 0.15 screen), z U[1,10], "
           "alpha U[0.05,0.5], seed 2",
     "c1": "256x256, 1k quads 4-40 px, z U[1,10], alpha U[0.2,0.8], seed 0",
+    "c3o": "1920x1080, 1M quads 1-30 px in a Gaussian cloud (sigma 0.15 screen), z U[1,10], "
+           "alpha U[0.8,1.0], seed 2",
 }
 
 KERNELS = {"setup": "k_setup", "bin_count": "k_bin_count", "bin_scan": "k_bin_scan_tiles+k_bin_scan_final",
@@ -290,6 +292,41 @@ def serving_leg(torch, lucidraster, scenes, rules, n_scenes, n_req, log):
     return res
 
 
+def cutoff_leg(torch, lucidraster, autotune, rules, steps, warmup, arena, log):
+    """The transmittance cutoff (LR_FLAG_ALPHA_CUTOFF) against the exact
+    blend, at the rule-table tuning: the 1920x1080 cloud (alpha U[0.05, 0.5])
+    and the same cloud with alpha U[0.8, 1.0]."""
+    from paper_2405_13364_amd import scenes
+    res = {"note": "ms per frame, exact blend vs transmittance cutoff (stop below 2^-20); fragments = "
+                   "fragments processed by the raster and the exact pass"}
+    for name in ("c3", "c3o"):
+        sc = scenes.scene(name)
+        b, k, bh = autotune.resolve(rules, sc.width, sc.height, sc.n)
+        row = {"workload": f"{name}: {WORKLOADS[name]}", "tuning": f"bin {b}, K {k}, 8x{bh}"}
+        for mode in ("exact", "cutoff"):
+            ctx = lucidraster.Context(arena_bytes=arena, bin_size=b, sorter_depth=k, block_h=bh,
+                                      alpha_cutoff=(mode == "cutoff"))
+            h = ctx.upload(sc.v, sc.rgba)
+            out = ctx.new_image(sc.width, sc.height)
+            ctx.render(h, sc.camera, sc.width, sc.height, out=out)
+            st = ctx.stats()
+            ms = time_steps(torch, lambda: ctx.render(h, sc.camera, sc.width, sc.height, out=out, check=False),
+                            steps, warmup) / steps
+            ctx.sync()
+            row[mode] = {"ms_per_frame": round(ms, 5), "frames_per_s": round(1000.0 / ms, 2),
+                         "fragments_processed": int(st["fragments"]),
+                         "flagged_pixels": int(st["flagged_pixels"])}
+            if mode == "cutoff":
+                row["max_lsb_vs_exact"] = int((out.to(torch.int32) - ref_img.to(torch.int32)).abs().max().item())
+            else:
+                ref_img = out.clone()
+            ctx.close()
+        row["speedup"] = round(row["exact"]["ms_per_frame"] / row["cutoff"]["ms_per_frame"], 3)
+        log(f"cutoff {name}: exact {row['exact']['ms_per_frame']:.4f} ms, cutoff {row['cutoff']['ms_per_frame']:.4f} ms")
+        res[name] = row
+    return res
+
+
 def frame_leg(torch, lucidraster, autotune, sc, workload, tune, tuning_note, steps, warmup, arena):
     """Sorted and unsorted frame times of one workload at one tuning, and the
     dominant kernel's roofline from a pass with events between stages."""
@@ -398,6 +435,7 @@ def main():
     ap.add_argument("--no-side", action="store_true", help="skip the 1280x720 side leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame mixed batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
+    ap.add_argument("--no-cutoff", action="store_true", help="skip the transmittance-cutoff leg")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-scenes", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -485,6 +523,9 @@ def main():
             side[mode] = frame_leg(torch, lucidraster, autotune, sc2, "c2", t2, n2, args.steps, args.warmup,
                                    arena)["line"]
         res["side_c2"] = side
+    if not args.no_cutoff:
+        log("transmittance cutoff leg")
+        res["alpha_cutoff"] = cutoff_leg(torch, lucidraster, autotune, rules, args.steps, args.warmup, arena, log)
     if not args.no_batch:
         log("64-frame mixed batch")
         res["batch"] = mixed_batch_leg(torch, lucidraster, scenes, rules, args.batch_reps, log)
