@@ -110,6 +110,20 @@ typedef struct {
                                  dumps then report the blended prefix
                                  (counts, order).  The unsorted baseline
                                  ignores it. */
+#define LR_FLAG_DENSITY_CLASSES 8u /* density classes (Section 4 proposes
+                                 adapting bins to the density and running the
+                                 low- and high-density rasterizers at the
+                                 same time): with a sorter depth above 4,
+                                 binning also estimates each bin's depth
+                                 complexity (the bbox pixels of its quads per
+                                 pixel), and one raster launch takes the
+                                 bins above 32 first and runs those at most
+                                 2 with a depth-4 sorter.  Images are
+                                 identical either way; off by default, since
+                                 on the workloads measured here it is slower
+                                 (the estimate costs the count stage, and
+                                 dense bins run together contend where screen
+                                 order mixes them with light ones). */
 
 /* Statistics of the last render call on the context (for a batch, summed over
  * its frames; error_word is the OR of theirs). */

@@ -100,7 +100,8 @@ struct FrameCounters {
     uint32_t error;            // kErr* bits
     uint32_t fb_next;          // next flagged pixel for the exact pass
     uint32_t fe_n;             // entries kept for the exact pass (may exceed fe_cap)
-    uint32_t pad[28];
+    uint32_t n_high;           // bins in high_list
+    uint32_t pad[27];
     StatStripe stripe[kStripes];
 };
 
@@ -171,6 +172,17 @@ struct FrameArgs {
     uint32_t *pairs;        // [pair_cap]
     uint32_t pair_cap;
     uint32_t match_bits;    // bits needed to hold a bin index
+    // density classes (the paper's Section 4 suggests adapting bins to the
+    // density and running low- and high-density rasterizers together): per
+    // bin, the sum over its pairs of the quad bbox's pixels inside the bin,
+    // a depth-complexity estimate d; the scan lists the dense bins (d above
+    // kDenseDepth, ctr->n_high of them, rasterized first) and marks each
+    // bin's class (kSparse: d at most kSparseDepth, rasterized with a
+    // kLowDepth sorter).  Null / 0 when the frame has one class.
+    unsigned long long *bin_px;  // [nbins]
+    uint32_t *high_list;         // [nbins]
+    uint8_t *bin_class;          // [nbins]
+    uint32_t k_low;              // sorter depth of sparse bins (0: one class)
     // raster
     uint32_t half_blocks;     // 1: block lists are sorted per 8x4 half-block
     uint32_t nblk_x, nblk_y;  // 8x8 blocks
@@ -229,6 +241,16 @@ struct FrameMap {
     uint32_t nf;
     uint32_t wg0[kMaxBatch + 1];
 };
+
+// Density classes of a bin by its depth estimate d (the pixels of its pairs'
+// bboxes inside it, per pixel of the bin): dense above kDenseDepth, sparse
+// at most kSparseDepth, mid between.
+enum BinClass : uint8_t { kSparse = 0, kMid = 1, kDense = 2 };
+constexpr uint32_t kDenseDepth = 32;
+constexpr uint32_t kSparseDepth = 2;
+// Sorter depth of sparse bins when the frame's depth is larger.
+constexpr uint32_t kLowDepth = 4;
+
 
 // Kernel launches (lr_kernels.hip).
 hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipStream_t s,

@@ -515,6 +515,12 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
     static_assert(kSetupQPL == 1, "record staging assumes one quad per lane");
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
+    if (a.bin_px) {
+        // the density estimate is summed by the binning count that follows
+        const uint32_t nblk = (a.n + 255) / 256;
+        for (uint32_t b = blk * blockDim.x + threadIdx.x; b < a.nbins; b += nblk * blockDim.x)
+            a.bin_px[b] = 0;
+    }
     __shared__ uint4 s_cov[256 * kCovChunks];
     __shared__ uint4 s_pl[256 * kPlaneChunks];
     uint32_t reasons[kSetupQPL];
@@ -717,8 +723,30 @@ __global__ __launch_bounds__(kScanWaves * 64) void k_bin_scan(Src src)
         run += w < wave ? v : 0u;
         total += v;
     }
-    if (on && wave == 0)
-        a.bin_count[b] = total;
+    if (wave == 0) {
+        if (on)
+            a.bin_count[b] = total;
+        if (a.k_low) {
+            // density class by the depth estimate; dense bins go to the
+            // list the raster takes first (one atomic per workgroup)
+            bool high = false;
+            if (on) {
+                const uint32_t bx = b % a.nbx, by = b / a.nbx;
+                const uint32_t w = min(a.W - (bx << a.bin_shift), 1u << a.bin_shift);
+                const uint32_t h = min(a.H - (by << a.bin_shift), 1u << a.bin_shift);
+                const unsigned long long px = a.bin_px[b], area = (unsigned long long)w * h;
+                high = px > kDenseDepth * area;
+                a.bin_class[b] = high ? kDense : (px > kSparseDepth * area ? kMid : kSparse);
+            }
+            const uint64_t hm = ballot(high);
+            uint32_t base = 0;
+            if (lane == 0 && hm)
+                base = atomicAdd(&a.ctr->n_high, (uint32_t)__popcll(hm));
+            base = lane_value(base, 0);
+            if (high)
+                a.high_list[base + rank_below(hm)] = b;
+        }
+    }
     if (on) {
         if (kept) {
 #pragma unroll
@@ -908,16 +936,31 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 constexpr uint32_t kBin4MaxBins = 8192;  // 4 x 32 KiB of per-wave offsets
 constexpr uint32_t kBin4Waves = 4;
 
+// Pixels of bbox bb inside bin (bx, by): the bin's share of the quad's
+// bbox, summed per bin as a depth-complexity estimate.
+__device__ __forceinline__ uint32_t bin_overlap_px(uint2 bb, uint32_t bx, uint32_t by, uint32_t shift)
+{
+    const int x0 = (int)(bx << shift), y0 = (int)(by << shift), s1 = (1 << shift) - 1;
+    const int w = min((int)(bb.x >> 16), x0 + s1) - max((int)(bb.x & 0xffffu), x0) + 1;
+    const int h = min((int)(bb.y >> 16), y0 + s1) - max((int)(bb.y & 0xffffu), y0) + 1;
+    return (uint32_t)(w * h);
+}
+
 template <class Src>
 __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
 {
-    extern __shared__ uint32_t s_hist[];
+    extern __shared__ uint32_t s_hist[];  // [nbins] counts, then [nbins] overlap pixels when gathered
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
     const uint2 *__restrict__ bbox = a.bbox;
     const uint32_t t = threadIdx.x, u = blk;
-    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64)
+    const bool px = a.bin_px != nullptr;
+    uint32_t *s_px = s_hist + a.nbins;
+    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64) {
         s_hist[b] = 0;
+        if (px)
+            s_px[b] = 0;
+    }
     __syncthreads();
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
     for (uint32_t base = q0; base < q1; base += kBin4Waves * 64 * kBinPrefetch) {
@@ -936,14 +979,19 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
                 for (uint32_t j = 0; j < np; j++) {
                     uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
                     atomicAdd(&s_hist[by * a.nbx + bx], 1u);
+                    if (px)
+                        atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb[k], bx, by, a.bin_shift));
                 }
             }
         }
     }
     __syncthreads();
     uint32_t *row = a.table + (size_t)u * a.nbins;
-    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64)
+    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64) {
         row[b] = s_hist[b];
+        if (px && s_px[b])
+            atomicAdd(&a.bin_px[b], (unsigned long long)s_px[b]);
+    }
 }
 
 template <class Src>
@@ -2050,10 +2098,43 @@ __device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGe
     }
 }
 
+// Phases 2 and 3 of one block whose n entries phase 1 has built, with a
+// K-deep per-pixel sorter, and the block's outputs.
+template <int K, bool DEBUG, bool CUT>
+__device__ __forceinline__ void walk_block(const FrameArgs &a, WaveLds &L, const BlockGeom &g, uint32_t lane,
+                                           uint32_t n, uint32_t ebase, uint32_t sb)
+{
+    PixelSorter<K, DEBUG, CUT> ps;
+    ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
+    if (n <= kFast) {
+        walk_fast<K, DEBUG, CUT>(a, L, n, sb, g, lane, ps);
+    } else {
+        // entries written by other lanes of this wave are read back below
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (n <= kSortCap) {
+            walk_entries<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps);
+        } else {
+            if (lane == 0)
+                atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
+            if (!walk_sliced<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps)) {
+                // no slice fits: the exact path takes the block
+                ps.flagged = true;
+                if (lane == 0)
+                    atomicOr(&a.ctr->error, kErrDense);
+            }
+        }
+    }
+    finish_block<K, DEBUG, CUT>(a, L, g, lane, ps, n, ebase);
+}
+
 // Sorted raster: one workgroup of NW waves per bin, one 8x8 block per wave
-// per round.
+// per round.  With density classes the launch takes the dense bins first
+// (their long workgroups start at once instead of at their place in screen
+// order) and the other bins alongside them, sparse ones with a
+// kLowDepth-deep sorter (the paper's Section 4 proposes adapting to density
+// and running its low- and high-density rasterizers at the same time).
 template <int K, bool DEBUG, class Src, int NW, bool CUT>
-__global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 12 || (K <= 16 && !CUT))) ? 4 : 2) void k_raster(Src src)
+__global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 8 || (K <= 16 && !CUT))) ? 4 : 2) void k_raster(Src src)
 {
     __shared__ BinChunk<NW> C;
     __shared__ WaveLds Lw[NW];
@@ -2064,6 +2145,23 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 12 || (K <= 16 && !CUT)))
     const uint32_t *__restrict__ pairs = a.pairs;
     if (a.ctr->error & kErrPairs)
         return;  // bin lists are incomplete: the frame is reported as failed
+    // with density classes the grid is twice the bins: first the dense bins,
+    // then every other bin in screen order, sparse ones with the shallower
+    // sorter
+    bool low = false;
+    if (a.k_low) {
+        if (bin < a.nbins) {
+            if (bin >= uniform(a.ctr->n_high))
+                return;
+            bin = uniform(a.high_list[bin]);
+        } else {
+            bin -= a.nbins;
+            const uint32_t cls = a.bin_class[bin];
+            if (cls == kDense)
+                return;
+            low = cls == kSparse;
+        }
+    }
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t bpb = 1u << (a.bin_shift - 3), nb = bpb * bpb;
     const uint32_t start = uniform(a.bin_start[bin]), cnt = uniform(a.bin_count[bin]);
@@ -2087,27 +2185,14 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 12 || (K <= 16 && !CUT)))
             sorted_batch<CUT>(a, xyp, L, m, g, lane, ebase, sb, half, n);
         });
         if (g.active) {
-            PixelSorter<K, DEBUG, CUT> ps;
-            ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
-            if (n <= kFast) {
-                walk_fast<K, DEBUG, CUT>(a, L, n, sb, g, lane, ps);
+            if constexpr (K > (int)kLowDepth) {
+                if (low)
+                    walk_block<(int)kLowDepth, DEBUG, CUT>(a, L, g, lane, n, ebase, sb);
+                else
+                    walk_block<K, DEBUG, CUT>(a, L, g, lane, n, ebase, sb);
             } else {
-                // entries written by other lanes of this wave are read back below
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-                if (n <= kSortCap) {
-                    walk_entries<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps);
-                } else {
-                    if (lane == 0)
-                        atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
-                    if (!walk_sliced<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps)) {
-                        // no slice fits: the exact path takes the block
-                        ps.flagged = true;
-                        if (lane == 0)
-                            atomicOr(&a.ctr->error, kErrDense);
-                    }
-                }
+                walk_block<K, DEBUG, CUT>(a, L, g, lane, n, ebase, sb);
             }
-            finish_block<K, DEBUG, CUT>(a, L, g, lane, ps, n, ebase);
         }
     }
 }
@@ -2437,7 +2522,8 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
     if (!bins)
         return hipGetLastError();
     if (a.bin_waves == kBin4Waves)
-        hipLaunchKernelGGL(k_bin_count4<OneFrame>, dim3(a.nunits), dim3(kBin4Waves * 64), a.nbins * 4, s, f);
+        hipLaunchKernelGGL(k_bin_count4<OneFrame>, dim3(a.nunits), dim3(kBin4Waves * 64),
+                           a.nbins * 4 * (a.bin_px ? 2 : 1), s, f);
     else
         hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
@@ -2471,21 +2557,25 @@ bool sorter_depth_supported(int k)
 }
 
 // Raster (one workgroup per bin), then the exact pass.
+// Raster workgroups of a frame: one per bin, twice that with density classes.
+static uint32_t raster_grid(const FrameArgs &a) { return a.k_low ? 2 * a.nbins : a.nbins; }
+
+// Raster (one workgroup per bin), then the exact pass.
 template <int K, bool DEBUG, bool CUT>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     const OneFrame f{a};
     // the parity dump keeps one more id per sorter slot: past depth 4 (and
-    // with the cutoff) its kernels do not fit 16 waves' registers and take 8
-    // (the image is the same)
-    constexpr bool wide_dbg = DEBUG && (K > 4 || CUT);
+    // with the cutoff) its kernels do not fit 16 waves' registers and take 8,
+    // as do cutoff kernels past depth 8 (the image is the same)
+    constexpr bool wide_dbg = (DEBUG && (K > 4 || CUT)) || (CUT && K > 8);
     const uint32_t nw = min(raster_waves_for(a.bin_shift, K), wide_dbg ? 8u : 16u);
     if (nw == 4)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4, CUT>), dim3(a.nbins), dim3(4 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4, CUT>), dim3(raster_grid(a)), dim3(4 * 64), 0, s, f);
     else if (nw == 8)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8, CUT>), dim3(a.nbins), dim3(8 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8, CUT>), dim3(raster_grid(a)), dim3(8 * 64), 0, s, f);
     else if constexpr (K <= 12 && !wide_dbg)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16, CUT>), dim3(a.nbins), dim3(16 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16, CUT>), dim3(raster_grid(a)), dim3(16 * 64), 0, s, f);
     if (ev) {
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
@@ -2607,7 +2697,7 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     if (mu.wg0[nf])
         hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
     if (mu4.wg0[nf])
-        hipLaunchKernelGGL(k_bin_count4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64), max_bins4 * 4, s, mu4);
+        hipLaunchKernelGGL(k_bin_count4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64), max_bins4 * 8, s, mu4);
     const FrameMap mt =
         stage_map(dev, nf, [&](uint32_t f) { return scan_groups(host[f].nbins); });
     hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(kScanWaves * 64), 0, s, mt);
@@ -2618,6 +2708,7 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
                            kBin4Waves * max_bins4 * 4, s, mu4);
     static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
     static const uint32_t kWaveCounts[] = {4, 8, 16};
+    // raster launches, one per (depth, waves, cutoff) present
     for (int K : kDepths) {
         for (uint32_t nw : kWaveCounts) {
             for (uint32_t cut = 0; cut < 2; cut++) {
@@ -2631,7 +2722,7 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
                 if (!any)
                     continue;
                 const FrameMap mr =
-                    stage_map(dev, nf, [&](uint32_t f) { return in_group(f) ? host[f].nbins : 0u; });
+                    stage_map(dev, nf, [&](uint32_t f) { return in_group(f) ? raster_grid(host[f]) : 0u; });
                 if (cut) {
                     switch (K) {
                     case 2: launch_raster_group<2, true>(mr, nw, s); break;

@@ -239,7 +239,7 @@ struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks;
     uint64_t o_cov, o_plane, o_extra, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
-        o_femask, o_feid, o_blkent, o_ebound, total;
+        o_femask, o_feid, o_blkent, o_ebound, o_binpx, o_highlist, o_binclass, total;
     uint32_t fe_cap;
     uint32_t cut;  // transmittance cutoff: entries carry a bound code
 };
@@ -294,6 +294,9 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_table = take((uint64_t)p.nunits * p.nbins * 4);
     p.o_start = take(((uint64_t)p.nbins + 1) * 4);
     p.o_count = take((uint64_t)p.nbins * 4);
+    p.o_binpx = take((uint64_t)p.nbins * 8);
+    p.o_highlist = take((uint64_t)p.nbins * 4);
+    p.o_binclass = take((uint64_t)p.nbins);
     p.o_pairs = take((uint64_t)p.pair_cap * 4);
     p.qcap_blocks = (p.nblk_x * p.nblk_y + lr::kQueues - 1) / lr::kQueues;
     p.o_fb = take((uint64_t)lr::kQueues * p.qcap_blocks * 64 * 4);
@@ -439,6 +442,11 @@ void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *ou
     a.ent_mask = reinterpret_cast<unsigned long long *>(base + plan.o_emask);
     a.ent_id = reinterpret_cast<uint32_t *>(base + plan.o_eid);
     a.ent_bound = plan.cut ? reinterpret_cast<uint32_t *>(base + plan.o_ebound) : nullptr;
+    // density classes (switched on per frame by set_classes)
+    a.bin_px = plan.bin_waves == 4 ? reinterpret_cast<unsigned long long *>(base + plan.o_binpx) : nullptr;
+    a.high_list = reinterpret_cast<uint32_t *>(base + plan.o_highlist);
+    a.bin_class = reinterpret_cast<uint8_t *>(base + plan.o_binclass);
+    a.k_low = 0;
     a.alpha_cut = plan.cut;
     a.fe_mask = reinterpret_cast<unsigned long long *>(base + plan.o_femask);
     a.fe_id = reinterpret_cast<uint32_t *>(base + plan.o_feid);
@@ -454,6 +462,18 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
                char *base, lr::FrameArgs &a)
 {
     fill_frame(ctx->arena + sc.off, sc.n, cam, out, plan, base, ctx->elog, a);
+}
+
+// Density classes of a frame rendered at sorter depth k (0: unsorted), with
+// LR_FLAG_DENSITY_CLASSES: when k is deeper than kLowDepth and the binning
+// can gather its density estimate (the four-wave kernels), the raster takes
+// the dense bins first and the sparse ones at kLowDepth.
+void set_classes(lr_context ctx, uint32_t k, lr::FrameArgs &a)
+{
+    const bool on = (ctx->cfg.flags & LR_FLAG_DENSITY_CLASSES) && a.bin_px && k > lr::kLowDepth;
+    a.k_low = on ? lr::kLowDepth : 0u;
+    if (!on)
+        a.bin_px = nullptr;  // nothing to estimate
 }
 
 // Tags a frame for the error log.
@@ -564,6 +584,7 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
         ctx->ring_head = (ctx->ring_head + 1) % kRing;
         ctx->ring_count = std::min(ctx->ring_count + 1, kRing);
     }
+    set_classes(ctx, unsorted ? 0u : t.k, a);
     hipError_t e = lr::launch_frame(a, (int)t.k, unsorted, s, ev);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "kernel launch");
@@ -740,6 +761,7 @@ lr_status launch_group(lr_context ctx, const lr::FrameArgs *host, const lr::Fram
         key.push_back(host[f].bin_waves);
         key.push_back((uint64_t)ks[f]);
         key.push_back(host[f].alpha_cut);
+        key.push_back(host[f].k_low);
     }
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
@@ -826,6 +848,7 @@ lr_status batch_impl(lr_context ctx, const lr_request *reqs, uint32_t n, hipStre
             host[f].status = r.status;
             tag_frame(ctx, r.scene, pl, host[f]);
             ks[f] = (int)tunes[i0 + f].k;
+            set_classes(ctx, tunes[i0 + f].k, host[f]);
             frames.push_back(FrameRef{base + o + pl.o_ctr, pl.n, (int)(slot - ctx->slots.data())});
             o += (pl.total + 255) & ~uint64_t(255);
         }
@@ -1107,6 +1130,7 @@ lr_status lr_render_noalloc(lr_context ctx, lr_scene scene, const lr_camera *cam
         ctx->ring_head = (ctx->ring_head + 1) % kRing;
         ctx->ring_count = std::min(ctx->ring_count + 1, kRing);
     }
+    set_classes(ctx, t.k, a);
     hipError_t e = lr::launch_frame(a, (int)t.k, 0, s, ev);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "kernel launch");

@@ -441,3 +441,45 @@ def test_c3_sampled_pixels(lr):
         b = ref["ids"][int(ref["offsets"][k]):int(ref["offsets"][k + 1])]
         np.testing.assert_array_equal(a, b)
     assert int(ref["count"].max()) > 200  # the sampled centre is the deep part
+
+
+@pytest.mark.parametrize("b,k,bh", [(16, 8, 8), (32, 12, 4), (64, 16, 8), (16, 4, 8)])
+def test_density_classes_do_not_change_the_image(lr, b, k, bh):
+    """Density classes (dense bins first, sparse ones with a depth-4 sorter,
+    one launch) against one class in screen order: fp32 colour and counts
+    bit-identical, and both against the oracle."""
+    sc = scenes.small(200, 150, 40000, 16, side=(1.0, 20.0), gaussian=True, alpha=(0.05, 0.5))
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    outs = []
+    for classes in (True, False):
+        ctx = lr.Context(arena_bytes=512 << 20, bin_size=b, sorter_depth=k, block_h=bh, density_classes=classes)
+        got = gpu_render(lr, ctx, sc)
+        check_frame(got, ref, f"bin {b} K {k} classes {classes}")
+        outs.append((got["rgba_f32"].cpu().numpy(), got["count"].cpu().numpy()))
+        ctx.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_density_classes_in_a_batch(lr):
+    """Batched frames with density classes (graph replay included) equal the
+    single renders, and the oracle."""
+    import torch
+    frames = [scenes.small(200, 150, 40000, 17, side=(1.0, 20.0), gaussian=True, alpha=(0.05, 0.5)),
+              scenes.small(160, 120, 8000, 18, side=(2.0, 12.0)),
+              scenes.small(256, 256, 60000, 19, side=(1.0, 16.0), gaussian=True, alpha=(0.1, 0.6))]
+    ctx = lr.Context(arena_bytes=1 << 30, density_classes=True)
+    hs = [ctx.upload(s.v, s.rgba) for s in frames]
+    outs = [ctx.new_image(s.width, s.height) for s in frames]
+    reqs = [(h, s.camera, s.width, s.height, o, b, k, 8) for h, s, o, (b, k) in
+            zip(hs, frames, outs, [(16, 8), (32, 12), (32, 8)])]
+    ctx.render_batch(reqs)
+    ctx.render_batch(reqs)
+    for h, s, o, r in zip(hs, frames, outs, reqs):
+        c2 = lr.Context(arena_bytes=256 << 20, bin_size=r[5], sorter_depth=r[6], density_classes=True)
+        single = c2.render(c2.upload(s.v, s.rgba), s.camera, s.width, s.height)
+        assert torch.equal(single, o)
+        c2.close()
+        ref = oracle.render(s.v, s.rgba, s.camera, s.width, s.height, want_order=False)
+        assert np.abs(o.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32)).max() <= 1
+    ctx.close()
