@@ -110,6 +110,16 @@ typedef struct {
                                  dumps then report the blended prefix
                                  (counts, order).  The unsorted baseline
                                  ignores it. */
+#define LR_FLAG_BBOX_BINNING 16u /* bin every quad to every bin its pixel
+                                 bbox meets.  By default a large quad (bbox
+                                 over more than 4 bins of 32 x 32 pixels, the
+                                 small/large split of Stage 1, Phase 1) is
+                                 binned only to the bins its edges do not
+                                 trivially reject (Stage 2, "Triangle
+                                 rasterization": a bin-level scan with a
+                                 trivial-reject test), its bins spread over
+                                 the lanes of a wave.  Images are identical
+                                 either way. */
 #define LR_FLAG_DENSITY_CLASSES 8u /* density classes (Section 4 proposes
                                  adapting bins to the density and running the
                                  low- and high-density rasterizers at the

@@ -69,6 +69,11 @@ constexpr uint32_t kT1Swap = 16u;
 // (eps, eps^2) never lies on the shared diagonal.
 constexpr uint32_t kConvex = 32u;
 
+// The small/large split of Stage 1, Phase 1: a quad whose bbox meets more
+// than kLargeBins bins of 32 x 32 pixels is large (whatever the frame's bin
+// size).
+constexpr uint32_t kLargeBins = 4;
+
 // Snapped vertices (sub-pixel units) of a quad.
 struct alignas(32) QuadXY {
     int32_t X[4];
@@ -183,6 +188,10 @@ struct FrameArgs {
     uint32_t *high_list;         // [nbins]
     uint8_t *bin_class;          // [nbins]
     uint32_t k_low;              // sorter depth of sparse bins (0: one class)
+    // large quads (bbox over more than kLargeBins bins of 32 px) are binned
+    // to the bins their half-planes do not trivially reject, with their
+    // bins spread over a wave's lanes; 1: every quad by its whole bbox
+    uint32_t bbox_binning;
     // raster
     uint32_t half_blocks;     // 1: block lists are sorted per 8x4 half-block
     uint32_t nblk_x, nblk_y;  // 8x8 blocks

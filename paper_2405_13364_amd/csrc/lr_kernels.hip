@@ -625,6 +625,91 @@ __device__ __forceinline__ bool quad_bins(uint2 bb, uint32_t shift, uint32_t &bx
 // together.
 constexpr uint32_t kBinPrefetch = 8;
 
+// Pixels of bbox bb inside bin (bx, by): the bin's share of the quad's
+// bbox, summed per bin as a depth-complexity estimate.
+__device__ __forceinline__ uint32_t bin_overlap_px(uint2 bb, uint32_t bx, uint32_t by, uint32_t shift)
+{
+    const int x0 = (int)(bx << shift), y0 = (int)(by << shift), s1 = (1 << shift) - 1;
+    const int w = min((int)(bb.x >> 16), x0 + s1) - max((int)(bb.x & 0xffffu), x0) + 1;
+    const int h = min((int)(bb.y >> 16), y0 + s1) - max((int)(bb.y & 0xffffu), y0) + 1;
+    return (uint32_t)(w * h);
+}
+
+// ----- large quads (Stage 1, Phase 1 split; Stage 2, "Triangle
+// rasterization": bins of a large primitive found by a bin-level scan with
+// a trivial-reject test)
+
+__device__ __forceinline__ bool quad_is_large(uint2 bb)
+{
+    const uint32_t imin = bb.x & 0xffffu, imax = bb.x >> 16, jmin = bb.y & 0xffffu, jmax = bb.y >> 16;
+    if (imin > imax || jmin > jmax)
+        return false;
+    return ((imax >> 5) - (imin >> 5) + 1) * ((jmax >> 5) - (jmin >> 5) + 1) > kLargeBins;
+}
+
+// Whether bin (bx, by) may hold a covered sample of the quad: the bin is
+// rejected when, for the convex quad or for each of its two triangles, some
+// edge stays below its threshold on every pixel centre of the bin inside
+// the quad's bbox (a linear function peaks at a corner of that rectangle),
+// so no sample there can be covered.  The test is conservative: a kept bin
+// may still hold no sample.  Quads on the fp64 coverage path keep every bin.
+__device__ __forceinline__ bool bin_maybe_covered(const CovRec &r, const ExtraRec &ex, uint32_t bx, uint32_t by,
+                                                  uint32_t shift)
+{
+    if (r.flags & kWide)
+        return true;
+    const int imin = (int)(r.bb_i & 0xffffu), imax = (int)(r.bb_i >> 16);
+    const int jmin = (int)(r.bb_j & 0xffffu), jmax = (int)(r.bb_j >> 16);
+    const int x0 = (int)(bx << shift), y0 = (int)(by << shift), s1 = (1 << shift) - 1;
+    const int di0 = max(x0, imin) - imin, di1 = min(x0 + s1, imax) - imin;
+    const int dj0 = max(y0, jmin) - jmin, dj1 = min(y0 + s1, jmax) - jmin;
+    auto out = [&](int a, int b, int t) { return a * (a >= 0 ? di1 : di0) + b * (b >= 0 ? dj1 : dj0) < t; };
+    const int32_t *h = r.hp;
+    if (r.flags & kConvex)
+        return !(out(h[0], h[1], h[2]) || out(h[3], h[4], h[5]) || out(h[6], h[7], h[8]) ||
+                 out(h[9], h[10], h[11]));
+    const bool t0 = out(h[0], h[1], h[2]) || out(h[3], h[4], h[5]) || out(h[6], h[7], h[8]);
+    const bool t1 = out(h[9], h[10], h[11]) || out(ex.hp[0], ex.hp[1], ex.hp[2]) || out(ex.hp[3], ex.hp[4], ex.hp[5]);
+    return !(t0 && t1);
+}
+
+// A large quad's records for the bin test (wave-uniform loads).
+__device__ __forceinline__ void large_records(const FrameArgs &a, uint32_t q, CovRec &r, ExtraRec &ex)
+{
+    r = a.cov[q];
+    ex = ExtraRec{};
+    if (!(r.flags & (kConvex | kWide)))
+        ex = a.extra[q];
+}
+
+// Counts the kept bins of the wave's large quads (lanes with large set),
+// one quad at a time, its bbox bins spread over the lanes.
+__device__ __forceinline__ void count_large(const FrameArgs &a, bool large, uint32_t q, uint2 bb, uint32_t *s_hist,
+                                            uint32_t *s_px)
+{
+    uint64_t lm = ballot(large);
+    const uint32_t lane = lane_id();
+    while (lm) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(lm);
+        lm &= lm - 1;
+        const uint32_t ql = lane_value(q, l);
+        const uint2 bl = make_uint2(lane_value(bb.x, l), lane_value(bb.y, l));
+        CovRec r;
+        ExtraRec ex;
+        large_records(a, ql, r, ex);
+        uint32_t bx0, by0, bw, np;
+        quad_bins(bl, a.bin_shift, bx0, by0, bw, np);
+        for (uint32_t j = lane; j < np; j += 64) {
+            const uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
+            if (bin_maybe_covered(r, ex, bx, by, a.bin_shift)) {
+                atomicAdd(&s_hist[by * a.nbx + bx], 1u);
+                if (s_px)
+                    atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bl, bx, by, a.bin_shift));
+            }
+        }
+    }
+}
+
 template <class Src>
 __global__ __launch_bounds__(64) void k_bin_count(Src src)
 {
@@ -647,13 +732,15 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
         }
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const bool large = !a.bbox_binning && quad_is_large(bb[k]);
             uint32_t bx0, by0, bw, np;
-            if (quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
+            if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
                 for (uint32_t j = 0; j < np; j++) {
                     uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
                     atomicAdd(&s_hist[by * a.nbx + bx], 1u);
                 }
             }
+            count_large(a, large, base + 64 * k + lane, bb[k], s_hist, nullptr);
         }
     }
     __syncthreads();
@@ -796,12 +883,15 @@ constexpr uint32_t kScatterGroup = 512;
 // each lane then takes the pair of its slot; lanes whose pairs share a bin
 // take consecutive slots in lane order from one LDS atomic on offs[bin], so
 // every bin list stays in ascending quad order.
-__device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
-                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane)
+__device__ __forceinline__ void scatter_small(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
+                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane,
+                                              uint32_t lo_lane, uint32_t hi_lane)
 {
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
     quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
+    if (lane < lo_lane || lane >= hi_lane)
+        np = 0;  // lanes of this run only
     // exclusive prefix of np over the wave: the chunk's pair pre .. pre + np - 1
     // belong to this lane's quad
     const uint32_t incl = wave_incl_scan(np);
@@ -844,6 +934,51 @@ __device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uin
         wave_sync();  // the window's owners are read before the next window marks its own
     }
     wave_sync();
+}
+
+// Places the kept bins of one large quad q (bbox bb), its bbox bins spread
+// over the lanes; every lane holds a different bin, so each takes its slot
+// with one LDS atomic.
+__device__ __forceinline__ void scatter_large(const FrameArgs &a, uint32_t q, uint2 bb, uint32_t *offs, uint32_t lane)
+{
+    CovRec r;
+    ExtraRec ex;
+    large_records(a, q, r, ex);
+    uint32_t bx0, by0, bw, np;
+    quad_bins(bb, a.bin_shift, bx0, by0, bw, np);
+    for (uint32_t j = lane; j < np; j += 64) {
+        const uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
+        if (bin_maybe_covered(r, ex, bx, by, a.bin_shift)) {
+            const uint32_t pos = atomicAdd(&offs[by * a.nbx + bx], 1u);
+            if (pos < a.pair_cap)
+                a.pairs[pos] = q;
+        }
+    }
+    wave_sync();
+}
+
+// The pairs of 64 consecutive quads (lane l holds the bbox of quad base +
+// l), in quad order: runs of small quads through scatter_small, each large
+// quad through scatter_large in its place, so every bin list stays in
+// ascending quad order.
+__device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
+                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane)
+{
+    const uint64_t lg = ballot(!a.bbox_binning && quad_is_large(cur));
+    if (!lg) {
+        scatter_small(a, cur, base, offs, s_pref, s_rect, s_own, lane, 0u, 64u);
+        return;
+    }
+    uint32_t lo = 0;
+    while (lo < 64) {
+        const uint64_t rest = lo ? (lg & (~0ull << lo)) : lg;
+        const uint32_t L = rest ? (uint32_t)__builtin_ctzll(rest) : 64u;
+        if (L > lo)
+            scatter_small(a, cur, base, offs, s_pref, s_rect, s_own, lane, lo, L);
+        if (L < 64)
+            scatter_large(a, base + L, make_uint2(lane_value(cur.x, L), lane_value(cur.y, L)), offs, lane);
+        lo = L + 1;
+    }
 }
 
 // Publishes a frame's bin offsets (bin_start) and total, and logs a
@@ -936,16 +1071,6 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 constexpr uint32_t kBin4MaxBins = 8192;  // 4 x 32 KiB of per-wave offsets
 constexpr uint32_t kBin4Waves = 4;
 
-// Pixels of bbox bb inside bin (bx, by): the bin's share of the quad's
-// bbox, summed per bin as a depth-complexity estimate.
-__device__ __forceinline__ uint32_t bin_overlap_px(uint2 bb, uint32_t bx, uint32_t by, uint32_t shift)
-{
-    const int x0 = (int)(bx << shift), y0 = (int)(by << shift), s1 = (1 << shift) - 1;
-    const int w = min((int)(bb.x >> 16), x0 + s1) - max((int)(bb.x & 0xffffu), x0) + 1;
-    const int h = min((int)(bb.y >> 16), y0 + s1) - max((int)(bb.y & 0xffffu), y0) + 1;
-    return (uint32_t)(w * h);
-}
-
 template <class Src>
 __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
 {
@@ -974,8 +1099,9 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
         }
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const bool large = !a.bbox_binning && quad_is_large(bb[k]);
             uint32_t bx0, by0, bw, np;
-            if (quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
+            if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
                 for (uint32_t j = 0; j < np; j++) {
                     uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
                     atomicAdd(&s_hist[by * a.nbx + bx], 1u);
@@ -983,6 +1109,7 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
                         atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb[k], bx, by, a.bin_shift));
                 }
             }
+            count_large(a, large, base + kBin4Waves * 64 * k + t, bb[k], s_hist, px ? s_px : nullptr);
         }
     }
     __syncthreads();
@@ -1020,13 +1147,17 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
         uint2 bb = make_uint2(0xffffu, 0xffffu);
         if (q < w1)
             bb = bbox[q];
+        // the same pairs as the count kernel: bbox bins of small quads, the
+        // kept bins of large ones
+        const bool large = !a.bbox_binning && quad_is_large(bb);
         uint32_t bx0, by0, bw, np;
-        if (quad_bins(bb, a.bin_shift, bx0, by0, bw, np)) {
+        if (!large && quad_bins(bb, a.bin_shift, bx0, by0, bw, np)) {
             for (uint32_t j = 0; j < np; j++) {
                 uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
                 atomicAdd(&offs[by * a.nbx + bx], 1u);
             }
         }
+        count_large(a, large, q, bb, offs, nullptr);
     }
     __syncthreads();
     // every workgroup takes the exclusive prefix over the bin counts itself

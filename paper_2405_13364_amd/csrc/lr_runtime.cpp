@@ -447,6 +447,7 @@ void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *ou
     a.high_list = reinterpret_cast<uint32_t *>(base + plan.o_highlist);
     a.bin_class = reinterpret_cast<uint8_t *>(base + plan.o_binclass);
     a.k_low = 0;
+    a.bbox_binning = 0;
     a.alpha_cut = plan.cut;
     a.fe_mask = reinterpret_cast<unsigned long long *>(base + plan.o_femask);
     a.fe_id = reinterpret_cast<uint32_t *>(base + plan.o_feid);
@@ -462,6 +463,7 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
                char *base, lr::FrameArgs &a)
 {
     fill_frame(ctx->arena + sc.off, sc.n, cam, out, plan, base, ctx->elog, a);
+    a.bbox_binning = (ctx->cfg.flags & LR_FLAG_BBOX_BINNING) ? 1u : 0u;
 }
 
 // Density classes of a frame rendered at sorter depth k (0: unsorted), with

@@ -27,6 +27,7 @@ LR_FLAG_TIMING = 1
 LR_FLAG_NO_GRAPH = 2
 LR_FLAG_ALPHA_CUTOFF = 4
 LR_FLAG_DENSITY_CLASSES = 8
+LR_FLAG_BBOX_BINNING = 16
 LR_FRAME_ERR_CAPACITY = 1
 LR_FRAME_ERR_DENSE = 4
 
@@ -153,7 +154,7 @@ class Context:
     def __init__(self, arena_bytes: int = 1 << 30, device: int = 0, bin_size: int = 32,
                  sorter_depth: int = 8, timing: bool = False, stream=None, block_h: int = 8,
                  batch_slots: int = 2, graphs: bool = True, tuning=None, alpha_cutoff: bool = False,
-                 density_classes: bool = False):
+                 density_classes: bool = False, bbox_binning: bool = False):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -167,7 +168,8 @@ class Context:
                      block_h=block_h, sorter_depth=sorter_depth,
                      flags=(LR_FLAG_TIMING if timing else 0) | (0 if graphs else LR_FLAG_NO_GRAPH) |
                      (LR_FLAG_ALPHA_CUTOFF if alpha_cutoff else 0) |
-                     (LR_FLAG_DENSITY_CLASSES if density_classes else 0),
+                     (LR_FLAG_DENSITY_CLASSES if density_classes else 0) |
+                     (LR_FLAG_BBOX_BINNING if bbox_binning else 0),
                      hbm_budget_bytes=0, batch_slots=batch_slots)
         self.bin_size, self.sorter_depth, self.block_h = bin_size, sorter_depth, block_h
         h = ctypes.c_void_p()

@@ -72,6 +72,24 @@ def general_quads(W=80, H=60, n=4000, seed=31, extent=(2.0, 12.0), centre=None):
     return scenes.from_quads(quads, W, H, name="general")
 
 
+def thin_large(W=320, H=240, n=150, seed=51):
+    """Long thin fronto-parallel quads (80-300 px by 2-6 px) turned in the
+    screen plane: their bboxes meet many bins their area never reaches."""
+    rng = np.random.default_rng(seed)
+    quads = []
+    for _ in range(n):
+        cx, cy = rng.uniform(0, W), rng.uniform(0, H)
+        L, T = rng.uniform(80.0, 300.0), rng.uniform(2.0, 6.0)
+        th = rng.uniform(0.0, np.pi)
+        u, v = np.array([np.cos(th), np.sin(th)]), np.array([-np.sin(th), np.cos(th)])
+        corners = [tuple(np.array([cx, cy]) + su * L / 2 * u + sv * T / 2 * v)
+                   for su, sv in ((-1, -1), (1, -1), (1, 1), (-1, 1))]
+        rgb = rng.integers(0, 256, 3)
+        rgba = int(scenes.pack_rgba(int(rgb[0]), int(rgb[1]), int(rgb[2]), int(rng.integers(40, 200))))
+        quads.append((scenes.screen_quad(corners, float(rng.uniform(1.0, 10.0)), W, H), rgba))
+    return scenes.from_quads(quads, W, H, name="thin_large")
+
+
 SCENES = {
     "small": lambda: scenes.small(96, 72, 3000, 11, side=(2.0, 24.0)),
     "ragged": lambda: scenes.small(101, 37, 1500, 12, side=(1.0, 30.0)),
@@ -85,6 +103,8 @@ SCENES = {
     "general_dense": lambda: general_quads(64, 48, 900, 32, extent=(2.0, 14.0), centre=(28.0, 20.0)),
     # non-planar quads: fragments whose plane depth is not positive (key 0)
     "twisted": lambda: scenes.twisted(72, 56, 1500, 41),
+    # long thin quads turned in the screen plane: the large-quad binning path
+    "thin_large": lambda: thin_large(),
 }
 
 
@@ -133,8 +153,44 @@ def test_setup_parity(lr, name):
         np.testing.assert_array_equal(got["plane"][vis].view(np.uint64), pl[vis].view(np.uint64))
 
 
+def large_quads(st):
+    """Quads whose bbox meets more than 4 bins of 32 px (Stage 1's
+    small/large split)."""
+    b = st.bbox
+    return ((b[:, 1] // 32 - b[:, 0] // 32 + 1) * (b[:, 3] // 32 - b[:, 2] // 32 + 1) > 4) & (st.cull == 0)
+
+
+def check_bin_lists(counts, ids, sc, st, bin_size):
+    """Small quads: every bin their bbox meets (exactly the oracle's bbox
+    lists).  Large quads: a subset of those bins that holds every bin with a
+    covered sample (the trivial reject only drops bins with none).  Each list
+    in ascending quad order."""
+    W, H = sc.width, sc.height
+    rc, roff, rids = oracle.bins(st, W, H, bin_size)
+    large = large_quads(st)
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, W, H)
+    nbx = (W + bin_size - 1) // bin_size
+    covered = {}
+    off = ref["order_offsets"]
+    for p in range(W * H):
+        q = ref["order_ids"][int(off[p]):int(off[p + 1])]
+        if len(q):
+            b = (p // W // bin_size) * nbx + (p % W) // bin_size
+            covered.setdefault(b, set()).update(int(x) for x in q)
+    got_off = np.zeros(counts.size + 1, np.int64)
+    got_off[1:] = np.cumsum(counts.reshape(-1).astype(np.int64))
+    for b in range(counts.size):
+        g = ids[got_off[b]:got_off[b + 1]]
+        r = rids[int(roff[b]):int(roff[b + 1])]
+        assert np.all(np.diff(g.astype(np.int64)) > 0), f"bin {b} not ascending"
+        assert set(g.tolist()) <= set(r.tolist()), f"bin {b}: quads outside the bbox lists"
+        must = {int(q) for q in r if not large[q]} | covered.get(b, set())
+        assert must <= set(g.tolist()), f"bin {b}: missing {sorted(must - set(g.tolist()))[:5]}"
+    return int(large.sum())
+
+
 @pytest.mark.parametrize("bin_size", [16, 32, 64])
-@pytest.mark.parametrize("name", ["small", "c1", "ragged", "wide"])
+@pytest.mark.parametrize("name", ["small", "c1", "ragged", "wide", "thin_large"])
 def test_bins_parity(lr, name, bin_size):
     sc = SCENES[name]()
     ctx = ctx_for(lr)
@@ -142,9 +198,17 @@ def test_bins_parity(lr, name, bin_size):
     counts, ids = ctx.debug_bins(h, sc.camera, sc.width, sc.height, bin_size)
     ctx.release(h)
     st = oracle.setup(sc.v, sc.camera, sc.width, sc.height)
+    nlarge = check_bin_lists(counts, ids, sc, st, bin_size)
+    if name == "thin_large":
+        assert nlarge > 0 and counts.sum() < oracle.bins(st, sc.width, sc.height, bin_size)[0].sum()
+    # with LR_FLAG_BBOX_BINNING every quad takes its whole bbox: the oracle's lists
+    c2 = lr.Context(arena_bytes=256 << 20, bbox_binning=True)
+    h2 = c2.upload(sc.v, sc.rgba)
+    counts2, ids2 = c2.debug_bins(h2, sc.camera, sc.width, sc.height, bin_size)
+    c2.close()
     rc, roff, rids = oracle.bins(st, sc.width, sc.height, bin_size)
-    np.testing.assert_array_equal(counts, rc)
-    np.testing.assert_array_equal(ids, rids)
+    np.testing.assert_array_equal(counts2, rc)
+    np.testing.assert_array_equal(ids2, rids)
 
 
 @pytest.mark.parametrize("name", sorted(SCENES))
@@ -483,3 +547,23 @@ def test_density_classes_in_a_batch(lr):
         ref = oracle.render(s.v, s.rgba, s.camera, s.width, s.height, want_order=False)
         assert np.abs(o.cpu().numpy().astype(np.int32) - ref["rgba8"].astype(np.int32)).max() <= 1
     ctx.close()
+
+
+@pytest.mark.parametrize("b", [16, 32, 64])
+def test_large_quad_binning_keeps_the_image(lr, b):
+    """The trivial reject of large quads' bins drops bin pairs but no
+    fragment: the same image, counts and order as bbox binning, and the
+    oracle's."""
+    sc = thin_large(480, 360, 400, 52)
+    ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height)
+    res = {}
+    for bbox in (False, True):
+        ctx = lr.Context(arena_bytes=512 << 20, bin_size=b, sorter_depth=8, bbox_binning=bbox)
+        got = gpu_render(lr, ctx, sc)
+        check_frame(got, ref, f"bin {b} bbox {bbox}")
+        h = ctx.upload(sc.v, sc.rgba)
+        ctx.render(h, sc.camera, sc.width, sc.height)
+        res[bbox] = (ctx.stats()["bin_pairs"], got["rgba_f32"].cpu().numpy())
+        ctx.close()
+    assert res[False][0] < res[True][0]
+    np.testing.assert_array_equal(res[False][1], res[True][1])
