@@ -292,6 +292,62 @@ def serving_leg(torch, lucidraster, scenes, rules, n_scenes, n_req, log):
     return res
 
 
+def variant_rows(torch, lucidraster, sc, tune, variants, steps, warmup, arena):
+    """Frame time and statistics of one frame under several context options
+    (same tuning), each timed back to back like the headline."""
+    b, k, bh = tune
+    rows = {}
+    for label, opts in variants.items():
+        ctx = lucidraster.Context(arena_bytes=arena, bin_size=b, sorter_depth=k, block_h=bh, **opts)
+        h = ctx.upload(sc.v, sc.rgba)
+        out = ctx.new_image(sc.width, sc.height)
+        ctx.render(h, sc.camera, sc.width, sc.height, out=out)
+        st = ctx.stats()
+        ms = time_steps(torch, lambda: ctx.render(h, sc.camera, sc.width, sc.height, out=out, check=False),
+                        steps, warmup) / steps
+        ctx.sync()
+        rows[label] = {"ms_per_frame": round(ms, 5), "frames_per_s": round(1000.0 / ms, 2),
+                       "bin_pairs": int(st["bin_pairs"]), "fragments_processed": int(st["fragments"]),
+                       "flagged_pixels": int(st["flagged_pixels"]), "image": out.cpu()}
+        ctx.close()
+    ref = next(iter(rows.values()))["image"]
+    for row in rows.values():
+        row["max_lsb_vs_first"] = int((row.pop("image").to(torch.int32) - ref.to(torch.int32)).abs().max().item())
+    return rows
+
+
+def large_quads_leg(torch, lucidraster, autotune, rules, steps, warmup, arena, log):
+    """The large-primitive path: the 1280x720 frame plus 4,000 long thin
+    quads (2% of the quads, 300-700 px by 3-8 px, turned in the screen plane),
+    binned by their kept bins vs by their whole bbox (LR_FLAG_BBOX_BINNING)."""
+    from paper_2405_13364_amd import scenes
+    sc = scenes.with_long_quads(scenes.scene("c2"), 4000, 7)
+    tune = tuple(autotune.resolve(rules, sc.width, sc.height, sc.n))
+    rows = variant_rows(torch, lucidraster, sc, tune, {"large_path": {}, "bbox_binning": {"bbox_binning": True}},
+                        steps, warmup, arena)
+    res = {"workload": "1280x720: the 200k-quad frame plus 4,000 quads of 300-700 x 3-8 px turned in the screen "
+                       "plane (seed 7)", "tuning": f"bin {tune[0]}, K {tune[1]}, 8x{tune[2]}", **rows,
+           "speedup": round(rows["bbox_binning"]["ms_per_frame"] / rows["large_path"]["ms_per_frame"], 3)}
+    log(f"large quads: {rows['large_path']['ms_per_frame']:.4f} ms vs bbox binning "
+        f"{rows['bbox_binning']['ms_per_frame']:.4f} ms")
+    return res
+
+
+def classes_leg(torch, lucidraster, steps, warmup, arena, log):
+    """Density classes (LR_FLAG_DENSITY_CLASSES, off by default) on the
+    1920x1080 cloud at bin 16 and bin 32, sorter depth 8."""
+    from paper_2405_13364_amd import scenes
+    sc = scenes.scene("c3")
+    res = {"workload": f"c3: {WORKLOADS['c3']}"}
+    for tune in ((16, 8, 8), (32, 8, 8)):
+        rows = variant_rows(torch, lucidraster, sc, tune, {"one_class": {}, "classes": {"density_classes": True}},
+                            steps, warmup, arena)
+        res[f"bin {tune[0]}, K {tune[1]}, 8x{tune[2]}"] = rows
+        log(f"density classes at bin {tune[0]}: {rows['classes']['ms_per_frame']:.4f} ms vs one class "
+            f"{rows['one_class']['ms_per_frame']:.4f} ms")
+    return res
+
+
 def cutoff_leg(torch, lucidraster, autotune, rules, steps, warmup, arena, log):
     """The transmittance cutoff (LR_FLAG_ALPHA_CUTOFF) against the exact
     blend, at the rule-table tuning: the 1920x1080 cloud (alpha U[0.05, 0.5])
@@ -436,6 +492,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-frame mixed batch")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving loop")
     ap.add_argument("--no-cutoff", action="store_true", help="skip the transmittance-cutoff leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the large-quad binning and density-class comparisons")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--serve-scenes", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -526,6 +584,10 @@ def main():
     if not args.no_cutoff:
         log("transmittance cutoff leg")
         res["alpha_cutoff"] = cutoff_leg(torch, lucidraster, autotune, rules, args.steps, args.warmup, arena, log)
+    if not args.no_variants:
+        log("large-quad binning and density classes")
+        res["large_quads"] = large_quads_leg(torch, lucidraster, autotune, rules, args.steps, args.warmup, arena, log)
+        res["density_classes"] = classes_leg(torch, lucidraster, args.steps, args.warmup, arena, log)
     if not args.no_batch:
         log("64-frame mixed batch")
         res["batch"] = mixed_batch_leg(torch, lucidraster, scenes, rules, args.batch_reps, log)

@@ -117,9 +117,15 @@ typedef struct {
                                  binned only to the bins its edges do not
                                  trivially reject (Stage 2, "Triangle
                                  rasterization": a bin-level scan with a
-                                 trivial-reject test), its bins spread over
-                                 the lanes of a wave.  Images are identical
-                                 either way. */
+                                 trivial-reject test).  Setup lists the large
+                                 quads and every binning workgroup takes a
+                                 share of the list after its own small quads,
+                                 with each large quad's bins spread over the
+                                 lanes of a wave; a bin list then holds its
+                                 small quads in ascending order and its large
+                                 quads in no set order (the unsorted baseline,
+                                 which blends in quad order, always bins by
+                                 bbox).  Images are identical either way. */
 #define LR_FLAG_DENSITY_CLASSES 8u /* density classes (Section 4 proposes
                                  adapting bins to the density and running the
                                  low- and high-density rasterizers at the

@@ -106,7 +106,8 @@ struct FrameCounters {
     uint32_t fb_next;          // next flagged pixel for the exact pass
     uint32_t fe_n;             // entries kept for the exact pass (may exceed fe_cap)
     uint32_t n_high;           // bins in high_list
-    uint32_t pad[27];
+    uint32_t n_large;          // quads in large_list
+    uint32_t pad[26];
     StatStripe stripe[kStripes];
 };
 
@@ -192,6 +193,9 @@ struct FrameArgs {
     // to the bins their half-planes do not trivially reject, with their
     // bins spread over a wave's lanes; 1: every quad by its whole bbox
     uint32_t bbox_binning;
+    // the frame's large quads, listed by setup (ctr->n_large of them, in no
+    // particular order); every binning workgroup takes a strided share
+    uint32_t *large_list;    // [n]
     // raster
     uint32_t half_blocks;     // 1: block lists are sorted per 8x4 half-block
     uint32_t nblk_x, nblk_y;  // 8x8 blocks

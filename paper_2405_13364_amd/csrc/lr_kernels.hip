@@ -241,6 +241,16 @@ __device__ __forceinline__ const FrameArgs *frame_of(const FrameMap &m, uint32_t
     return m.tab + lo;
 }
 
+// The small/large split of Stage 1, Phase 1: a quad whose pixel bbox meets
+// more than kLargeBins bins of 32 x 32 pixels is large.
+__device__ __forceinline__ bool quad_is_large(uint2 bb)
+{
+    const uint32_t imin = bb.x & 0xffffu, imax = bb.x >> 16, jmin = bb.y & 0xffffu, jmax = bb.y >> 16;
+    if (imin > imax || jmin > jmax)
+        return false;
+    return ((imax >> 5) - (imin >> 5) + 1) * ((jmax >> 5) - (jmin >> 5) + 1) > kLargeBins;
+}
+
 // ------------------------------------------------------------- frame begin
 
 template <class Src>
@@ -524,11 +534,14 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
     __shared__ uint4 s_cov[256 * kCovChunks];
     __shared__ uint4 s_pl[256 * kPlaneChunks];
     uint32_t reasons[kSetupQPL];
+    uint2 my_bb = make_uint2(0xffffu, 0xffffu);  // the lane's pixel bbox (visible quads)
     {
         const uint32_t t = threadIdx.x;
         const uint32_t q = blk * 256 + t;
         QuadSetup r;
         reasons[0] = q < a.n ? setup_quad(a, q, r) : 0xffu;
+        if (reasons[0] == VISIBLE)
+            my_bb = make_uint2(r.bb_i, r.bb_j);
         uint4 cc[kCovChunks], pc[kPlaneChunks];
         if (reasons[0] == VISIBLE) {
             cc[0] = make_uint4(r.hp[0], r.hp[1], r.hp[2], r.hp[3]);
@@ -584,6 +597,18 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
         }
     }
     const uint32_t lane = lane_id();
+    if (!a.bbox_binning) {
+        // the frame's list of large quads (binned by every binning workgroup)
+        const uint32_t q = blk * 256 + threadIdx.x;
+        const bool large = reasons[0] == VISIBLE && quad_is_large(my_bb);
+        const uint64_t lm = ballot(large);
+        uint32_t base = 0;
+        if (lane == 0 && lm)
+            base = atomicAdd(&a.ctr->n_large, (uint32_t)__popcll(lm));
+        base = lane_value(base, 0);
+        if (large)
+            a.large_list[base + rank_below(lm)] = q;
+    }
     for (uint32_t r = 0; r < 6; r++) {
         uint32_t c = 0;
 #pragma unroll
@@ -639,13 +664,6 @@ __device__ __forceinline__ uint32_t bin_overlap_px(uint2 bb, uint32_t bx, uint32
 // rasterization": bins of a large primitive found by a bin-level scan with
 // a trivial-reject test)
 
-__device__ __forceinline__ bool quad_is_large(uint2 bb)
-{
-    const uint32_t imin = bb.x & 0xffffu, imax = bb.x >> 16, jmin = bb.y & 0xffffu, jmax = bb.y >> 16;
-    if (imin > imax || jmin > jmax)
-        return false;
-    return ((imax >> 5) - (imin >> 5) + 1) * ((jmax >> 5) - (jmin >> 5) + 1) > kLargeBins;
-}
 
 // Whether bin (bx, by) may hold a covered sample of the quad: the bin is
 // rejected when, for the convex quad or for each of its two triangles, some
@@ -682,32 +700,38 @@ __device__ __forceinline__ void large_records(const FrameArgs &a, uint32_t q, Co
         ex = a.extra[q];
 }
 
-// Counts the kept bins of the wave's large quads (lanes with large set),
-// one quad at a time, its bbox bins spread over the lanes.
-__device__ __forceinline__ void count_large(const FrameArgs &a, bool large, uint32_t q, uint2 bb, uint32_t *s_hist,
-                                            uint32_t *s_px)
+// Counts the kept bins of one large quad q (wave-uniform), its bbox bins
+// spread over the lanes.
+__device__ __forceinline__ void count_one_large(const FrameArgs &a, uint32_t q, uint32_t *s_hist, uint32_t *s_px)
 {
-    uint64_t lm = ballot(large);
     const uint32_t lane = lane_id();
-    while (lm) {
-        const uint32_t l = (uint32_t)__builtin_ctzll(lm);
-        lm &= lm - 1;
-        const uint32_t ql = lane_value(q, l);
-        const uint2 bl = make_uint2(lane_value(bb.x, l), lane_value(bb.y, l));
-        CovRec r;
-        ExtraRec ex;
-        large_records(a, ql, r, ex);
-        uint32_t bx0, by0, bw, np;
-        quad_bins(bl, a.bin_shift, bx0, by0, bw, np);
-        for (uint32_t j = lane; j < np; j += 64) {
-            const uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
-            if (bin_maybe_covered(r, ex, bx, by, a.bin_shift)) {
-                atomicAdd(&s_hist[by * a.nbx + bx], 1u);
-                if (s_px)
-                    atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bl, bx, by, a.bin_shift));
-            }
+    const uint2 bb = a.bbox[q];
+    CovRec r;
+    ExtraRec ex;
+    large_records(a, q, r, ex);
+    uint32_t bx0, by0, bw, np;
+    quad_bins(bb, a.bin_shift, bx0, by0, bw, np);
+    for (uint32_t j = lane; j < np; j += 64) {
+        const uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
+        if (bin_maybe_covered(r, ex, bx, by, a.bin_shift)) {
+            atomicAdd(&s_hist[by * a.nbx + bx], 1u);
+            if (s_px)
+                atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb, bx, by, a.bin_shift));
         }
     }
+}
+
+// Calls f(q) for the large quads that wave w (of nw) of binning unit u
+// takes: list entries u + nunits * (w + nw * m), so they spread over every
+// unit whatever their indices (the count and the scatter take the same).
+template <typename F>
+__device__ __forceinline__ void for_large_share(const FrameArgs &a, uint32_t u, uint32_t w, uint32_t nw, F &&f)
+{
+    if (a.bbox_binning)
+        return;
+    const uint32_t nl = uniform(a.ctr->n_large);
+    for (uint32_t i = u + a.nunits * w; i < nl; i += a.nunits * nw)
+        f(uniform(a.large_list[i]));
 }
 
 template <class Src>
@@ -732,7 +756,7 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
         }
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
-            const bool large = !a.bbox_binning && quad_is_large(bb[k]);
+            const bool large = !a.bbox_binning && quad_is_large(bb[k]);  // binned from the large list
             uint32_t bx0, by0, bw, np;
             if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
                 for (uint32_t j = 0; j < np; j++) {
@@ -740,9 +764,9 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
                     atomicAdd(&s_hist[by * a.nbx + bx], 1u);
                 }
             }
-            count_large(a, large, base + 64 * k + lane, bb[k], s_hist, nullptr);
         }
     }
+    for_large_share(a, u, 0, 1, [&](uint32_t q) { count_one_large(a, q, s_hist, nullptr); });
     __syncthreads();
     uint32_t *row = a.table + (size_t)u * a.nbins;
     for (uint32_t b = lane; b < a.nbins; b += 64)
@@ -958,27 +982,12 @@ __device__ __forceinline__ void scatter_large(const FrameArgs &a, uint32_t q, ui
 }
 
 // The pairs of 64 consecutive quads (lane l holds the bbox of quad base +
-// l), in quad order: runs of small quads through scatter_small, each large
-// quad through scatter_large in its place, so every bin list stays in
-// ascending quad order.
+// l); large quads are left to the large list.
 __device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
                                               uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane)
 {
-    const uint64_t lg = ballot(!a.bbox_binning && quad_is_large(cur));
-    if (!lg) {
-        scatter_small(a, cur, base, offs, s_pref, s_rect, s_own, lane, 0u, 64u);
-        return;
-    }
-    uint32_t lo = 0;
-    while (lo < 64) {
-        const uint64_t rest = lo ? (lg & (~0ull << lo)) : lg;
-        const uint32_t L = rest ? (uint32_t)__builtin_ctzll(rest) : 64u;
-        if (L > lo)
-            scatter_small(a, cur, base, offs, s_pref, s_rect, s_own, lane, lo, L);
-        if (L < 64)
-            scatter_large(a, base + L, make_uint2(lane_value(cur.x, L), lane_value(cur.y, L)), offs, lane);
-        lo = L + 1;
-    }
+    const bool large = !a.bbox_binning && quad_is_large(cur);
+    scatter_small(a, large ? make_uint2(0xffffu, 0xffffu) : cur, base, offs, s_pref, s_rect, s_own, lane, 0u, 64u);
 }
 
 // Publishes a frame's bin offsets (bin_start) and total, and logs a
@@ -1058,6 +1067,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
         scatter_chunk(a, s_bb[(base - q0) % kScatterGroup + lane], base, s_off, s_pref, s_rect, s_own, lane);
         wave_sync();  // one wave per workgroup
     }
+    for_large_share(a, u, 0, 1, [&](uint32_t q) { scatter_large(a, q, bbox[q], s_off, lane); });
 }
 
 
@@ -1099,7 +1109,7 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
         }
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
-            const bool large = !a.bbox_binning && quad_is_large(bb[k]);
+            const bool large = !a.bbox_binning && quad_is_large(bb[k]);  // binned from the large list
             uint32_t bx0, by0, bw, np;
             if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
                 for (uint32_t j = 0; j < np; j++) {
@@ -1109,9 +1119,9 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
                         atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb[k], bx, by, a.bin_shift));
                 }
             }
-            count_large(a, large, base + kBin4Waves * 64 * k + t, bb[k], s_hist, px ? s_px : nullptr);
         }
     }
+    for_large_share(a, u, t >> 6, kBin4Waves, [&](uint32_t q) { count_one_large(a, q, s_hist, px ? s_px : nullptr); });
     __syncthreads();
     uint32_t *row = a.table + (size_t)u * a.nbins;
     for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64) {
@@ -1147,8 +1157,8 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
         uint2 bb = make_uint2(0xffffu, 0xffffu);
         if (q < w1)
             bb = bbox[q];
-        // the same pairs as the count kernel: bbox bins of small quads, the
-        // kept bins of large ones
+        // the same pairs as the count kernel: bbox bins of the small quads,
+        // then the kept bins of this wave's share of the large list
         const bool large = !a.bbox_binning && quad_is_large(bb);
         uint32_t bx0, by0, bw, np;
         if (!large && quad_bins(bb, a.bin_shift, bx0, by0, bw, np)) {
@@ -1157,8 +1167,8 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
                 atomicAdd(&offs[by * a.nbx + bx], 1u);
             }
         }
-        count_large(a, large, q, bb, offs, nullptr);
     }
+    for_large_share(a, u, wave, kBin4Waves, [&](uint32_t q) { count_one_large(a, q, offs, nullptr); });
     __syncthreads();
     // every workgroup takes the exclusive prefix over the bin counts itself
     // (the first one also publishes it); thread t owns a contiguous run of bins
@@ -1218,6 +1228,7 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
             bb = bbox[q];
         scatter_chunk(a, bb, base, offs, s_pref[wave], s_rect[wave], s_own[wave], lane);
     }
+    for_large_share(a, u, wave, kBin4Waves, [&](uint32_t q) { scatter_large(a, q, bbox[q], offs, lane); });
 }
 
 // ------------------------------------------------------------------ raster

@@ -239,7 +239,7 @@ struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks;
     uint64_t o_cov, o_plane, o_extra, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
-        o_femask, o_feid, o_blkent, o_ebound, o_binpx, o_highlist, o_binclass, total;
+        o_femask, o_feid, o_blkent, o_ebound, o_binpx, o_highlist, o_binclass, o_large, total;
     uint32_t fe_cap;
     uint32_t cut;  // transmittance cutoff: entries carry a bound code
 };
@@ -291,6 +291,7 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_xy = take((uint64_t)n * sizeof(lr::QuadXY));
     p.o_bbox = take((uint64_t)n * 8);
     p.o_cull = take((uint64_t)n);
+    p.o_large = take((uint64_t)n * 4);
     p.o_table = take((uint64_t)p.nunits * p.nbins * 4);
     p.o_start = take(((uint64_t)p.nbins + 1) * 4);
     p.o_count = take((uint64_t)p.nbins * 4);
@@ -448,6 +449,7 @@ void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *ou
     a.bin_class = reinterpret_cast<uint8_t *>(base + plan.o_binclass);
     a.k_low = 0;
     a.bbox_binning = 0;
+    a.large_list = reinterpret_cast<uint32_t *>(base + plan.o_large);
     a.alpha_cut = plan.cut;
     a.fe_mask = reinterpret_cast<unsigned long long *>(base + plan.o_femask);
     a.fe_id = reinterpret_cast<uint32_t *>(base + plan.o_feid);
@@ -587,6 +589,8 @@ lr_status render_impl(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
         ctx->ring_count = std::min(ctx->ring_count + 1, kRing);
     }
     set_classes(ctx, unsorted ? 0u : t.k, a);
+    if (unsorted)
+        a.bbox_binning = 1;  // the unsorted blend needs every bin list in quad order
     hipError_t e = lr::launch_frame(a, (int)t.k, unsorted, s, ev);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "kernel launch");

@@ -248,3 +248,33 @@ def twisted(width: int, height: int, n: int, seed: int, extent=(2.0, 10.0),
         rgba = int(pack_rgba(int(rgb[0]), int(rgb[1]), int(rgb[2]), int(rng.integers(20, 236))))
         quads.append((screen_quad(corners, zs, width, height), rgba))
     return from_quads(quads, width, height, name=f"twisted{width}x{height}n{n}s{seed}")
+
+
+def with_long_quads(base: Scene, n: int, seed: int, length=(300.0, 700.0), width=(3.0, 8.0),
+                    z=(1.0, 50.0), alpha=(0.1, 0.9)) -> Scene:
+    """The base scene plus n long thin fronto-parallel quads turned in the
+    screen plane at uniform angles (drawn vectorised: centre pair, length,
+    width, angle, depth, RGB, alpha).  Their bboxes span many bins that their
+    area never reaches: the workload of the large-primitive binning path."""
+    rng = np.random.default_rng(seed)
+    W, H = base.width, base.height
+    cxy = rng.uniform(0.0, 1.0, (n, 2)) * np.array([W, H])
+    L = rng.uniform(*length, n)
+    T = rng.uniform(*width, n)
+    th = rng.uniform(0.0, math.pi, n)
+    zz = rng.uniform(*z, n)
+    rgb = rng.integers(0, 256, (n, 3))
+    a8 = np.rint(255.0 * rng.uniform(*alpha, n)).astype(np.uint32)
+    u = np.stack([np.cos(th), np.sin(th)], 1)
+    v = np.stack([-np.sin(th), np.cos(th)], 1)
+    f = focal_pixels(H, base.camera.fov_y)
+    quads = np.zeros((n, 4, 3), np.float64)
+    for k, (su, sv) in enumerate(((-1, -1), (1, -1), (1, 1), (-1, 1))):
+        p = cxy + (su * L / 2)[:, None] * u + (sv * T / 2)[:, None] * v
+        quads[:, k, 0] = (p[:, 0] - 0.5 * W) * zz / f
+        quads[:, k, 1] = -(p[:, 1] - 0.5 * H) * zz / f
+        quads[:, k, 2] = zz
+    rgba = pack_rgba(rgb[:, 0], rgb[:, 1], rgb[:, 2], a8)
+    return Scene(v=np.concatenate([base.v, quads.astype(np.float32)]),
+                 rgba=np.concatenate([base.rgba, rgba.astype(np.uint32)]),
+                 width=W, height=H, camera=base.camera, name=f"{base.name}+{n}long")

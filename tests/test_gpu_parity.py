@@ -161,10 +161,10 @@ def large_quads(st):
 
 
 def check_bin_lists(counts, ids, sc, st, bin_size):
-    """Small quads: every bin their bbox meets (exactly the oracle's bbox
-    lists).  Large quads: a subset of those bins that holds every bin with a
-    covered sample (the trivial reject only drops bins with none).  Each list
-    in ascending quad order."""
+    """Small quads: every bin their bbox meets (the oracle's bbox lists), in
+    ascending order within each list.  Large quads: a subset of those bins
+    that holds every bin with a covered sample (the trivial reject only
+    drops bins with none), anywhere in the list, once."""
     W, H = sc.width, sc.height
     rc, roff, rids = oracle.bins(st, W, H, bin_size)
     large = large_quads(st)
@@ -182,7 +182,9 @@ def check_bin_lists(counts, ids, sc, st, bin_size):
     for b in range(counts.size):
         g = ids[got_off[b]:got_off[b + 1]]
         r = rids[int(roff[b]):int(roff[b + 1])]
-        assert np.all(np.diff(g.astype(np.int64)) > 0), f"bin {b} not ascending"
+        small = np.array([q for q in g if not large[q]], np.int64)
+        assert np.all(np.diff(small) > 0), f"bin {b}: small quads not ascending"
+        assert len(set(g.tolist())) == len(g), f"bin {b}: a quad listed twice"
         assert set(g.tolist()) <= set(r.tolist()), f"bin {b}: quads outside the bbox lists"
         must = {int(q) for q in r if not large[q]} | covered.get(b, set())
         assert must <= set(g.tolist()), f"bin {b}: missing {sorted(must - set(g.tolist()))[:5]}"
