@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "liblroracle.so")
 # catch it (tests/test_oracle_mutations.py).
 _LIB_OVERRIDE = os.environ.get("LR_ORACLE_LIB")
 
-CULL_NAMES = ["visible", "near", "guard", "degenerate", "no_sample", "edge_on"]
+CULL_NAMES = ["visible", "near", "guard", "degenerate", "no_sample", "edge_on", "backface"]
 
 
 def build(force: bool = True) -> str:
@@ -58,7 +58,7 @@ def _load():
         lib.lro_focal.argtypes = [ctypes.c_uint32, ctypes.c_float]
         lib.lro_setup.restype = None
         lib.lro_setup.argtypes = [ctypes.c_uint32, P, ctypes.POINTER(_Cam), ctypes.c_uint32,
-                                  ctypes.c_uint32, ctypes.c_double, P, P, P, P, P, P, P]
+                                  ctypes.c_uint32, ctypes.c_double, P, P, P, P, P, P, P, ctypes.c_int]
         lib.lro_render.restype = ctypes.c_int64
         lib.lro_render.argtypes = [ctypes.c_uint32, P, P, P, P, P, P, P, P, ctypes.c_uint32,
                                    ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, ctypes.c_uint32]
@@ -124,7 +124,9 @@ class Setup:
         return {name: int(bc[k]) for k, name in enumerate(CULL_NAMES)}
 
 
-def setup(v: np.ndarray, camera, W: int, H: int) -> Setup:
+def setup(v: np.ndarray, camera, W: int, H: int, cull_backfaces: bool = False) -> Setup:
+    """Per-quad setup; with cull_backfaces, quads winding clockwise on the
+    display are culled (reason "backface")."""
     lib = _load()
     v = np.ascontiguousarray(v, np.float32).reshape(-1, 4, 3)
     n = v.shape[0]
@@ -133,7 +135,7 @@ def setup(v: np.ndarray, camera, W: int, H: int) -> Setup:
     s.f = lib.lro_focal(H, cam.fov_y)
     if n:
         lib.lro_setup(n, _p(v), ctypes.byref(cam), W, H, s.f, _p(s.X), _p(s.Y), _p(s.bbox),
-                      _p(s.A), _p(s.B), _p(s.C0), _p(s.cull))
+                      _p(s.A), _p(s.B), _p(s.C0), _p(s.cull), int(cull_backfaces))
     return s
 
 
@@ -158,7 +160,8 @@ def _mode(unsorted: bool, cutoff: bool) -> int:
 
 def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bool = False,
            want_order: bool = True, st: Optional[Setup] = None,
-           threads: Optional[int] = None, cutoff: bool = False) -> Dict[str, np.ndarray]:
+           threads: Optional[int] = None, cutoff: bool = False,
+           cull_backfaces: bool = False) -> Dict[str, np.ndarray]:
     """Whole-frame reference render.  Returns rgba_f64 [H,W,4], rgba8 [H,W,4],
     count [H,W], order_offsets [W*H+1], order_ids [total], setup, and the
     number of worker threads used (row bands; the result does not depend on
@@ -167,7 +170,7 @@ def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bo
     those of the blended prefixes ("covering" keeps the full total)."""
     lib = _load()
     mode = _mode(unsorted, cutoff)
-    st = st or setup(v, camera, W, H)
+    st = st or setup(v, camera, W, H, cull_backfaces)
     threads = default_threads() if threads is None else max(1, int(threads))
     rgba = np.ascontiguousarray(rgba, np.uint32)
     npix = W * H
@@ -211,13 +214,14 @@ def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bo
 
 def pixels(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, pix: np.ndarray,
            unsorted: bool = False, want_ids: bool = True,
-           st: Optional[Setup] = None, cutoff: bool = False) -> Dict[str, np.ndarray]:
+           st: Optional[Setup] = None, cutoff: bool = False,
+           cull_backfaces: bool = False) -> Dict[str, np.ndarray]:
     """Reference result for selected pixels (pix = j*W + i), each computed by
     testing every quad.  Returns rgba_f64 [k,4], count [k], offsets, ids
     (with cutoff: those of the blended prefixes)."""
     lib = _load()
     mode = _mode(unsorted, cutoff)
-    st = st or setup(v, camera, W, H)
+    st = st or setup(v, camera, W, H, cull_backfaces)
     rgba = np.ascontiguousarray(rgba, np.uint32)
     pix = np.ascontiguousarray(pix, np.uint32)
     k = pix.shape[0]

@@ -68,6 +68,7 @@
 #define LRO_DEGENERATE 3
 #define LRO_NO_SAMPLE 4
 #define LRO_EDGE_ON 5
+#define LRO_BACKFACE 6
 
 typedef struct {
     float pos[3];
@@ -127,12 +128,19 @@ static int64_t floordiv256(int64_t a) { return a >= 0 ? a / 256 : -((-a + 255) /
  * Per-quad setup.  v: float[n][4][3] world vertices.  Outputs per quad:
  * X, Y int32[n][4] snapped vertices; bbox int32[n][4] = (imin, imax, jmin,
  * jmax); A, B, C0 double[n]; cull uint8[n] (0 = visible, else the first
- * failing test in the order near, guard, degenerate, no-sample, edge-on).
- * Fields of culled quads are left as far as they were computed.
+ * failing test in the order near, guard, degenerate, no-sample, edge-on,
+ * back-facing).  Fields of culled quads are left as far as they were
+ * computed.
+ *
+ * Back-face culling (cull_back != 0; Stage 1 culls primitives facing away
+ * from the camera): dd = n . m, with n the cross product of the diagonals
+ * and m the vertex centroid in camera space, is positive when the vertices
+ * wind counter-clockwise on the display (screen y down), as front faces do
+ * in OpenGL; a quad with dd < 0 is back-facing.
  */
 void lro_setup(uint32_t n, const float *v, const lro_camera *cam, uint32_t W, uint32_t H, double f,
                int32_t *X, int32_t *Y, int32_t *bbox, double *A, double *B, double *C0,
-               uint8_t *cull)
+               uint8_t *cull, int cull_back)
 {
     const double cx = 0.5 * (double)W, cy = 0.5 * (double)H;
     double R[9], P[3];
@@ -242,6 +250,10 @@ void lro_setup(uint32_t n, const float *v, const lro_camera *cam, uint32_t W, ui
             continue;
         }
         A[q] = a; B[q] = b; C0[q] = c0;
+        if (cull_back && dd < 0.0) {
+            cull[q] = LRO_BACKFACE;
+            continue;
+        }
         cull[q] = LRO_VISIBLE;
     }
 }

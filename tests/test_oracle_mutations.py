@@ -32,12 +32,14 @@ MUTANTS = {
     "cutoff_counts_before_blending": ("        k++;\n        if (T32 < LRO_CUT_T)\n            break;",
                                       "        if (T32 < LRO_CUT_T)\n            break;\n        k++;"),
     "cutoff_threshold_too_high": ("#define LRO_CUT_T (1.0f / 1048576.0f)", "#define LRO_CUT_T (1.0f / 65536.0f)"),
+    "backface_sign_flipped": ("if (cull_back && dd < 0.0) {", "if (cull_back && dd > 0.0) {"),
     "unsorted_under": ("C[ch] = a * ((double)((c >> (8 * ch)) & 255u) / 255.0) + (1.0 - a) * C[ch];",
                        "C[ch] = (1.0 - a) * ((double)((c >> (8 * ch)) & 255u) / 255.0) + a * C[ch];"),
 }
 
 PINS = ["tests/test_oracle_hand.py", "tests/test_oracle_bruteforce.py", "tests/test_oracle_invariants.py",
-        "tests/test_oracle_keys.py", "tests/test_oracle_cutoff.py"]
+        "tests/test_oracle_keys.py", "tests/test_oracle_cutoff.py",
+        "tests/test_oracle_backface.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
