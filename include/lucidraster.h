@@ -126,6 +126,12 @@ typedef struct {
                                  quads in no set order (the unsorted baseline,
                                  which blends in quad order, always bins by
                                  bbox).  Images are identical either way. */
+#define LR_FLAG_CULL_BACKFACES 32u /* cull quads facing away from the camera
+                                 (Stage 1): with n the cross product of the
+                                 diagonals and m the vertex centroid in camera
+                                 space, n . m < 0, i.e. the vertices wind
+                                 clockwise on the display (front faces wind
+                                 counter-clockwise, as OpenGL's default) */
 #define LR_FLAG_DENSITY_CLASSES 8u /* density classes (Section 4 proposes
                                  adapting bins to the density and running the
                                  low- and high-density rasterizers at the
@@ -146,8 +152,9 @@ typedef struct {
 typedef struct {
     uint64_t quads;           /* input quads */
     uint64_t visible;         /* quads that passed setup */
-    uint64_t culled[6];       /* [1] near [2] guard band [3] degenerate
-                                 [4] no sample [5] edge-on plane */
+    uint64_t culled[8];       /* [1] near [2] guard band [3] degenerate
+                                 [4] no sample [5] edge-on plane
+                                 [6] back-facing ([0], [7] unused) */
     uint64_t bin_pairs;       /* (bin, quad) pairs written by binning */
     uint64_t block_entries;   /* non-empty (block, quad) pairs */
     uint64_t fragments;       /* covered (pixel, quad) pairs */

@@ -7,7 +7,8 @@
 namespace lr {
 
 // Cull reasons, in the order the setup stage tests them.
-enum Cull : uint8_t { VISIBLE = 0, NEAR = 1, GUARD = 2, DEGENERATE = 3, NO_SAMPLE = 4, EDGE_ON = 5 };
+enum Cull : uint8_t { VISIBLE = 0, NEAR = 1, GUARD = 2, DEGENERATE = 3, NO_SAMPLE = 4, EDGE_ON = 5, BACKFACE = 6 };
+constexpr uint32_t kCullReasons = 7;
 
 // Quads whose snapped vertex extent stays within 2^18 sub-pixel units (1024
 // px) in x and y use 32-bit half-plane tests; wider quads take an exact fp64
@@ -84,7 +85,7 @@ struct alignas(32) QuadXY {
 // picked by workgroup index: device-scope atomics on one address serialize
 // across the XCDs, atomics on different lines do not.  The host sums them.
 constexpr uint32_t kStripes = 256;
-enum Stat { ST_CULL0 = 0, ST_ENTRIES = 6, ST_FRAGMENTS = 7, ST_COUNT = 8 };  // ST_CULL0 + reason
+enum Stat { ST_CULL0 = 0, ST_ENTRIES = 7, ST_FRAGMENTS = 8, ST_COUNT = 9 };  // ST_CULL0 + reason
 
 // The queue of flagged pixels is split the same way into kQueues stripes (by
 // block index), each with its counter in the stripe's line; a stripe holds at
@@ -95,7 +96,7 @@ struct alignas(128) StatStripe {
     unsigned long long v[ST_COUNT];
     uint32_t dense_n;   // blocks processed in depth slices
     uint32_t flag_n;    // pixels in flagged-queue stripe
-    uint32_t pad[14];
+    uint32_t pad[12];
 };
 static_assert(sizeof(StatStripe) == 128, "one line per stripe");
 
@@ -166,6 +167,7 @@ struct FrameArgs {
     uint2 *bbox;      // (imin | imax << 16, jmin | jmax << 16); culled: (0xffff, 0xffff)
     uint8_t *cull;
     uint32_t want_xy;  // write snapped vertices of every snapped quad (parity dump); else wide quads only
+    uint32_t cull_back;  // cull back-facing quads (dd < 0: clockwise on the display)
     // binning
     uint32_t bin_shift;     // log2(bin size)
     uint32_t nbx, nby, nbins;

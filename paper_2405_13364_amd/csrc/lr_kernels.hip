@@ -464,6 +464,9 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q, Q
                         if (dd == 0.0 || !isfinite(dd) || !isfinite(A) || !isfinite(B) ||
                             !isfinite(C0)) {
                             reason = EDGE_ON;
+                        } else if (a.cull_back && dd < 0.0) {
+                            // facing away: n . m < 0 is clockwise on the display
+                            reason = BACKFACE;
                         } else {
                             reason = VISIBLE;
                             uint32_t flags = 0;
@@ -574,8 +577,8 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
             s_pl[t * kPlaneChunks + (c ^ (t & (kPlaneChunks - 1)))] = pc[c];
     }
     // cull statistics: one atomic per workgroup and reason, striped
-    __shared__ uint32_t s_cull[6];
-    if (threadIdx.x < 6)
+    __shared__ uint32_t s_cull[kCullReasons];
+    if (threadIdx.x < kCullReasons)
         s_cull[threadIdx.x] = 0;
     __syncthreads();
     {
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
         if (large)
             a.large_list[base + rank_below(lm)] = q;
     }
-    for (uint32_t r = 0; r < 6; r++) {
+    for (uint32_t r = 0; r < kCullReasons; r++) {
         uint32_t c = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kSetupQPL; k++)
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(256 / kSetupQPL) void k_setup(Src src)
             atomicAdd(&s_cull[r], c);
     }
     __syncthreads();
-    if (threadIdx.x < 6 && s_cull[threadIdx.x])
+    if (threadIdx.x < kCullReasons && s_cull[threadIdx.x])
         add_stat(a.ctr, ST_CULL0 + threadIdx.x, s_cull[threadIdx.x]);
 }
 

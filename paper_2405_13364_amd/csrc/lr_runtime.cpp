@@ -466,6 +466,7 @@ void fill_args(lr_context ctx, const SceneRec &sc, const lr_camera *cam, uint8_t
 {
     fill_frame(ctx->arena + sc.off, sc.n, cam, out, plan, base, ctx->elog, a);
     a.bbox_binning = (ctx->cfg.flags & LR_FLAG_BBOX_BINNING) ? 1u : 0u;
+    a.cull_back = (ctx->cfg.flags & LR_FLAG_CULL_BACKFACES) ? 1u : 0u;
 }
 
 // Density classes of a frame rendered at sorter depth k (0: unsorted), with
@@ -625,7 +626,7 @@ lr_status add_frame_stats(lr_context ctx, const FrameRef &fr, lr_stats *sum)
             v[i] += c.stripe[k].v[i];
     sum->quads += fr.quads;
     sum->visible += v[lr::ST_CULL0 + lr::VISIBLE];
-    for (int r = 1; r < 6; r++)
+    for (uint32_t r = 1; r < lr::kCullReasons; r++)
         sum->culled[r] += v[lr::ST_CULL0 + r];
     sum->bin_pairs += c.pairs_total;
     sum->block_entries += v[lr::ST_ENTRIES];

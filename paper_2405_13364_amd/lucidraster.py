@@ -28,6 +28,7 @@ LR_FLAG_NO_GRAPH = 2
 LR_FLAG_ALPHA_CUTOFF = 4
 LR_FLAG_DENSITY_CLASSES = 8
 LR_FLAG_BBOX_BINNING = 16
+LR_FLAG_CULL_BACKFACES = 32
 LR_FRAME_ERR_CAPACITY = 1
 LR_FRAME_ERR_DENSE = 4
 
@@ -58,7 +59,7 @@ class Config(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("quads", ctypes.c_uint64), ("visible", ctypes.c_uint64),
-                ("culled", ctypes.c_uint64 * 6), ("bin_pairs", ctypes.c_uint64),
+                ("culled", ctypes.c_uint64 * 8), ("bin_pairs", ctypes.c_uint64),
                 ("block_entries", ctypes.c_uint64), ("fragments", ctypes.c_uint64),
                 ("flagged_pixels", ctypes.c_uint64), ("dense_blocks", ctypes.c_uint64),
                 ("error_word", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
@@ -154,7 +155,7 @@ class Context:
     def __init__(self, arena_bytes: int = 1 << 30, device: int = 0, bin_size: int = 32,
                  sorter_depth: int = 8, timing: bool = False, stream=None, block_h: int = 8,
                  batch_slots: int = 2, graphs: bool = True, tuning=None, alpha_cutoff: bool = False,
-                 density_classes: bool = False, bbox_binning: bool = False):
+                 density_classes: bool = False, bbox_binning: bool = False, cull_backfaces: bool = False):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -169,7 +170,8 @@ class Context:
                      flags=(LR_FLAG_TIMING if timing else 0) | (0 if graphs else LR_FLAG_NO_GRAPH) |
                      (LR_FLAG_ALPHA_CUTOFF if alpha_cutoff else 0) |
                      (LR_FLAG_DENSITY_CLASSES if density_classes else 0) |
-                     (LR_FLAG_BBOX_BINNING if bbox_binning else 0),
+                     (LR_FLAG_BBOX_BINNING if bbox_binning else 0) |
+                     (LR_FLAG_CULL_BACKFACES if cull_backfaces else 0),
                      hbm_budget_bytes=0, batch_slots=batch_slots)
         self.bin_size, self.sorter_depth, self.block_h = bin_size, sorter_depth, block_h
         h = ctypes.c_void_p()

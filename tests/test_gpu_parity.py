@@ -330,7 +330,8 @@ def test_stats_match_oracle(lr):
     ref = oracle.render(sc.v, sc.rgba, sc.camera, sc.width, sc.height, want_order=False)
     cc = ref["setup"].cull_counts()
     assert st["visible"] == cc["visible"]
-    assert st["culled"][1:] == [cc["near"], cc["guard"], cc["degenerate"], cc["no_sample"], cc["edge_on"]]
+    assert st["culled"][1:7] == [cc["near"], cc["guard"], cc["degenerate"], cc["no_sample"], cc["edge_on"],
+                                 cc["backface"]]
     assert st["fragments"] == ref["total"]
     counts, _, _ = oracle.bins(ref["setup"], sc.width, sc.height, 32)
     assert st["bin_pairs"] == int(counts.sum())
@@ -569,3 +570,27 @@ def test_large_quad_binning_keeps_the_image(lr, b):
         ctx.close()
     assert res[False][0] < res[True][0]
     np.testing.assert_array_equal(res[False][1], res[True][1])
+
+
+@pytest.mark.parametrize("name", ["small", "c1", "general", "twisted"])
+def test_backface_culling(lr, name):
+    """LR_FLAG_CULL_BACKFACES: setup culls exactly the quads the oracle culls
+    as back-facing (bit-exact records for the rest), and the frame matches
+    the oracle's with the same culling: counts, order, colour, statistics."""
+    sc = SCENES[name]()
+    cam = moved_camera()
+    st = oracle.setup(sc.v, cam, sc.width, sc.height, cull_backfaces=True)
+    assert np.count_nonzero(st.cull == 6) > 0
+    ctx = lr.Context(arena_bytes=256 << 20, cull_backfaces=True)
+    h = ctx.upload(sc.v, sc.rgba)
+    got = ctx.debug_setup(h, cam, sc.width, sc.height, sc.n)
+    np.testing.assert_array_equal(got["cull"], st.cull)
+    vis = st.cull == 0
+    np.testing.assert_array_equal(got["bbox"][vis], st.bbox[vis])
+    ref = oracle.render(sc.v, sc.rgba, cam, sc.width, sc.height, st=st)
+    check_frame(ctx.render_debug(h, cam, sc.width, sc.height, order=True), ref, f"{name} culled")
+    ctx.render(h, cam, sc.width, sc.height)
+    stats = ctx.stats()
+    assert stats["culled"][6] == int(np.count_nonzero(st.cull == 6))
+    assert stats["fragments"] == ref["total"]
+    ctx.close()
