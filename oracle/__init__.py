@@ -58,16 +58,18 @@ def _load():
         lib.lro_focal.argtypes = [ctypes.c_uint32, ctypes.c_float]
         lib.lro_setup.restype = None
         lib.lro_setup.argtypes = [ctypes.c_uint32, P, ctypes.POINTER(_Cam), ctypes.c_uint32,
-                                  ctypes.c_uint32, ctypes.c_double, P, P, P, P, P, P, P, ctypes.c_int]
+                                  ctypes.c_uint32, ctypes.c_double, P, P, P, P, P, P, P, ctypes.c_int, P]
         lib.lro_render.restype = ctypes.c_int64
         lib.lro_render.argtypes = [ctypes.c_uint32, P, P, P, P, P, P, P, P, ctypes.c_uint32,
-                                   ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, ctypes.c_uint32]
+                                   ctypes.c_uint32, ctypes.c_int, P, P, P, P, P, ctypes.c_uint32,
+                                   P, P, ctypes.c_double]
         lib.lro_count.restype = ctypes.c_int64
         lib.lro_count.argtypes = [ctypes.c_uint32, P, P, P, P, ctypes.c_uint32, ctypes.c_uint32, P,
                                   ctypes.c_uint32]
         lib.lro_pixels.restype = ctypes.c_int64
         lib.lro_pixels.argtypes = [ctypes.c_uint32, P, P, P, P, P, P, P, P, ctypes.c_uint32,
-                                   ctypes.c_int, ctypes.c_uint32, P, P, P, P, P, ctypes.c_uint64]
+                                   ctypes.c_int, ctypes.c_uint32, P, P, P, P, P, ctypes.c_uint64,
+                                   P, P, ctypes.c_double, ctypes.c_uint32]
         lib.lro_bins.restype = ctypes.c_int64
         lib.lro_bins.argtypes = [ctypes.c_uint32, P, P, ctypes.c_uint32, ctypes.c_uint32,
                                  ctypes.c_uint32, P, P, P, ctypes.c_uint64]
@@ -113,6 +115,7 @@ class Setup:
         self.B = np.zeros(n, np.float64)
         self.C0 = np.zeros(n, np.float64)
         self.cull = np.zeros(n, np.uint8)
+        self.cam = np.zeros((n, 4, 3), np.float64)  # camera-space vertices
         self.f = 0.0
 
     @property
@@ -135,7 +138,7 @@ def setup(v: np.ndarray, camera, W: int, H: int, cull_backfaces: bool = False) -
     s.f = lib.lro_focal(H, cam.fov_y)
     if n:
         lib.lro_setup(n, _p(v), ctypes.byref(cam), W, H, s.f, _p(s.X), _p(s.Y), _p(s.bbox),
-                      _p(s.A), _p(s.B), _p(s.C0), _p(s.cull), int(cull_backfaces))
+                      _p(s.A), _p(s.B), _p(s.C0), _p(s.cull), int(cull_backfaces), _p(s.cam))
     return s
 
 
@@ -161,15 +164,20 @@ def _mode(unsorted: bool, cutoff: bool) -> int:
 def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bool = False,
            want_order: bool = True, st: Optional[Setup] = None,
            threads: Optional[int] = None, cutoff: bool = False,
-           cull_backfaces: bool = False) -> Dict[str, np.ndarray]:
+           cull_backfaces: bool = False, vcol: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """Whole-frame reference render.  Returns rgba_f64 [H,W,4], rgba8 [H,W,4],
     count [H,W], order_offsets [W*H+1], order_ids [total], setup, and the
     number of worker threads used (row bands; the result does not depend on
     it).  With cutoff, each pixel stops after the fragment that brings its
     single-precision transmittance below 2^-20: count, order and total are
-    those of the blended prefixes ("covering" keeps the full total)."""
+    those of the blended prefixes ("covering" keeps the full total).  vcol:
+    per-vertex colours uint32 [n, 4] (perspective-correct interpolation over
+    the triangle covering each sample) instead of the flat rgba."""
     lib = _load()
     mode = _mode(unsorted, cutoff)
+    if vcol is not None and cutoff:
+        raise ValueError("the transmittance cutoff is defined for flat colours only")
+    vc = None if vcol is None else np.ascontiguousarray(vcol, np.uint32).reshape(-1, 4)
     st = st or setup(v, camera, W, H, cull_backfaces)
     threads = default_threads() if threads is None else max(1, int(threads))
     rgba = np.ascontiguousarray(rgba, np.uint32)
@@ -188,7 +196,8 @@ def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bo
         if n:
             total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
                                    _p(st.cull), _p(rgba), W, H, mode, _p(out_f), _p(out_8),
-                                   _p(cnt), _p(off), _p(ids), threads)
+                                   _p(cnt), _p(off), _p(ids), threads,
+                                   None if vc is None else _p(vc), _p(st.cam), st.f)
         if total < 0:
             raise MemoryError("oracle render failed")
         ids = ids[:int(total)]
@@ -204,7 +213,8 @@ def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bo
     else:
         total = lib.lro_render(n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B), _p(st.C0),
                                _p(st.cull), _p(rgba), W, H, mode, _p(out_f), _p(out_8),
-                               _p(cnt), None, None, threads) if n else 0
+                               _p(cnt), None, None, threads,
+                               None if vc is None else _p(vc), _p(st.cam), st.f) if n else 0
     if total < 0:
         raise MemoryError("oracle render failed")
     res["covering"] = int(total)
@@ -215,12 +225,15 @@ def render(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, unsorted: bo
 def pixels(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, pix: np.ndarray,
            unsorted: bool = False, want_ids: bool = True,
            st: Optional[Setup] = None, cutoff: bool = False,
-           cull_backfaces: bool = False) -> Dict[str, np.ndarray]:
+           cull_backfaces: bool = False, vcol: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """Reference result for selected pixels (pix = j*W + i), each computed by
     testing every quad.  Returns rgba_f64 [k,4], count [k], offsets, ids
     (with cutoff: those of the blended prefixes)."""
     lib = _load()
     mode = _mode(unsorted, cutoff)
+    if vcol is not None and cutoff:
+        raise ValueError("the transmittance cutoff is defined for flat colours only")
+    vc = None if vcol is None else np.ascontiguousarray(vcol, np.uint32).reshape(-1, 4)
     st = st or setup(v, camera, W, H, cull_backfaces)
     rgba = np.ascontiguousarray(rgba, np.uint32)
     pix = np.ascontiguousarray(pix, np.uint32)
@@ -234,7 +247,8 @@ def pixels(v: np.ndarray, rgba: np.ndarray, camera, W: int, H: int, pix: np.ndar
         total = lib.lro_pixels(st.n, _p(st.X), _p(st.Y), _p(st.bbox), _p(st.A), _p(st.B),
                                _p(st.C0), _p(st.cull), _p(rgba), W, mode, k, _p(pix),
                                _p(out_f), _p(cnt), _p(off) if want_ids else None,
-                               _p(ids) if want_ids else None, cap)
+                               _p(ids) if want_ids else None, cap, None if vc is None else _p(vc),
+                               _p(st.cam), st.f, H)
         if total >= 0:
             break
         if not want_ids or cap > (1 << 31):

@@ -45,6 +45,15 @@
  *            T *= 1 - a; output premultiplied (C, 1 - T); RGBA8 is
  *            clamp(floor(255 x + 0.5)).
  *   unsorted quad index order, "over": C = a c + (1-a) C, al = a + (1-a) al.
+ *   vertex colours (optional; Stage 3 "Sample shading" interpolates
+ *            per-vertex attributes): a covered sample takes triangle T0 if
+ *            T0 covers it, else T1; its colour is the barycentric mix of
+ *            that triangle's vertex colours (bytes / 255) at the point where
+ *            the ray through the pixel centre meets the triangle's plane in
+ *            camera space: with r = ((px - cx)/f, -(py - cy)/f, 1) and the
+ *            triangle's camera-space vertices (A, B, C), the weights are
+ *            r.(BxC), r.(CxA), r.(AxB) over their sum (perspective-correct
+ *            interpolation).  The colour is blended unrounded.
  *   cutoff   (optional; Stage 3 "Sample blending" stops a pixel once its
  *            accumulated alpha passes a threshold) a pixel stops after the
  *            first fragment that brings its transmittance below 2^-20; the
@@ -129,8 +138,8 @@ static int64_t floordiv256(int64_t a) { return a >= 0 ? a / 256 : -((-a + 255) /
  * X, Y int32[n][4] snapped vertices; bbox int32[n][4] = (imin, imax, jmin,
  * jmax); A, B, C0 double[n]; cull uint8[n] (0 = visible, else the first
  * failing test in the order near, guard, degenerate, no-sample, edge-on,
- * back-facing).  Fields of culled quads are left as far as they were
- * computed.
+ * back-facing); camv double[n][4][3] camera-space vertices (may be NULL).
+ * Fields of culled quads are left as far as they were computed.
  *
  * Back-face culling (cull_back != 0; Stage 1 culls primitives facing away
  * from the camera): dd = n . m, with n the cross product of the diagonals
@@ -140,7 +149,7 @@ static int64_t floordiv256(int64_t a) { return a >= 0 ? a / 256 : -((-a + 255) /
  */
 void lro_setup(uint32_t n, const float *v, const lro_camera *cam, uint32_t W, uint32_t H, double f,
                int32_t *X, int32_t *Y, int32_t *bbox, double *A, double *B, double *C0,
-               uint8_t *cull, int cull_back)
+               uint8_t *cull, int cull_back, double *camv)
 {
     const double cx = 0.5 * (double)W, cy = 0.5 * (double)H;
     double R[9], P[3];
@@ -164,6 +173,10 @@ void lro_setup(uint32_t n, const float *v, const lro_camera *cam, uint32_t W, ui
             for (int r = 0; r < 3; r++)
                 c[k][r] = fma(R[3 * r + 2], d2, fma(R[3 * r + 1], d1, R[3 * r + 0] * d0));
         }
+        if (camv)  /* camera-space vertices, for vertex colours */
+            for (int k = 0; k < 4; k++)
+                for (int r = 0; r < 3; r++)
+                    camv[12 * (size_t)q + 3 * k + r] = c[k][r];
         /* near plane */
         int near = 0;
         for (int k = 0; k < 4; k++)
@@ -286,22 +299,79 @@ static int cmp_frag(const void *pa, const void *pb)
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
-/* One front-to-back step: the fragment of colour c under transmittance T. */
-static void blend_step(uint32_t c, double *T, double C[3])
+/* A fragment's colour: R, G, B, A in [0, 1]. */
+typedef struct {
+    double c[4];
+} colour_t;
+
+static colour_t colour_of(uint32_t c)
 {
-    double a = (double)(c >> 24) / 255.0;
+    colour_t o;
+    for (int ch = 0; ch < 4; ch++)
+        o.c[ch] = (double)((c >> (8 * ch)) & 255u) / 255.0;
+    return o;
+}
+
+/* One front-to-back step: a fragment of colour col under transmittance T. */
+static void blend_step(const colour_t *col, double *T, double C[3])
+{
+    double a = col->c[3];
     double w = *T * a;
     for (int ch = 0; ch < 3; ch++)
-        C[ch] = C[ch] + w * ((double)((c >> (8 * ch)) & 255u) / 255.0);
+        C[ch] = C[ch] + w * col->c[ch];
     *T = *T * (1.0 - a);
 }
 
-/* Front-to-back blend of fragments already in order. */
-static void blend_front_to_back(const frag_t *fr, uint32_t cnt, double out[4])
+/* Vertex colours of a quad: camera-space vertices cv[4][3], colours rgba4[4],
+ * snapped vertices X, Y (for the triangle choice) and the camera's f, cx,
+ * cy; the colour at pixel (i, j), which the quad covers. */
+typedef struct {
+    const double *cv;
+    const uint32_t *rgba4;
+    const int32_t *X, *Y;
+    double f, cx, cy;
+} vquad_t;
+
+static void cross3(const double *a, const double *b, double *o)
+{
+    double p, s;
+    p = a[1] * b[2]; s = a[2] * b[1]; o[0] = p - s;
+    p = a[2] * b[0]; s = a[0] * b[2]; o[1] = p - s;
+    p = a[0] * b[1]; s = a[1] * b[0]; o[2] = p - s;
+}
+
+static colour_t vertex_colour(const vquad_t *vq, int32_t i, int32_t j)
+{
+    int64_t sx = 256 * (int64_t)i + 128, sy = 256 * (int64_t)j + 128;
+    int t[3] = {0, 1, 2};
+    if (!tri_covers(vq->X, vq->Y, 0, 1, 2, sx, sy)) {
+        t[1] = 2;
+        t[2] = 3;
+    }
+    const double r[3] = {(((double)i + 0.5) - vq->cx) / vq->f, -((((double)j + 0.5) - vq->cy) / vq->f), 1.0};
+    double w[3], sum = 0.0;
+    for (int k = 0; k < 3; k++) {
+        double n[3];
+        cross3(vq->cv + 3 * t[(k + 1) % 3], vq->cv + 3 * t[(k + 2) % 3], n);
+        w[k] = (r[0] * n[0] + r[1] * n[1]) + r[2] * n[2];
+        sum += w[k];
+    }
+    colour_t o;
+    for (int ch = 0; ch < 4; ch++) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; k++)
+            acc += (w[k] / sum) * ((double)((vq->rgba4[t[k]] >> (8 * ch)) & 255u) / 255.0);
+        o.c[ch] = acc;
+    }
+    return o;
+}
+
+/* Front-to-back blend of fragments already in order (colours col[k]). */
+static void blend_front_to_back(const colour_t *col, uint32_t cnt, double out[4])
 {
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
     for (uint32_t k = 0; k < cnt; k++)
-        blend_step(fr[k].rgba, &T, C);
+        blend_step(&col[k], &T, C);
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
 }
 
@@ -318,7 +388,8 @@ static uint32_t blend_front_to_back_cut(const frag_t *fr, uint32_t cnt, double o
     uint32_t k = 0;
     while (k < cnt) {
         uint32_t c = fr[k].rgba;
-        blend_step(c, &T, C);
+        const colour_t col = colour_of(c);
+        blend_step(&col, &T, C);
         float a32 = (float)(c >> 24) * inv255;
         T32 = T32 * (1.0f - a32);
         k++;
@@ -330,17 +401,34 @@ static uint32_t blend_front_to_back_cut(const frag_t *fr, uint32_t cnt, double o
 }
 
 /* "Over" blend in quad index order (the unsorted baseline). */
-static void blend_over(const frag_t *fr, uint32_t cnt, double out[4])
+static void blend_over(const colour_t *col, uint32_t cnt, double out[4])
 {
     double C[3] = {0.0, 0.0, 0.0}, al = 0.0;
     for (uint32_t k = 0; k < cnt; k++) {
-        uint32_t c = fr[k].rgba;
-        double a = (double)(c >> 24) / 255.0;
+        double a = col[k].c[3];
         for (int ch = 0; ch < 3; ch++)
-            C[ch] = a * ((double)((c >> (8 * ch)) & 255u) / 255.0) + (1.0 - a) * C[ch];
+            C[ch] = a * col[k].c[ch] + (1.0 - a) * C[ch];
         al = a + (1.0 - a) * al;
     }
     out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = al;
+}
+
+/* Colours of the cnt fragments of pixel (i, j): flat, or from the quads'
+ * vertex colours (vcol != NULL: rgba4[n][4], camv[n][4][3]). */
+static void fragment_colours(const frag_t *fr, uint32_t cnt, const uint32_t *vcol, const double *camv,
+                             const int32_t *X, const int32_t *Y, double f, double cx, double cy,
+                             int32_t i, int32_t j, colour_t *col)
+{
+    for (uint32_t k = 0; k < cnt; k++) {
+        if (!vcol) {
+            col[k] = colour_of(fr[k].rgba);
+        } else {
+            const uint32_t q = (uint32_t)(fr[k].key & 0xffffffffu);
+            vquad_t vq = {camv + 12 * (size_t)q, vcol + 4 * (size_t)q, X + 4 * (size_t)q, Y + 4 * (size_t)q,
+                          f, cx, cy};
+            col[k] = vertex_colour(&vq, i, j);
+        }
+    }
 }
 
 static uint8_t to_u8(double x)
@@ -375,6 +463,9 @@ typedef struct {
     const uint8_t *cull;
     const uint32_t *rgba;
     int mode;               /* 0 sorted, 1 unsorted (quad order), 2 sorted with the cutoff */
+    const uint32_t *vcol;   /* vertex colours [n][4], or NULL */
+    const double *camv;     /* camera-space vertices [n][4][3] (with vcol) */
+    double f;
     /* outputs and work arrays */
     double *rgba_f64;
     uint8_t *rgba8;
@@ -423,21 +514,45 @@ static void band_quads(lro_job *jb, int32_t j0, int32_t j1, int fill_pass)
     }
 }
 
+/* Grows *buf to hold n colours; 0 when memory runs out. */
+static int colour_room(colour_t **buf, size_t *cap, size_t n)
+{
+    if (n <= *cap)
+        return 1;
+    size_t c = *cap ? *cap : 256;
+    while (c < n)
+        c *= 2;
+    colour_t *nb = (colour_t *)realloc(*buf, c * sizeof(colour_t));
+    if (!nb)
+        return 0;
+    *buf = nb;
+    *cap = c;
+    return 1;
+}
+
 /* Pass 3 for the pixels of rows j0..j1: order and blend. */
 static void band_blend(lro_job *jb, int32_t j0, int32_t j1)
 {
+    colour_t *col = NULL;
+    size_t cap = 0;
+    const double cx = 0.5 * (double)jb->W, cy = 0.5 * (double)jb->H;
     for (size_t p = (size_t)j0 * jb->W; p < (size_t)(j1 + 1) * jb->W; p++) {
         frag_t *pf = jb->fr + jb->off[p];
         uint32_t cnt = jb->count[p];
         double o[4];
-        if (jb->mode == 1) {
-            blend_over(pf, cnt, o);
-        } else {
+        if (jb->mode != 1)
             qsort(pf, cnt, sizeof(frag_t), cmp_frag);
-            if (jb->mode == 2)
-                jb->count[p] = cnt = blend_front_to_back_cut(pf, cnt, o);  /* the blended prefix */
+        if (jb->mode == 2) {
+            jb->count[p] = cnt = blend_front_to_back_cut(pf, cnt, o);  /* the blended prefix */
+        } else {
+            if (!colour_room(&col, &cap, cnt))
+                abort();
+            fragment_colours(pf, cnt, jb->vcol, jb->camv, jb->X, jb->Y, jb->f, cx, cy, (int32_t)(p % jb->W),
+                             (int32_t)(p / jb->W), col);
+            if (jb->mode == 1)
+                blend_over(col, cnt, o);
             else
-                blend_front_to_back(pf, cnt, o);
+                blend_front_to_back(col, cnt, o);
         }
         for (int ch = 0; ch < 4; ch++) {
             if (jb->rgba_f64) jb->rgba_f64[4 * p + ch] = o[ch];
@@ -447,6 +562,7 @@ static void band_blend(lro_job *jb, int32_t j0, int32_t j1)
             for (uint32_t t = 0; t < cnt; t++)
                 jb->order_ids[jb->off[p] + t] = (uint32_t)(pf[t].key & 0xffffffffu);
     }
+    free(col);
 }
 
 static void *band_worker(void *arg)
@@ -527,12 +643,17 @@ int64_t lro_render(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
                    const double *A, const double *B, const double *C0, const uint8_t *cull,
                    const uint32_t *rgba, uint32_t W, uint32_t H, int mode, double *rgba_f64,
                    uint8_t *rgba8, uint32_t *count, uint64_t *order_offsets, uint32_t *order_ids,
-                   uint32_t threads)
+                   uint32_t threads, const uint32_t *vcol, const double *camv, double f)
 {
     const size_t npix = (size_t)W * H;
     threads = pick_threads(threads);
+    if (vcol && mode == 2)
+        return -2;  /* the cutoff is defined on flat colours only */
     lro_job jb;
     job_init(&jb, n, X, Y, bbox, A, B, C0, cull, rgba, W, H, mode, count);
+    jb.vcol = vcol;
+    jb.camv = camv;
+    jb.f = f;
     uint64_t *off = (uint64_t *)calloc(npix + 1, sizeof(uint64_t));
     if (!off) {
         pthread_mutex_destroy(&jb.mu);
@@ -582,8 +703,13 @@ int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
                    const double *A, const double *B, const double *C0, const uint8_t *cull,
                    const uint32_t *rgba, uint32_t W, int mode, uint32_t npix,
                    const uint32_t *pix, double *rgba_f64, uint32_t *count, uint64_t *offsets,
-                   uint32_t *ids, uint64_t ids_cap)
+                   uint32_t *ids, uint64_t ids_cap, const uint32_t *vcol, const double *camv, double f,
+                   uint32_t H)
 {
+    if (vcol && mode == 2)
+        return -2;
+    colour_t *col = NULL;
+    size_t ccap = 0;
     size_t cap = 1024;
     frag_t *fr = (frag_t *)malloc(cap * sizeof(frag_t));
     if (!fr)
@@ -607,6 +733,7 @@ int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
                 frag_t *nf = (frag_t *)realloc(fr, cap * sizeof(frag_t));
                 if (!nf) {
                     free(fr);
+                    free(col);
                     return -1;
                 }
                 fr = nf;
@@ -616,14 +743,20 @@ int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
             cnt++;
         }
         double o[4];
-        if (mode == 1) {
-            blend_over(fr, cnt, o);
-        } else {
+        if (mode != 1)
             qsort(fr, cnt, sizeof(frag_t), cmp_frag);
-            if (mode == 2)
-                cnt = blend_front_to_back_cut(fr, cnt, o);  /* the blended prefix */
+        if (mode == 2) {
+            cnt = blend_front_to_back_cut(fr, cnt, o);  /* the blended prefix */
+        } else {
+            if (!colour_room(&col, &ccap, cnt)) {
+                free(fr);
+                return -1;
+            }
+            fragment_colours(fr, cnt, vcol, camv, X, Y, f, 0.5 * (double)W, 0.5 * (double)H, i, j, col);
+            if (mode == 1)
+                blend_over(col, cnt, o);
             else
-                blend_front_to_back(fr, cnt, o);
+                blend_front_to_back(col, cnt, o);
         }
         for (int ch = 0; ch < 4; ch++)
             rgba_f64[4 * (size_t)k + ch] = o[ch];
@@ -631,6 +764,7 @@ int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
         if (ids) {
             if (total + cnt > ids_cap) {
                 free(fr);
+                free(col);
                 return -1;
             }
             for (uint32_t t = 0; t < cnt; t++)
@@ -641,6 +775,7 @@ int64_t lro_pixels(uint32_t n, const int32_t *X, const int32_t *Y, const int32_t
             offsets[k + 1] = total;
     }
     free(fr);
+    free(col);
     return (int64_t)total;
 }
 

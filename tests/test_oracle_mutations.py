@@ -33,13 +33,16 @@ MUTANTS = {
                                       "        if (T32 < LRO_CUT_T)\n            break;\n        k++;"),
     "cutoff_threshold_too_high": ("#define LRO_CUT_T (1.0f / 1048576.0f)", "#define LRO_CUT_T (1.0f / 65536.0f)"),
     "backface_sign_flipped": ("if (cull_back && dd < 0.0) {", "if (cull_back && dd > 0.0) {"),
-    "unsorted_under": ("C[ch] = a * ((double)((c >> (8 * ch)) & 255u) / 255.0) + (1.0 - a) * C[ch];",
-                       "C[ch] = (1.0 - a) * ((double)((c >> (8 * ch)) & 255u) / 255.0) + a * C[ch];"),
+    "vcol_wrong_triangle": ("    if (!tri_covers(vq->X, vq->Y, 0, 1, 2, sx, sy)) {", "    if (tri_covers(vq->X, vq->Y, 0, 1, 2, sx, sy)) {"),
+    "vcol_weights_rotated": ("cross3(vq->cv + 3 * t[(k + 1) % 3], vq->cv + 3 * t[(k + 2) % 3], n);",
+                             "cross3(vq->cv + 3 * t[(k + 2) % 3], vq->cv + 3 * t[k], n);"),
+    "unsorted_under": ("C[ch] = a * col[k].c[ch] + (1.0 - a) * C[ch];",
+                       "C[ch] = (1.0 - a) * col[k].c[ch] + a * C[ch];"),
 }
 
 PINS = ["tests/test_oracle_hand.py", "tests/test_oracle_bruteforce.py", "tests/test_oracle_invariants.py",
         "tests/test_oracle_keys.py", "tests/test_oracle_cutoff.py",
-        "tests/test_oracle_backface.py"]
+        "tests/test_oracle_backface.py", "tests/test_oracle_vcol.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
