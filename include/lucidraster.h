@@ -66,6 +66,15 @@ typedef struct {
 } lr_quad;
 #pragma pack(pop)
 
+/* A quad with one straight-alpha RGBA8 colour per vertex (R in the low
+ * byte).  64 bytes, packed. */
+#pragma pack(push, 4)
+typedef struct {
+    float v[4][3];
+    uint32_t rgba[4];
+} lr_quad_vc;
+#pragma pack(pop)
+
 /* Pinhole camera: rows of rot are the camera x, y, z axes in world space. */
 typedef struct {
     float pos[3];
@@ -233,6 +242,17 @@ lr_status lr_destroy(lr_context ctx);
  * returns.  1 <= n <= 2^24; LR_ERR_OUT_OF_MEMORY when the arena is full. */
 lr_status lr_upload_scene(lr_context ctx, const lr_quad *q, uint32_t n, int q_on_device,
                           lr_scene *out);
+
+/* Make quads with per-vertex colours resident (host memory; the call waits
+ * for the copy).  Every render of such a scene interpolates the colours per
+ * sample (Stage 3, "Sample shading"): a covered sample takes triangle T0 =
+ * (P0, P1, P2) if T0 covers it, else T1 = (P0, P2, P3), and the barycentric
+ * mix of that triangle's vertex colours where the ray through the pixel
+ * centre meets the triangle's plane (perspective-correct), blended in fp32
+ * without rounding to 8 bits.  Rendering such a scene with
+ * LR_FLAG_ALPHA_CUTOFF fails with LR_ERR_INVALID_ARG.  1 <= n <= 2^24;
+ * LR_ERR_OUT_OF_MEMORY when the arena is full (68 bytes per quad). */
+lr_status lr_upload_scene_vertex_colors(lr_context ctx, const lr_quad_vc *q, uint32_t n, lr_scene *out);
 
 /* Return a scene's arena space (after the device drains).  This library's
  * own memory management. */

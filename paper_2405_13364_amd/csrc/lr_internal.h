@@ -57,6 +57,20 @@ struct alignas(32) ExtraRec {
 };
 static_assert(sizeof(ExtraRec) == 32, "ExtraRec is 32 bytes");
 
+// VColRec: per-vertex colours of a visible quad (scenes uploaded with vertex
+// colours), for each of its triangles T0 = (P0, P1, P2) and T1 = (P0, P2,
+// P3): five planes (a, b, c) in fp64, relative to the bbox origin ij --
+// the sum of the barycentric weights (pl[t][0..2]) and the weighted sums of
+// R, G, B and A (pl[t][3 + 3 ch ..]).  At pixel (imin + di, jmin + dj),
+// channel ch is plane(3 + 3 ch) / plane(0), each plane fma(a, di, fma(b, dj,
+// c)).  256 bytes.
+struct alignas(32) VColRec {
+    double pl[2][15];
+    uint32_t ij;       // imin | jmin << 16
+    uint32_t pad[3];
+};
+static_assert(sizeof(VColRec) == 256, "VColRec is 256 bytes");
+
 constexpr uint32_t kWide = 1u;       // use the fp64 coverage path
 constexpr uint32_t kT0Valid = 2u;    // triangle (P0, P1, P2) has non-zero area
 constexpr uint32_t kT0Swap = 4u;     // ... and is stored as (P0, P2, P1)
@@ -153,6 +167,10 @@ struct FrameArgs {
     const float *v;
     const uint32_t *rgba_in;
     uint32_t n;
+    // per-vertex colours vcol_in[k * n + q] of vertex k (null: flat colours),
+    // and the interpolation records setup writes for them
+    const uint32_t *vcol_in;
+    VColRec *vcrec;
     // camera
     float pos[3];
     float rot[9];

@@ -165,10 +165,6 @@ __device__ __forceinline__ void blend_ftb_dec(float4 d, float &T, float &R, floa
     T = T * (1.0f - d.x);
 }
 
-__device__ __forceinline__ void blend_ftb(uint32_t c, float &T, float &R, float &G, float &B)
-{
-    blend_ftb_dec(decode_rgba(c), T, R, G, B);
-}
 
 // Transmittance below which a pixel stops when the cutoff is on (the
 // tolerance-safe form of the alpha threshold of Stage 3, "Sample blending":
@@ -190,16 +186,15 @@ __device__ __forceinline__ void blend_ftb_cut(float4 d, float &T, float &R, floa
     T = stopped ? T : Tn;
 }
 
-// "Over" step of the unsorted baseline (fp32).
-__device__ __forceinline__ void blend_over(uint32_t c, float &R, float &G, float &B, float &Al)
+// "Over" step of the unsorted baseline (fp32) for a blend operand d
+// (alpha, R, G, B).
+__device__ __forceinline__ void blend_over_dec(float4 d, float &R, float &G, float &B, float &Al)
 {
-    const float s = 1.0f / 255.0f;
-    float a = (float)(c >> 24) * s;
-    float om = 1.0f - a;
-    R = fmaf(a, (float)(c & 255u) * s, om * R);
-    G = fmaf(a, (float)((c >> 8) & 255u) * s, om * G);
-    B = fmaf(a, (float)((c >> 16) & 255u) * s, om * B);
-    Al = fmaf(om, Al, a);
+    const float om = 1.0f - d.x;
+    R = fmaf(d.x, d.y, om * R);
+    G = fmaf(d.x, d.z, om * G);
+    B = fmaf(d.x, d.w, om * B);
+    Al = fmaf(om, Al, d.x);
 }
 
 __device__ __forceinline__ uint32_t to_u8(float x)
@@ -364,6 +359,95 @@ __device__ void convex_halfplanes(const int32_t *X, const int32_t *Y, double Rx,
 // A visible quad's setup results, held in registers; k_setup stores them
 // as the quad's CovRec, PlaneRec and, when it is not strictly convex, its
 // ExtraRec.
+// Interpolation planes of a quad's vertex colours (Stage 3, "Sample
+// shading": per-vertex attributes interpolated per sample).  For a triangle
+// with camera-space vertices (A, B, C), the ray through pixel centre (px,
+// py), r = ((px - cx)/f, -(py - cy)/f, 1), meets the triangle's plane at
+// barycentric weights proportional to r.(BxC), r.(CxA), r.(AxB): affine in
+// the pixel, so each weight, their sum and the weighted colour sums are
+// planes over (di, dj) = (px - 0.5 - imin, py - 0.5 - jmin).
+__device__ void vertex_colour_planes(const FrameArgs &a, uint32_t q, const double (*c)[3], int imin, int jmin)
+{
+    VColRec rec;
+    const double u0 = ((double)imin + 0.5) - a.cx, w0 = ((double)jmin + 0.5) - a.cy;
+    for (int t = 0; t < 2; t++) {
+        const int idx[3] = {0, t ? 2 : 1, t ? 3 : 2};
+        double pl[15];
+        for (int k = 0; k < 15; k++)
+            pl[k] = 0.0;
+        for (int k = 0; k < 3; k++) {
+            const double *P = c[idx[(k + 1) % 3]], *Q = c[idx[(k + 2) % 3]];
+            double n[3], p, s;
+            p = P[1] * Q[2]; s = P[2] * Q[1]; n[0] = p - s;
+            p = P[2] * Q[0]; s = P[0] * Q[2]; n[1] = p - s;
+            p = P[0] * Q[1]; s = P[1] * Q[0]; n[2] = p - s;
+            // the weight w_k(di, dj) = wa di + wb dj + wc
+            const double wa = n[0] / a.f, wb = -n[1] / a.f;
+            const double wc = (u0 * n[0] - w0 * n[1]) / a.f + n[2];
+            const uint32_t col = a.vcol_in[(size_t)idx[k] * a.n + q];
+            pl[0] += wa;
+            pl[1] += wb;
+            pl[2] += wc;
+            for (int ch = 0; ch < 4; ch++) {
+                const double v = (double)((col >> (8 * ch)) & 255u) / 255.0;
+                pl[3 + 3 * ch] += v * wa;
+                pl[4 + 3 * ch] += v * wb;
+                pl[5 + 3 * ch] += v * wc;
+            }
+        }
+        for (int k = 0; k < 15; k++)
+            rec.pl[t][k] = pl[k];
+    }
+    rec.ij = (uint32_t)imin | ((uint32_t)jmin << 16);
+    rec.pad[0] = rec.pad[1] = rec.pad[2] = 0;
+    a.vcrec[q] = rec;
+}
+
+// Whether triangle (P0, P_ib, P_ic) of the snapped vertices covers the centre
+// of pixel (px, py) under the top-left rule (exact: products below 2^50 in
+// fp64); a zero-area triangle covers nothing.
+__device__ bool snapped_tri_covers(const QuadXY &xy, int ib, int ic, int px, int py)
+{
+    const double Sx = 256.0 * (double)px + 128.0, Sy = 256.0 * (double)py + 128.0;
+    double vx[3] = {(double)xy.X[0], (double)xy.X[ib], (double)xy.X[ic]};
+    double vy[3] = {(double)xy.Y[0], (double)xy.Y[ib], (double)xy.Y[ic]};
+    const double area2 = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vy[1] - vy[0]) * (vx[2] - vx[0]);
+    if (area2 == 0.0)
+        return false;
+    if (area2 < 0.0) {
+        const double tx = vx[1], ty = vy[1];
+        vx[1] = vx[2];
+        vy[1] = vy[2];
+        vx[2] = tx;
+        vy[2] = ty;
+    }
+    for (int e = 0; e < 3; e++) {
+        const double dx = vx[(e + 1) % 3] - vx[e], dy = vy[(e + 1) % 3] - vy[e];
+        const double E = dx * (Sy - vy[e]) - dy * (Sx - vx[e]);
+        const bool tl = (dy < 0.0) || (dy == 0.0 && dx > 0.0);
+        if (!(E > 0.0 || (E == 0.0 && tl)))
+            return false;
+    }
+    return true;
+}
+
+// The colour of quad q at pixel (px, py), which it covers: interpolated over
+// T0 if T0 covers the sample, else over T1; as a blend operand (alpha, R, G,
+// B), like decode_rgba.
+__device__ float4 vertex_colour(const FrameArgs &a, uint32_t q, int px, int py)
+{
+    const QuadXY xy = a.xy[q];
+    const int t = snapped_tri_covers(xy, 1, 2, px, py) ? 0 : 1;
+    const VColRec &r = a.vcrec[q];
+    const double di = (double)(px - (int)(r.ij & 0xffffu)), dj = (double)(py - (int)(r.ij >> 16));
+    const double *pl = r.pl[t];
+    const double den = fma(pl[0], di, fma(pl[1], dj, pl[2]));
+    float ch[4];
+    for (int k = 0; k < 4; k++)
+        ch[k] = (float)(fma(pl[3 + 3 * k], di, fma(pl[4 + 3 * k], dj, pl[5 + 3 * k])) / den);
+    return make_float4(ch[3], ch[0], ch[1], ch[2]);
+}
+
 struct QuadSetup {
     int32_t hp[18];
     uint32_t bb_i, bb_j, rgba, flags;
@@ -494,6 +578,10 @@ __device__ __forceinline__ uint32_t setup_quad(const FrameArgs &a, uint32_t q, Q
                             r.B = B;
                             r.C0 = C0;
                             bb = make_uint2(r.bb_i, r.bb_j);
+                            if (a.vcol_in) {
+                                vertex_colour_planes(a, q, c, imin, jmin);
+                                keep_xy = true;  // the triangle choice reads the snapped vertices
+                            }
                         }
                     }
                 }
@@ -1715,13 +1803,14 @@ __device__ __forceinline__ void push_flagged(const FrameArgs &a, bool flag, cons
 // Per-pixel state of phase 3: the K-deep sorter (codes ascending, filled
 // with placeholder code 0 that is emitted first and blends nothing), the
 // last emitted code, and the front-to-back blend.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 struct PixelSorter {
     uint32_t qk[K], qc[K], qi[DEBUG ? K : 1];
     uint32_t last, nfrag, npop, obase;
     bool flagged;
     bool done;     // CUT: stopped, and no fragment left can precede the ones emitted
     float T, R, G, B;
+    int px, py;    // VCOL: the pixel (queued colours are quad indices)
 
     // CUT: the transmittance is below kCutT: nothing more is blended
     __device__ __forceinline__ bool stopped() const { return T < kCutT; }
@@ -1748,10 +1837,13 @@ struct PixelSorter {
         flagged |= (pk - 1u) < last;  // emitted codes must strictly increase (placeholders excepted)
         last = pk;
         const bool live = !CUT || !stopped();  // this fragment is blended
+        // with vertex colours pc is the quad (placeholders blend nothing)
+        const float4 d = VCOL ? (pk ? vertex_colour(a, pc, px, py) : make_float4(0.0f, 0.0f, 0.0f, 0.0f))
+                              : decode_rgba(pc);
         if (CUT)
-            blend_ftb_cut(decode_rgba(pc), T, R, G, B);
+            blend_ftb_cut(d, T, R, G, B);
         else
-            blend_ftb(pc, T, R, G, B);
+            blend_ftb_dec(d, T, R, G, B);
         if (DEBUG && pk != 0 && live) {
             if (a.dbg_ids && on && obase + npop < a.dbg_cap)
                 a.dbg_ids[obase + npop] = pi;
@@ -1926,9 +2018,9 @@ __device__ __forceinline__ void sorted_batch(const FrameArgs &a, const QuadXY *_
 // its last emitted code, and so has everything still in its queue.  Then
 // the fragments it blended are exactly the first ones of the full order.
 // A wave stops walking when all its pixels are done or flagged.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 __device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t ebase, uint32_t sb,
-                             const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG, CUT> &ps,
+                             const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG, CUT, VCOL> &ps,
                              uint32_t rest_after = 0xFFFFFFFFu)
 {
     wave_sync();
@@ -1967,7 +2059,7 @@ __device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_
             m = a.ent_mask[slot];
             const uint32_t q = a.ent_id[slot];
             L.s.w.st[lane] = a.plane[q];
-            if (DEBUG)
+            if (DEBUG || VCOL)
                 L.s.w.sid[lane] = q;
         }
         wave_sync();
@@ -1980,7 +2072,8 @@ __device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_
             const Stage st = L.s.w.st[k];
             const float kf =
                 frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
-            ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.s.w.sid[k] : 0);
+            const uint32_t sid = (DEBUG || VCOL) ? L.s.w.sid[k] : 0u;
+            ps.push(a, g.on, order_code(kf), VCOL ? sid : st.rgba, sid);
             if (ps.flagged)
                 col = 0;
         }
@@ -2017,9 +2110,9 @@ __device__ __forceinline__ uint32_t wave_sort_reg(uint32_t v, uint32_t lane)
 // Phases 2 and 3 for a block of n <= kFast entries, all on chip: the keys
 // are sorted in registers and each entry's mask, plane and colour come from
 // the fast entries written during phase 1.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t sb, const BlockGeom &g,
-                          uint32_t lane, PixelSorter<K, DEBUG, CUT> &ps)
+                          uint32_t lane, PixelSorter<K, DEBUG, CUT, VCOL> &ps)
 {
     wave_sync();
     uint32_t key = lane < n ? L.k.f.key[lane] : 0xFFFFFFFFu;
@@ -2029,7 +2122,7 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
         const uint32_t slot = key & ((1u << sb) - 1);
         m = L.k.f.mask[slot];
         L.s.w.st[lane] = L.k.f.st[slot];
-        if (DEBUG)
+        if (DEBUG || VCOL)
             L.s.w.sid[lane] = L.k.f.id[slot];
     }
     wave_sync();
@@ -2041,7 +2134,8 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
         col &= col - 1;
         const Stage st = L.s.w.st[k];
         const float kf = frag_key(st.A, st.B, st.C0, g.px - (int)(st.ij & 0xffffu), g.py - (int)(st.ij >> 16));
-        ps.push(a, g.on, order_code(kf), st.rgba, DEBUG ? L.s.w.sid[k] : 0);
+        const uint32_t sid = (DEBUG || VCOL) ? L.s.w.sid[k] : 0u;
+        ps.push(a, g.on, order_code(kf), VCOL ? sid : st.rgba, sid);
         if (ps.flagged)
             col = 0;
     }
@@ -2057,9 +2151,9 @@ __device__ void walk_fast(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t s
 // more than kSortCap entries.  With the cutoff, each slice is walked knowing
 // the smallest bound code of the slices after it, and the walk ends when
 // every pixel of the block is done or flagged.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 __device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t ebase, uint32_t sb,
-                            const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG, CUT> &ps)
+                            const BlockGeom &g, uint32_t lane, PixelSorter<K, DEBUG, CUT, VCOL> &ps)
 {
     // the key range of the block's entries
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
@@ -2150,7 +2244,7 @@ __device__ bool walk_sliced(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_t
             const uint32_t v = k == 0 ? sfx[0] : (k == 1 ? sfx[1] : (k == 2 ? sfx[2] : sfx[3]));
             rest = lane_value(v, b1 >> 2);
         }
-        walk_entries<K, DEBUG, CUT>(a, L, ns, ebase, sb, g, lane, ps, rest);
+        walk_entries<K, DEBUG, CUT, VCOL>(a, L, ns, ebase, sb, g, lane, ps, rest);
         if (CUT && !ballot(g.on && !ps.flagged && !ps.done))
             break;
         b0 = b1;
@@ -2208,9 +2302,9 @@ __device__ void keep_flagged_entries(const FrameArgs &a, const WaveLds &L, const
 // Outputs of a finished block: the pixel, flagged pixels to the exact
 // queue (with the block's entries kept for them), and the wave's running
 // statistics.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 __device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGeom &g, uint32_t lane,
-                             PixelSorter<K, DEBUG, CUT> &ps, uint32_t entries, uint32_t ebase)
+                             PixelSorter<K, DEBUG, CUT, VCOL> &ps, uint32_t entries, uint32_t ebase)
 {
     if (g.on && !ps.flagged)
         ps.flush(a, g.on);
@@ -2245,23 +2339,25 @@ __device__ void finish_block(const FrameArgs &a, const WaveLds &L, const BlockGe
 
 // Phases 2 and 3 of one block whose n entries phase 1 has built, with a
 // K-deep per-pixel sorter, and the block's outputs.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 __device__ __forceinline__ void walk_block(const FrameArgs &a, WaveLds &L, const BlockGeom &g, uint32_t lane,
                                            uint32_t n, uint32_t ebase, uint32_t sb)
 {
-    PixelSorter<K, DEBUG, CUT> ps;
+    PixelSorter<K, DEBUG, CUT, VCOL> ps;
     ps.init((DEBUG && g.on && a.dbg_off) ? a.dbg_off[g.pix] : 0);
+    ps.px = g.px;
+    ps.py = g.py;
     if (n <= kFast) {
-        walk_fast<K, DEBUG, CUT>(a, L, n, sb, g, lane, ps);
+        walk_fast<K, DEBUG, CUT, VCOL>(a, L, n, sb, g, lane, ps);
     } else {
         // entries written by other lanes of this wave are read back below
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         if (n <= kSortCap) {
-            walk_entries<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps);
+            walk_entries<K, DEBUG, CUT, VCOL>(a, L, n, ebase, sb, g, lane, ps);
         } else {
             if (lane == 0)
                 atomicAdd(&a.ctr->stripe[g.blk % kQueues].dense_n, 1u);
-            if (!walk_sliced<K, DEBUG, CUT>(a, L, n, ebase, sb, g, lane, ps)) {
+            if (!walk_sliced<K, DEBUG, CUT, VCOL>(a, L, n, ebase, sb, g, lane, ps)) {
                 // no slice fits: the exact path takes the block
                 ps.flagged = true;
                 if (lane == 0)
@@ -2269,7 +2365,7 @@ __device__ __forceinline__ void walk_block(const FrameArgs &a, WaveLds &L, const
             }
         }
     }
-    finish_block<K, DEBUG, CUT>(a, L, g, lane, ps, n, ebase);
+    finish_block<K, DEBUG, CUT, VCOL>(a, L, g, lane, ps, n, ebase);
 }
 
 // Sorted raster: one workgroup of NW waves per bin, one 8x8 block per wave
@@ -2278,8 +2374,8 @@ __device__ __forceinline__ void walk_block(const FrameArgs &a, WaveLds &L, const
 // order) and the other bins alongside them, sparse ones with a
 // kLowDepth-deep sorter (the paper's Section 4 proposes adapting to density
 // and running its low- and high-density rasterizers at the same time).
-template <int K, bool DEBUG, class Src, int NW, bool CUT>
-__global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 8 || (K <= 16 && !CUT))) ? 4 : 2) void k_raster(Src src)
+template <int K, bool DEBUG, class Src, int NW, bool CUT, bool VCOL>
+__global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 8 || (K <= 16 && !CUT && !VCOL))) ? 4 : 2) void k_raster(Src src)
 {
     __shared__ BinChunk<NW> C;
     __shared__ WaveLds Lw[NW];
@@ -2332,11 +2428,11 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 8 || (K <= 16 && !CUT))) 
         if (g.active) {
             if constexpr (K > (int)kLowDepth) {
                 if (low)
-                    walk_block<(int)kLowDepth, DEBUG, CUT>(a, L, g, lane, n, ebase, sb);
+                    walk_block<(int)kLowDepth, DEBUG, CUT, VCOL>(a, L, g, lane, n, ebase, sb);
                 else
-                    walk_block<K, DEBUG, CUT>(a, L, g, lane, n, ebase, sb);
+                    walk_block<K, DEBUG, CUT, VCOL>(a, L, g, lane, n, ebase, sb);
             } else {
-                walk_block<K, DEBUG, CUT>(a, L, g, lane, n, ebase, sb);
+                walk_block<K, DEBUG, CUT, VCOL>(a, L, g, lane, n, ebase, sb);
             }
         }
     }
@@ -2512,8 +2608,8 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                         q = (uint32_t)(s_key[e] & 0xffffffffu);
                         c = a.plane[q].rgba;
                     }
-                    // colours decoded by all lanes, then blended in order
-                    s_col[lane] = decode_rgba(c);
+                    // colours decoded (or interpolated) by all lanes, then blended in order
+                    s_col[lane] = (a.vcol_in && e < n) ? vertex_colour(a, q, i, j) : decode_rgba(c);
                     wave_sync();
                     const uint32_t lim = min(64u, n - base);
                     uint32_t nb = lim;  // fragments of this group blended
@@ -2609,7 +2705,8 @@ __global__ __launch_bounds__(NW * 64) void k_unsorted(Src src)
             while (bits) {
                 const uint32_t kk = (uint32_t)__builtin_ctzll(bits);
                 bits &= bits - 1;
-                blend_over(U.col[kk], R, G, B, Al);
+                blend_over_dec(a.vcol_in ? vertex_colour(a, U.cand[kk], g.px, g.py) : decode_rgba(U.col[kk]), R, G,
+                               B, Al);
                 nfrag++;
             }
             wave_sync();
@@ -2706,21 +2803,22 @@ bool sorter_depth_supported(int k)
 static uint32_t raster_grid(const FrameArgs &a) { return a.k_low ? 2 * a.nbins : a.nbins; }
 
 // Raster (one workgroup per bin), then the exact pass.
-template <int K, bool DEBUG, bool CUT>
+template <int K, bool DEBUG, bool CUT, bool VCOL>
 static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     const OneFrame f{a};
     // the parity dump keeps one more id per sorter slot: past depth 4 (and
-    // with the cutoff) its kernels do not fit 16 waves' registers and take 8,
-    // as do cutoff kernels past depth 8 (the image is the same)
-    constexpr bool wide_dbg = (DEBUG && (K > 4 || CUT)) || (CUT && K > 8);
+    // with the cutoff or vertex colours) its kernels do not fit 16 waves'
+    // registers and take 8, as do cutoff and vertex-colour kernels past depth
+    // 8 (the image is the same)
+    constexpr bool wide_dbg = (DEBUG && (K > 4 || CUT || VCOL)) || ((CUT || VCOL) && K > 8);
     const uint32_t nw = min(raster_waves_for(a.bin_shift, K), wide_dbg ? 8u : 16u);
     if (nw == 4)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4, CUT>), dim3(raster_grid(a)), dim3(4 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 4, CUT, VCOL>), dim3(raster_grid(a)), dim3(4 * 64), 0, s, f);
     else if (nw == 8)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8, CUT>), dim3(raster_grid(a)), dim3(8 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 8, CUT, VCOL>), dim3(raster_grid(a)), dim3(8 * 64), 0, s, f);
     else if constexpr (K <= 12 && !wide_dbg)
-        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16, CUT>), dim3(raster_grid(a)), dim3(16 * 64), 0, s, f);
+        hipLaunchKernelGGL((k_raster<K, DEBUG, OneFrame, 16, CUT, VCOL>), dim3(raster_grid(a)), dim3(16 * 64), 0, s, f);
     if (ev) {
         (void)hipEventRecord(ev[5], s);
         (void)hipEventRecord(ev[6], s);
@@ -2731,17 +2829,17 @@ static void launch_sorted(const FrameArgs &a, hipStream_t s, hipEvent_t *ev)
         (void)hipEventRecord(ev[7], s);
 }
 
-template <bool DEBUG, bool CUT>
+template <bool DEBUG, bool CUT, bool VCOL>
 static void launch_sorted_k(const FrameArgs &a, int k, hipStream_t s, hipEvent_t *ev)
 {
     switch (k) {
-    case 2: launch_sorted<2, DEBUG, CUT>(a, s, ev); break;
-    case 4: launch_sorted<4, DEBUG, CUT>(a, s, ev); break;
-    case 8: launch_sorted<8, DEBUG, CUT>(a, s, ev); break;
-    case 12: launch_sorted<12, DEBUG, CUT>(a, s, ev); break;
-    case 16: launch_sorted<16, DEBUG, CUT>(a, s, ev); break;
-    case 24: launch_sorted<24, DEBUG, CUT>(a, s, ev); break;
-    default: launch_sorted<32, DEBUG, CUT>(a, s, ev); break;
+    case 2: launch_sorted<2, DEBUG, CUT, VCOL>(a, s, ev); break;
+    case 4: launch_sorted<4, DEBUG, CUT, VCOL>(a, s, ev); break;
+    case 8: launch_sorted<8, DEBUG, CUT, VCOL>(a, s, ev); break;
+    case 12: launch_sorted<12, DEBUG, CUT, VCOL>(a, s, ev); break;
+    case 16: launch_sorted<16, DEBUG, CUT, VCOL>(a, s, ev); break;
+    case 24: launch_sorted<VCOL ? 16 : 24, DEBUG, CUT, VCOL>(a, s, ev); break;
+    default: launch_sorted<VCOL ? 16 : 32, DEBUG, CUT, VCOL>(a, s, ev); break;
     }
 }
 
@@ -2775,14 +2873,18 @@ hipError_t launch_frame(const FrameArgs &a, int sorter_depth, int unsorted, hipS
             (void)hipEventRecord(ev[7], s);
         }
     } else if (dbg) {
-        if (a.alpha_cut)
-            launch_sorted_k<true, true>(a, sorter_depth, s, ev);
+        if (a.vcol_in)
+            launch_sorted_k<true, false, true>(a, sorter_depth, s, ev);
+        else if (a.alpha_cut)
+            launch_sorted_k<true, true, false>(a, sorter_depth, s, ev);
         else
-            launch_sorted_k<true, false>(a, sorter_depth, s, ev);
+            launch_sorted_k<true, false, false>(a, sorter_depth, s, ev);
+    } else if (a.vcol_in) {
+        launch_sorted_k<false, false, true>(a, sorter_depth, s, ev);
     } else if (a.alpha_cut) {
-        launch_sorted_k<false, true>(a, sorter_depth, s, ev);
+        launch_sorted_k<false, true, false>(a, sorter_depth, s, ev);
     } else {
-        launch_sorted_k<false, false>(a, sorter_depth, s, ev);
+        launch_sorted_k<false, false, false>(a, sorter_depth, s, ev);
     }
     return hipGetLastError();
 }
@@ -2805,15 +2907,34 @@ static FrameMap stage_map(const FrameArgs *dev, uint32_t nf, F &&wg)
     return m;
 }
 
-template <int K, bool CUT>
+template <int K, bool CUT, bool VCOL>
 static void launch_raster_group(const FrameMap &m, uint32_t nw, hipStream_t s)
 {
+    // cutoff and vertex-colour kernels past depth 8 do not fit 16 waves'
+    // registers: they take 8 (the frames' entry regions hold 16)
+    constexpr bool narrow = (CUT || VCOL) && K > 8;
+    if (narrow && nw == 16)
+        nw = 8;
     if (nw == 4)
-        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 4, CUT>), dim3(m.wg0[m.nf]), dim3(4 * 64), 0, s, m);
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 4, CUT, VCOL>), dim3(m.wg0[m.nf]), dim3(4 * 64), 0, s, m);
     else if (nw == 8)
-        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 8, CUT>), dim3(m.wg0[m.nf]), dim3(8 * 64), 0, s, m);
-    else if constexpr (K <= 12)
-        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 16, CUT>), dim3(m.wg0[m.nf]), dim3(16 * 64), 0, s, m);
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 8, CUT, VCOL>), dim3(m.wg0[m.nf]), dim3(8 * 64), 0, s, m);
+    else if constexpr (K <= 12 && !narrow)
+        hipLaunchKernelGGL((k_raster<K, false, FrameMap, 16, CUT, VCOL>), dim3(m.wg0[m.nf]), dim3(16 * 64), 0, s, m);
+}
+
+template <bool CUT, bool VCOL>
+static void raster_group_k(int K, const FrameMap &mr, uint32_t nw, hipStream_t s)
+{
+    switch (K) {
+    case 2: launch_raster_group<2, CUT, VCOL>(mr, nw, s); break;
+    case 4: launch_raster_group<4, CUT, VCOL>(mr, nw, s); break;
+    case 8: launch_raster_group<8, CUT, VCOL>(mr, nw, s); break;
+    case 12: launch_raster_group<12, CUT, VCOL>(mr, nw, s); break;
+    case 16: launch_raster_group<16, CUT, VCOL>(mr, nw, s); break;
+    case 24: launch_raster_group<VCOL ? 16 : 24, CUT, VCOL>(mr, nw, s); break;
+    default: launch_raster_group<VCOL ? 16 : 32, CUT, VCOL>(mr, nw, s); break;
+    }
 }
 
 hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *sorter_depth, uint32_t nf,
@@ -2856,10 +2977,10 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     // raster launches, one per (depth, waves, cutoff) present
     for (int K : kDepths) {
         for (uint32_t nw : kWaveCounts) {
-            for (uint32_t cut = 0; cut < 2; cut++) {
+            for (uint32_t mode = 0; mode < 3; mode++) {  // flat, flat with the cutoff, vertex colours
                 auto in_group = [&](uint32_t f) {
-                    return sorter_depth[f] == K && raster_waves_for(host[f].bin_shift, K) == nw &&
-                           (host[f].alpha_cut != 0) == (cut != 0);
+                    const uint32_t fm = host[f].vcol_in ? 2u : (host[f].alpha_cut ? 1u : 0u);
+                    return sorter_depth[f] == K && raster_waves_for(host[f].bin_shift, K) == nw && fm == mode;
                 };
                 bool any = false;
                 for (uint32_t f = 0; f < nf; f++)
@@ -2868,27 +2989,12 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
                     continue;
                 const FrameMap mr =
                     stage_map(dev, nf, [&](uint32_t f) { return in_group(f) ? raster_grid(host[f]) : 0u; });
-                if (cut) {
-                    switch (K) {
-                    case 2: launch_raster_group<2, true>(mr, nw, s); break;
-                    case 4: launch_raster_group<4, true>(mr, nw, s); break;
-                    case 8: launch_raster_group<8, true>(mr, nw, s); break;
-                    case 12: launch_raster_group<12, true>(mr, nw, s); break;
-                    case 16: launch_raster_group<16, true>(mr, nw, s); break;
-                    case 24: launch_raster_group<24, true>(mr, nw, s); break;
-                    default: launch_raster_group<32, true>(mr, nw, s); break;
-                    }
-                } else {
-                    switch (K) {
-                    case 2: launch_raster_group<2, false>(mr, nw, s); break;
-                    case 4: launch_raster_group<4, false>(mr, nw, s); break;
-                    case 8: launch_raster_group<8, false>(mr, nw, s); break;
-                    case 12: launch_raster_group<12, false>(mr, nw, s); break;
-                    case 16: launch_raster_group<16, false>(mr, nw, s); break;
-                    case 24: launch_raster_group<24, false>(mr, nw, s); break;
-                    default: launch_raster_group<32, false>(mr, nw, s); break;
-                    }
-                }
+                if (mode == 1)
+                    raster_group_k<true, false>(K, mr, nw, s);
+                else if (mode == 2)
+                    raster_group_k<false, true>(K, mr, nw, s);
+                else
+                    raster_group_k<false, false>(K, mr, nw, s);
             }
         }
     }

@@ -79,7 +79,8 @@ private:
 
 struct SceneRec {
     uint32_t n;
-    uint64_t off;  // v[12][n] floats then rgba[n]
+    uint64_t off;       // v[12][n] floats, rgba[n], then (vertex colours) vc[4][n]
+    bool vcol = false;  // per-vertex colours
 };
 
 struct Workspace {
@@ -239,12 +240,14 @@ struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
         match_bits, qcap_blocks;
     uint64_t o_cov, o_plane, o_extra, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
-        o_femask, o_feid, o_blkent, o_ebound, o_binpx, o_highlist, o_binclass, o_large, total;
+        o_femask, o_feid, o_blkent, o_ebound, o_binpx, o_highlist, o_binclass, o_large, o_vcrec, total;
     uint32_t fe_cap;
     uint32_t cut;  // transmittance cutoff: entries carry a bound code
+    bool vcol;     // vertex-colour records
 };
 
-Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, uint32_t pair_hint, uint32_t cut)
+Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, uint32_t pair_hint, uint32_t cut,
+               bool vcol)
 {
     Plan p{};
     p.cut = cut;
@@ -292,6 +295,8 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.o_bbox = take((uint64_t)n * 8);
     p.o_cull = take((uint64_t)n);
     p.o_large = take((uint64_t)n * 4);
+    p.o_vcrec = vcol ? take((uint64_t)n * sizeof(lr::VColRec)) : 0;
+    p.vcol = vcol;
     p.o_table = take((uint64_t)p.nunits * p.nbins * 4);
     p.o_start = take(((uint64_t)p.nbins + 1) * 4);
     p.o_count = take((uint64_t)p.nbins * 4);
@@ -387,7 +392,10 @@ lr_status check_frame(lr_context ctx, lr_scene scene, const lr_camera *cam, uint
         return fail(ctx, LR_ERR_INVALID_ARG, "sorter depth must be one of 2, 4, 8, 12, 16, 24, 32");
     if (!std::isfinite(cam->fov_y) || !(cam->fov_y > 0.0f) || !(cam->fov_y < 3.14159f))
         return fail(ctx, LR_ERR_INVALID_ARG, "fov_y must be in (0, pi)");
-    plan = make_plan(it->second.n, W, H, t.bin, t.half, pair_hint(ctx, scene, W, H, t.bin), ctx->cut ? 1u : 0u);
+    if (it->second.vcol && ctx->cut)
+        return fail(ctx, LR_ERR_INVALID_ARG, "the transmittance cutoff is defined for flat colours only");
+    plan = make_plan(it->second.n, W, H, t.bin, t.half, pair_hint(ctx, scene, W, H, t.bin), ctx->cut ? 1u : 0u,
+                     it->second.vcol);
     if (plan.nbins > kMaxBins)
         return fail(ctx, LR_ERR_INVALID_ARG,
                     "too many bins for this frame size (at most 16384; use a larger bin size)");
@@ -403,6 +411,10 @@ void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *ou
     a.v = reinterpret_cast<const float *>(scene);
     a.rgba_in = reinterpret_cast<const uint32_t *>(scene + 48ull * n);
     a.n = n;
+    if (plan.vcol) {
+        a.vcol_in = reinterpret_cast<const uint32_t *>(scene + 52ull * n);
+        a.vcrec = reinterpret_cast<lr::VColRec *>(base + plan.o_vcrec);
+    }
     for (int k = 0; k < 3; k++)
         a.pos[k] = cam->pos[k];
     for (int r = 0; r < 3; r++)
@@ -533,6 +545,11 @@ Tune resolve_tune(lr_context ctx, const lr_request &r)
         t.k = r.sorter_depth;
     if (r.block_h)
         t.half = r.block_h == 4 ? 1u : (r.block_h == 8 ? 0u : 2u);  // 2: invalid
+    // Vertex-colour frames sort at depth 16 at most: deeper queues beside the
+    // colour planes outgrow the register file.  The depth never changes the
+    // image (pixels past the queue take the exact pass).
+    if (sc != ctx->scenes.end() && sc->second.vcol && t.k > 16)
+        t.k = 16;
     return t;
 }
 
@@ -1069,7 +1086,51 @@ lr_status lr_upload_scene(lr_context ctx, const lr_quad *q, uint32_t n, int q_on
         }
     }
     lr_scene id = ctx->next_scene++;
-    ctx->scenes[id] = SceneRec{n, off};
+    SceneRec rec;
+    rec.n = n;
+    rec.off = off;
+    ctx->scenes[id] = rec;
+    *out = id;
+    return LR_OK;
+}
+
+lr_status lr_upload_scene_vertex_colors(lr_context ctx, const lr_quad_vc *q, uint32_t n, lr_scene *out)
+{
+    if (!ctx || !q || !out)
+        return fail(ctx, LR_ERR_INVALID_ARG, "NULL argument");
+    if (n < 1 || n > (1u << 24))
+        return fail(ctx, LR_ERR_INVALID_ARG, "quad count must be in [1, 2^24]");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    uint64_t off;
+    if (!ctx->alloc.alloc(68ull * n, off))
+        return fail(ctx, LR_ERR_OUT_OF_MEMORY, "arena full");
+    // v[12][n] fp32, rgba[n] (vertex 0's colour), vc[4][n]
+    std::vector<float> hv((size_t)12 * n);
+    std::vector<uint32_t> hc((size_t)5 * n);
+    for (uint32_t i = 0; i < n; i++) {
+        for (int k = 0; k < 4; k++) {
+            for (int r = 0; r < 3; r++)
+                hv[(size_t)(k * 3 + r) * n + i] = q[i].v[k][r];
+            hc[(size_t)(1 + k) * n + i] = q[i].rgba[k];
+        }
+        hc[i] = q[i].rgba[0];
+    }
+    char *base = ctx->arena + off;
+    hipError_t e = hipMemcpyAsync(base, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + 48ull * n, hc.data(), hc.size() * 4, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        ctx->alloc.release(off);
+        return hip_fail(ctx, e, "scene upload");
+    }
+    lr_scene id = ctx->next_scene++;
+    SceneRec rec;
+    rec.n = n;
+    rec.off = off;
+    rec.vcol = true;
+    ctx->scenes[id] = rec;
     *out = id;
     return LR_OK;
 }

@@ -81,7 +81,7 @@ class TuneRule(ctypes.Structure):
 
 
 EXPORTS = ["lr_status_string", "lr_last_error", "lr_create", "lr_destroy", "lr_upload_scene",
-           "lr_release_scene", "lr_render", "lr_render_noalloc", "lr_render_debug", "lr_render_unsorted",
+           "lr_upload_scene_vertex_colors", "lr_release_scene", "lr_render", "lr_render_noalloc", "lr_render_debug", "lr_render_unsorted",
            "lr_render_batch", "lr_set_tuning", "lr_request_bytes", "lr_sync", "lr_get_stats",
            "lr_get_stage_times", "lr_debug_setup", "lr_debug_bins"]
 
@@ -106,6 +106,7 @@ def load_library(path: str = LIB_PATH):
         "lr_create": [ctypes.POINTER(Config), ctypes.POINTER(CTX)],
         "lr_destroy": [CTX],
         "lr_upload_scene": [CTX, P, U32, ctypes.c_int, ctypes.POINTER(U64)],
+        "lr_upload_scene_vertex_colors": [CTX, P, U32, ctypes.POINTER(U64)],
         "lr_release_scene": [CTX, U64],
         "lr_render": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P],
         "lr_render_noalloc": [CTX, U64, ctypes.POINTER(Camera), U32, U32, P, P],
@@ -212,6 +213,18 @@ class Context:
         out = ctypes.c_uint64()
         self._check(self.lib.lr_upload_scene(self.h, rec.ctypes.data_as(ctypes.c_void_p), n, 0,
                                              ctypes.byref(out)), self.h)
+        return int(out.value)
+
+    def upload_vertex_colors(self, v: np.ndarray, vcol: np.ndarray) -> int:
+        """Make quads with per-vertex colours resident: v float32 [n,4,3],
+        vcol uint32 [n,4] (straight-alpha RGBA8 per vertex)."""
+        n = int(v.shape[0])
+        rec = np.zeros(n, dtype=np.dtype([("v", "<f4", (4, 3)), ("rgba", "<u4", (4,))]))
+        rec["v"] = v
+        rec["rgba"] = np.asarray(vcol, np.uint32).reshape(n, 4)
+        out = ctypes.c_uint64()
+        self._check(self.lib.lr_upload_scene_vertex_colors(self.h, rec.ctypes.data_as(ctypes.c_void_p), n,
+                                                           ctypes.byref(out)), self.h)
         return int(out.value)
 
     def upload_device(self, quads) -> int:

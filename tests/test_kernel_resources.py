@@ -38,11 +38,12 @@ def test_no_kernel_uses_scratch(kernels):
 
 
 def test_raster_register_budget(kernels):
-    # release variants: depth 4..16 exact, depth 4 and 8 with the transmittance cutoff
+    # release variants: depth 4..16 exact (flat colours), depth 4 and 8 with
+    # the transmittance cutoff or vertex colours
     seen = 0
     for name, v in kernels.items():
-        if "k_raster" in name and (re.search(r"ILi(4|8|12|16)ELb0E.*ELb0EEEvT", name) or
-                                   re.search(r"ILi(4|8)ELb0E.*ELb1EEEvT", name)):
+        if "k_raster" in name and (re.search(r"ILi(4|8|12|16)ELb0E.*ELb0ELb0EEEvT", name) or
+                                   re.search(r"ILi(4|8)ELb0E.*ELb(1ELb0|0ELb1)EEEvT", name)):
             assert v["vgpr"] <= 128, (name, v["vgpr"])
             seen += 1
     assert seen >= 20
@@ -53,7 +54,7 @@ def test_raster_lds_allows_sixteen_waves_per_cu(kernels):
     CU (160 KiB of LDS), so LDS does not cut occupancy below 4 waves/SIMD."""
     seen = 0
     for name, v in kernels.items():
-        m = re.search(r"k_raster.*Li(\d+)ELb[01]EEEvT", name)
+        m = re.search(r"k_raster.*Li(\d+)ELb[01]ELb[01]EEEvT", name)
         if m:
             nw = int(m.group(1))
             assert (16 // nw) * v["lds"] <= 160 * 1024, (name, nw, v["lds"])
