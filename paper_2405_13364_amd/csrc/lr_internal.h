@@ -161,6 +161,27 @@ __host__ __device__ constexpr uint32_t raster_waves_for(uint32_t bin_shift, int 
     return (raster_waves(bin_shift) == 16 && sorter_depth > 12) ? 8u : raster_waves(bin_shift);
 }
 
+// Bands of bin rows of the four-wave scatter: each unit's scatter is split
+// over workgroups that own one band each, so that the band's per-wave
+// offsets (four rows of at most kBandBins words) leave room for several
+// workgroups per CU.  Bands double until one holds at most kBandBins bins
+// (or is a single row).
+constexpr uint32_t kBandBins = 2048;
+
+__host__ __device__ constexpr uint32_t scatter_bands(uint32_t nbx, uint32_t nby)
+{
+    uint32_t s = 1;
+    while (2 * s <= nby && ((nby + s - 1) / s) * nbx > kBandBins)
+        s *= 2;
+    return s;
+}
+
+// Bins of the largest band.
+__host__ __device__ constexpr uint32_t band_bins(uint32_t nbx, uint32_t nby)
+{
+    return (nby + scatter_bands(nbx, nby) - 1) / scatter_bands(nbx, nby) * nbx;
+}
+
 // Everything one frame's kernels need (passed by value).
 struct FrameArgs {
     // scene (SoA): v[(k*3 + r) * n + q] for vertex k, component r; rgba[n]

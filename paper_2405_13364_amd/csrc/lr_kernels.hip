@@ -737,6 +737,37 @@ __device__ __forceinline__ bool quad_bins(uint2 bb, uint32_t shift, uint32_t &bx
     return true;
 }
 
+// The rows [r0, r1) of a bin rectangle (bx0, by0, bw wide, np bins): by0
+// becomes its first kept row relative to r0, np its kept bins.
+__device__ __forceinline__ void clip_rows(uint32_t &by0, uint32_t bw, uint32_t &np, uint32_t r0, uint32_t r1)
+{
+    if (!np)
+        return;
+    const uint32_t ya = max(by0, r0), yb = min(by0 + np / bw, r1);
+    np = ya < yb ? (yb - ya) * bw : 0u;
+    by0 = ya < yb ? ya - r0 : 0u;
+}
+
+// Calls f(i, bx, by) for the np bins of a rectangle bw bins wide whose
+// first bin is (bx0, by0), row by row (i = by * nbx + bx): steps instead of
+// a division per bin.
+template <typename F>
+__device__ __forceinline__ void for_rect_bins(uint32_t bx0, uint32_t by0, uint32_t bw, uint32_t np, uint32_t nbx,
+                                              F &&f)
+{
+    uint32_t bx = bx0, by = by0, i = by0 * nbx + bx0;
+    for (uint32_t j = 0; j < np; j++) {
+        f(i, bx, by);
+        if (++bx == bx0 + bw) {
+            bx = bx0;
+            by++;
+            i += nbx - bw + 1;
+        } else {
+            i++;
+        }
+    }
+}
+
 // Groups of 64 quads (and of 64 bins) whose loads a binning wave issues
 // together.
 constexpr uint32_t kBinPrefetch = 8;
@@ -792,8 +823,9 @@ __device__ __forceinline__ void large_records(const FrameArgs &a, uint32_t q, Co
 }
 
 // Counts the kept bins of one large quad q (wave-uniform), its bbox bins
-// spread over the lanes.
-__device__ __forceinline__ void count_one_large(const FrameArgs &a, uint32_t q, uint32_t *s_hist, uint32_t *s_px)
+// spread over the lanes; only bins in rows [r0, r1), indexed from row r0.
+__device__ __forceinline__ void count_one_large(const FrameArgs &a, uint32_t q, uint32_t *s_hist, uint32_t *s_px,
+                                                uint32_t r0 = 0, uint32_t r1 = 0xFFFFu)
 {
     const uint32_t lane = lane_id();
     const uint2 bb = a.bbox[q];
@@ -802,12 +834,13 @@ __device__ __forceinline__ void count_one_large(const FrameArgs &a, uint32_t q, 
     large_records(a, q, r, ex);
     uint32_t bx0, by0, bw, np;
     quad_bins(bb, a.bin_shift, bx0, by0, bw, np);
+    clip_rows(by0, bw, np, r0, r1);
     for (uint32_t j = lane; j < np; j += 64) {
         const uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
-        if (bin_maybe_covered(r, ex, bx, by, a.bin_shift)) {
+        if (bin_maybe_covered(r, ex, bx, by + r0, a.bin_shift)) {
             atomicAdd(&s_hist[by * a.nbx + bx], 1u);
             if (s_px)
-                atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb, bx, by, a.bin_shift));
+                atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb, bx, by + r0, a.bin_shift));
         }
     }
 }
@@ -849,12 +882,8 @@ __global__ __launch_bounds__(64) void k_bin_count(Src src)
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
             const bool large = !a.bbox_binning && quad_is_large(bb[k]);  // binned from the large list
             uint32_t bx0, by0, bw, np;
-            if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
-                for (uint32_t j = 0; j < np; j++) {
-                    uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
-                    atomicAdd(&s_hist[by * a.nbx + bx], 1u);
-                }
-            }
+            if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np))
+                for_rect_bins(bx0, by0, bw, np, a.nbx, [&](uint32_t i, uint32_t, uint32_t) { atomicAdd(&s_hist[i], 1u); });
         }
     }
     for_large_share(a, u, 0, 1, [&](uint32_t q) { count_one_large(a, q, s_hist, nullptr); });
@@ -1000,11 +1029,12 @@ constexpr uint32_t kScatterGroup = 512;
 // every bin list stays in ascending quad order.
 __device__ __forceinline__ void scatter_small(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
                                               uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane,
-                                              uint32_t lo_lane, uint32_t hi_lane)
+                                              uint32_t lo_lane, uint32_t hi_lane, uint32_t r0, uint32_t r1)
 {
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
     quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
+    clip_rows(by0, bw, np, r0, r1);  // bins of the band, rows from r0
     if (lane < lo_lane || lane >= hi_lane)
         np = 0;  // lanes of this run only
     // exclusive prefix of np over the wave: the chunk's pair pre .. pre + np - 1
@@ -1054,16 +1084,18 @@ __device__ __forceinline__ void scatter_small(const FrameArgs &a, uint2 cur, uin
 // Places the kept bins of one large quad q (bbox bb), its bbox bins spread
 // over the lanes; every lane holds a different bin, so each takes its slot
 // with one LDS atomic.
-__device__ __forceinline__ void scatter_large(const FrameArgs &a, uint32_t q, uint2 bb, uint32_t *offs, uint32_t lane)
+__device__ __forceinline__ void scatter_large(const FrameArgs &a, uint32_t q, uint2 bb, uint32_t *offs, uint32_t lane,
+                                              uint32_t r0, uint32_t r1)
 {
     CovRec r;
     ExtraRec ex;
     large_records(a, q, r, ex);
     uint32_t bx0, by0, bw, np;
     quad_bins(bb, a.bin_shift, bx0, by0, bw, np);
+    clip_rows(by0, bw, np, r0, r1);  // bins of the band, rows from r0
     for (uint32_t j = lane; j < np; j += 64) {
         const uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
-        if (bin_maybe_covered(r, ex, bx, by, a.bin_shift)) {
+        if (bin_maybe_covered(r, ex, bx, by + r0, a.bin_shift)) {
             const uint32_t pos = atomicAdd(&offs[by * a.nbx + bx], 1u);
             if (pos < a.pair_cap)
                 a.pairs[pos] = q;
@@ -1075,10 +1107,12 @@ __device__ __forceinline__ void scatter_large(const FrameArgs &a, uint32_t q, ui
 // The pairs of 64 consecutive quads (lane l holds the bbox of quad base +
 // l); large quads are left to the large list.
 __device__ __forceinline__ void scatter_chunk(const FrameArgs &a, uint2 cur, uint32_t base, uint32_t *offs,
-                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane)
+                                              uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane,
+                                              uint32_t r0 = 0, uint32_t r1 = 0xFFFFu)
 {
     const bool large = !a.bbox_binning && quad_is_large(cur);
-    scatter_small(a, large ? make_uint2(0xffffu, 0xffffu) : cur, base, offs, s_pref, s_rect, s_own, lane, 0u, 64u);
+    scatter_small(a, large ? make_uint2(0xffffu, 0xffffu) : cur, base, offs, s_pref, s_rect, s_own, lane, 0u, 64u, r0,
+                  r1);
 }
 
 // Publishes a frame's bin offsets (bin_start) and total, and logs a
@@ -1158,18 +1192,20 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
         scatter_chunk(a, s_bb[(base - q0) % kScatterGroup + lane], base, s_off, s_pref, s_rect, s_own, lane);
         wave_sync();  // one wave per workgroup
     }
-    for_large_share(a, u, 0, 1, [&](uint32_t q) { scatter_large(a, q, bbox[q], s_off, lane); });
+    for_large_share(a, u, 0, 1, [&](uint32_t q) { scatter_large(a, q, bbox[q], s_off, lane, 0u, 0xFFFFu); });
 }
 
 
 // Binning with four waves per unit (frames of at most kBin4MaxBins bins).
 // Count: the unit's quads are split over the 256 lanes into one LDS
-// histogram.  Scatter: wave w takes the w-th quarter of the unit and counts
-// it into its own histogram; a per-bin prefix over the four quarters, on
-// top of the bin's start and the unit's scanned table entry, gives each wave
+// histogram.  Scatter: one workgroup per unit and band of bin rows; wave w
+// takes the w-th quarter of the unit and counts its pairs in the band into
+// its own histogram; the bin's start (a prefix over the bin counts each
+// workgroup takes), the unit's scanned table entry and a per-bin prefix
+// over the four quarters give each wave
 // its own offsets, so the quarters scatter concurrently and every bin list
 // still comes out in ascending quad order.
-constexpr uint32_t kBin4MaxBins = 8192;  // 4 x 32 KiB of per-wave offsets
+constexpr uint32_t kBin4MaxBins = 8192;  // the count's histogram: 32 KiB
 constexpr uint32_t kBin4Waves = 4;
 
 template <class Src>
@@ -1203,12 +1239,11 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
             const bool large = !a.bbox_binning && quad_is_large(bb[k]);  // binned from the large list
             uint32_t bx0, by0, bw, np;
             if (!large && quad_bins(bb[k], a.bin_shift, bx0, by0, bw, np)) {
-                for (uint32_t j = 0; j < np; j++) {
-                    uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
-                    atomicAdd(&s_hist[by * a.nbx + bx], 1u);
+                for_rect_bins(bx0, by0, bw, np, a.nbx, [&](uint32_t i, uint32_t bx, uint32_t by) {
+                    atomicAdd(&s_hist[i], 1u);
                     if (px)
-                        atomicAdd(&s_px[by * a.nbx + bx], bin_overlap_px(bb[k], bx, by, a.bin_shift));
-                }
+                        atomicAdd(&s_px[i], bin_overlap_px(bb[k], bx, by, a.bin_shift));
+                });
             }
         }
     }
@@ -1222,19 +1257,52 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
     }
 }
 
+// Groups of 64 quads whose bboxes a scatter wave loads into registers at
+// once: with loads and stores counted by one completion counter, a load
+// inside the scatter loop would also wait for every scattered store before
+// it, so all loads of a run of groups are issued up front.
+constexpr uint32_t kScatterRegGroups = 16;
+
+// bb[k] = bbox of quad c0 + 64 k + lane (no pixel past w1).
+__device__ __forceinline__ void load_groups(const uint2 *__restrict__ bbox, uint32_t c0, uint32_t w1, uint32_t lane,
+                                            uint2 (&bb)[kScatterRegGroups])
+{
+#pragma unroll
+    for (uint32_t k = 0; k < kScatterRegGroups; k++) {
+        const uint32_t q = c0 + 64 * k + lane;
+        bb[k] = make_uint2(0xffffu, 0xffffu);
+        if (q < w1)
+            bb[k] = bbox[q];
+    }
+}
+
+// Moves group k + 1 to bb[k]: the group in hand is always bb[0], so the
+// loops over groups index the array statically (register moves, no dynamic
+// register indexing).
+__device__ __forceinline__ void shift_groups(uint2 (&bb)[kScatterRegGroups])
+{
+#pragma unroll
+    for (uint32_t k = 0; k + 1 < kScatterRegGroups; k++)
+        bb[k] = bb[k + 1];
+}
+
 template <class Src>
 __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
 {
-    extern __shared__ uint32_t s_offs[];  // [kBin4Waves][nbins]
+    extern __shared__ uint32_t s_offs[];  // [kBin4Waves][bins of the band]
     __shared__ uint32_t s_pref[kBin4Waves][64];
     __shared__ uint32_t s_rect[kBin4Waves][64][3];
     __shared__ uint32_t s_own[kBin4Waves][64];
-    __shared__ uint32_t s_part[kBin4Waves];
+    __shared__ uint32_t s_part[2][kBin4Waves];
     uint32_t blk;
     const FrameArgs &a = *frame_of(src, blk);
     const uint2 *__restrict__ bbox = a.bbox;
-    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63, u = blk;
-    const uint32_t nbins = a.nbins;
+    const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    // workgroup = (unit u, band h of bin rows r0 .. r1 - 1)
+    const uint32_t nb = scatter_bands(a.nbx, a.nby), rows = (a.nby + nb - 1) / nb;
+    const uint32_t u = blk / nb, h = blk % nb;
+    const uint32_t r0 = min(h * rows, a.nby), r1 = min(r0 + rows, a.nby);
+    const uint32_t b0 = r0 * a.nbx, nbins = (r1 - r0) * a.nbx;  // the band's bins: b0 .. b0 + nbins - 1
     uint32_t *offs = s_offs + wave * nbins;
     // this wave's quarter of the unit, in groups of 64 quads
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
@@ -1243,83 +1311,104 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
     for (uint32_t b = lane; b < nbins; b += 64)
         offs[b] = 0;
     wave_sync();
-    for (uint32_t base = w0; base < w1; base += 64) {
-        const uint32_t q = base + lane;
-        uint2 bb = make_uint2(0xffffu, 0xffffu);
-        if (q < w1)
-            bb = bbox[q];
-        // the same pairs as the count kernel: bbox bins of the small quads,
-        // then the kept bins of this wave's share of the large list
-        const bool large = !a.bbox_binning && quad_is_large(bb);
-        uint32_t bx0, by0, bw, np;
-        if (!large && quad_bins(bb, a.bin_shift, bx0, by0, bw, np)) {
-            for (uint32_t j = 0; j < np; j++) {
-                uint32_t by = by0 + j / bw, bx = bx0 + j % bw;
-                atomicAdd(&offs[by * a.nbx + bx], 1u);
+    for (uint32_t c0 = w0; c0 < w1; c0 += 64 * kScatterRegGroups) {
+        uint2 bb[kScatterRegGroups];
+        load_groups(bbox, c0, w1, lane, bb);
+        // the same pairs as the count kernel, in the band: bbox bins of the
+        // small quads, then the kept bins of this wave's share of the large
+        // list
+        for (uint32_t base = c0; base < min(c0 + 64 * kScatterRegGroups, w1); base += 64) {
+            const bool large = !a.bbox_binning && quad_is_large(bb[0]);
+            uint32_t bx0, by0, bw, np;
+            if (!large && quad_bins(bb[0], a.bin_shift, bx0, by0, bw, np)) {
+                clip_rows(by0, bw, np, r0, r1);
+                for_rect_bins(bx0, by0, bw, np, a.nbx, [&](uint32_t i, uint32_t, uint32_t) { atomicAdd(&offs[i], 1u); });
             }
+            shift_groups(bb);
         }
     }
-    for_large_share(a, u, wave, kBin4Waves, [&](uint32_t q) { count_one_large(a, q, offs, nullptr); });
+    for_large_share(a, u, wave, kBin4Waves, [&](uint32_t q) { count_one_large(a, q, offs, nullptr, r0, r1); });
     __syncthreads();
-    // every workgroup takes the exclusive prefix over the bin counts itself
-    // (the first one also publishes it); thread t owns a contiguous run of bins
-    const uint32_t *row = a.table + (size_t)u * nbins;
-    const uint32_t run_len = (nbins + kBin4Waves * 64 - 1) / (kBin4Waves * 64);
-    const uint32_t b0 = min(t * run_len, nbins), b1 = min(b0 + run_len, nbins);
-    uint32_t sum = 0;
-    for (uint32_t b = b0; b < b1; b += kBinPrefetch) {
+    // the bins before the band: their total is where the band's lists start
+    uint32_t before = 0;
+    for (uint32_t c0 = 0; c0 < b0; c0 += kBin4Waves * 64 * kBinPrefetch) {
         uint32_t c[kBinPrefetch];
 #pragma unroll
-        for (uint32_t k = 0; k < kBinPrefetch; k++)
-            c[k] = b + k < b1 ? a.bin_count[b + k] : 0u;
+        for (uint32_t k = 0; k < kBinPrefetch; k++) {
+            const uint32_t b = c0 + kBin4Waves * 64 * k + t;
+            c[k] = b < b0 ? a.bin_count[b] : 0u;
+        }
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++)
-            sum += c[k];
+            before += c[k];
     }
-    // exclusive prefix of the run sums: within each wave, then over waves
-    const uint32_t incl = wave_incl_scan(sum);
-    if (lane == 63)
-        s_part[wave] = incl;
+    before = lane_value(wave_incl_scan(before), 63);
+    if (lane == 0)
+        s_part[1][wave] = before;
     __syncthreads();
-    uint32_t start = incl - sum, total = 0;
-    for (uint32_t w = 0; w < kBin4Waves; w++) {
-        const uint32_t ws = s_part[w];
-        start += w < wave ? ws : 0u;
-        total += ws;
-    }
-    for (uint32_t b = b0; b < b1; b += kBinPrefetch) {
+    uint32_t total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kBin4Waves; w++)
+        total += s_part[1][w];
+    // exclusive prefix over the band's bins, 256 consecutive bins per step:
+    // the lanes of a wave touch consecutive LDS words, so the per-wave offset
+    // rows are read and rewritten without bank conflicts; the first unit
+    // also publishes bin_start
+    const uint32_t *row = a.table + (size_t)u * a.nbins;
+    uint32_t step = 0;
+    for (uint32_t c0 = 0; c0 < nbins; c0 += kBin4Waves * 64 * kBinPrefetch) {
         uint32_t c[kBinPrefetch], r[kBinPrefetch];
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
-            c[k] = b + k < b1 ? a.bin_count[b + k] : 0u;
-            r[k] = b + k < b1 ? row[b + k] : 0u;
+            const uint32_t b = c0 + kBin4Waves * 64 * k + t;
+            c[k] = b < nbins ? a.bin_count[b0 + b] : 0u;
+            r[k] = b < nbins ? row[b0 + b] : 0u;
         }
 #pragma unroll
-        for (uint32_t k = 0; k < kBinPrefetch; k++) {
-            if (b + k < b1) {
+        for (uint32_t k = 0; k < kBinPrefetch; k++, step++) {
+            const uint32_t b = c0 + kBin4Waves * 64 * k + t;
+            if (c0 + kBin4Waves * 64 * k >= nbins)
+                break;
+            // wave sums go to alternating rows (the row above was read before
+            // the barrier ending the previous step): a row is rewritten two
+            // steps later, after every wave has passed the barrier in between
+            const uint32_t incl = wave_incl_scan(c[k]);
+            if (lane == 63)
+                s_part[step & 1][wave] = incl;
+            __syncthreads();
+            uint32_t start = total + incl - c[k];
+#pragma unroll
+            for (uint32_t w = 0; w < kBin4Waves; w++) {
+                const uint32_t ws = s_part[step & 1][w];
+                start += w < wave ? ws : 0u;
+                total += ws;
+            }
+            if (b < nbins) {
                 if (u == 0)
-                    a.bin_start[b + k] = start;
+                    a.bin_start[b0 + b] = start;
                 uint32_t run = start + r[k];
+#pragma unroll
                 for (uint32_t w = 0; w < kBin4Waves; w++) {
-                    const uint32_t cw = s_offs[w * nbins + b + k];
-                    s_offs[w * nbins + b + k] = run;
+                    const uint32_t cw = s_offs[w * nbins + b];
+                    s_offs[w * nbins + b] = run;
                     run += cw;
                 }
-                start += c[k];
             }
         }
     }
-    if (u == 0 && t == 0)
+    // the last band ends at the last row: its total is the frame's
+    if (u == 0 && h == nb - 1 && t == 0)
         publish_total(a, total);
     __syncthreads();
-    for (uint32_t base = w0; base < w1; base += 64) {
-        const uint32_t q = base + lane;
-        uint2 bb = make_uint2(0xffffu, 0xffffu);
-        if (q < w1)
-            bb = bbox[q];
-        scatter_chunk(a, bb, base, offs, s_pref[wave], s_rect[wave], s_own[wave], lane);
+    for (uint32_t c0 = w0; c0 < w1; c0 += 64 * kScatterRegGroups) {
+        uint2 bb[kScatterRegGroups];
+        load_groups(bbox, c0, w1, lane, bb);
+        for (uint32_t base = c0; base < min(c0 + 64 * kScatterRegGroups, w1); base += 64) {
+            scatter_chunk(a, bb[0], base, offs, s_pref[wave], s_rect[wave], s_own[wave], lane, r0, r1);
+            shift_groups(bb);
+        }
     }
-    for_large_share(a, u, wave, kBin4Waves, [&](uint32_t q) { scatter_large(a, q, bbox[q], offs, lane); });
+    for_large_share(a, u, wave, kBin4Waves, [&](uint32_t q) { scatter_large(a, q, bbox[q], offs, lane, r0, r1); });
 }
 
 // ------------------------------------------------------------------ raster
@@ -2774,8 +2863,8 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
     if (ev)
         (void)hipEventRecord(ev[3], s);
     if (a.bin_waves == kBin4Waves)
-        hipLaunchKernelGGL(k_bin_scatter4<OneFrame>, dim3(a.nunits), dim3(kBin4Waves * 64),
-                           kBin4Waves * a.nbins * 4, s, f);
+        hipLaunchKernelGGL(k_bin_scatter4<OneFrame>, dim3(a.nunits * scatter_bands(a.nbx, a.nby)),
+                           dim3(kBin4Waves * 64), kBin4Waves * band_bins(a.nbx, a.nby) * 4, s, f);
     else
         hipLaunchKernelGGL(k_bin_scatter<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
     if (ev)
@@ -2960,6 +3049,14 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     const FrameMap mu = stage_map(dev, nf, [&](uint32_t f) { return host[f].bin_waves == 1 ? host[f].nunits : 0u; });
     const FrameMap mu4 =
         stage_map(dev, nf, [&](uint32_t f) { return host[f].bin_waves == kBin4Waves ? host[f].nunits : 0u; });
+    // the scatter: one workgroup per unit and band of bin rows
+    uint32_t max_band4 = 0;
+    for (uint32_t f = 0; f < nf; f++)
+        if (host[f].bin_waves == kBin4Waves)
+            max_band4 = std::max(max_band4, band_bins(host[f].nbx, host[f].nby));
+    const FrameMap mb4 = stage_map(dev, nf, [&](uint32_t f) {
+        return host[f].bin_waves == kBin4Waves ? host[f].nunits * scatter_bands(host[f].nbx, host[f].nby) : 0u;
+    });
     if (mu.wg0[nf])
         hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
     if (mu4.wg0[nf])
@@ -2969,9 +3066,9 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(kScanWaves * 64), 0, s, mt);
     if (mu.wg0[nf])
         hipLaunchKernelGGL(k_bin_scatter<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
-    if (mu4.wg0[nf])
-        hipLaunchKernelGGL(k_bin_scatter4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64),
-                           kBin4Waves * max_bins4 * 4, s, mu4);
+    if (mb4.wg0[nf])
+        hipLaunchKernelGGL(k_bin_scatter4<FrameMap>, dim3(mb4.wg0[nf]), dim3(kBin4Waves * 64),
+                           kBin4Waves * max_band4 * 4, s, mb4);
     static const int kDepths[] = {2, 4, 8, 12, 16, 24, 32};
     static const uint32_t kWaveCounts[] = {4, 8, 16};
     // raster launches, one per (depth, waves, cutoff) present
