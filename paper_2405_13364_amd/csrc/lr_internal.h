@@ -118,7 +118,7 @@ static_assert(sizeof(StatStripe) == 128, "one line per stripe");
 struct FrameCounters {
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
-    uint32_t fb_next;          // next flagged pixel for the exact pass
+    uint32_t fb_next;          // unused
     uint32_t fe_n;             // entries kept for the exact pass (may exceed fe_cap)
     uint32_t n_high;           // bins in high_list
     uint32_t n_large;          // quads in large_list

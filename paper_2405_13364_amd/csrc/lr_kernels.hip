@@ -2541,13 +2541,96 @@ __global__ __launch_bounds__(NW * 64, (!DEBUG && (K <= 8 || (K <= 16 && !CUT && 
 // when the buffer fills, sorts it and keeps its lower half (raising an upper
 // cut), so a round blends the smallest keys left, at least half a buffer.
 
-constexpr uint32_t kFallbackBuf = 4096;
-constexpr uint32_t kFallbackStep = 4;
+constexpr uint32_t kFallbackBuf = 2048;
+constexpr uint32_t kFallbackStep = 8;
+// Groups of 64 sorted fragments whose colours the blend loads at once.
+constexpr uint32_t kFallbackColours = 8;
 // The exact pass runs one workgroup per CU, each with kFallbackWaves waves
-// working on their own pixels with their own 32 KiB key buffer.
-constexpr uint32_t kFallbackWaves = 4;
+// working on their own pixels with their own 16 KiB key buffer.
+constexpr uint32_t kFallbackWaves = 8;
 constexpr uint32_t kFallbackGrid = 256;
-constexpr size_t kFallbackLds = (size_t)kFallbackWaves * (kFallbackBuf * 8 + 64 * 16);
+constexpr size_t kFallbackLds = (size_t)kFallbackWaves * kFallbackBuf * 8;
+
+// Ascending bitonic sort of the 64 R keys v[r] at index lane * R + r, in
+// registers: partners in the same lane (the first log2 R steps of every
+// merge) are compared directly, partners in other lanes exchanged with
+// shfl_xor.  Every lane must be active.
+template <int R>
+__device__ __forceinline__ void wave_sort_regs(unsigned long long (&v)[R], uint32_t lane)
+{
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * R; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j < (uint32_t)R) {
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)R; r++) {
+                    if (r & j)
+                        continue;
+                    const bool up = ((lane * R + r) & k) == 0;
+                    const unsigned long long x = v[r], y = v[r | j];
+                    const bool sw = (x > y) == up;
+                    v[r] = sw ? y : x;
+                    v[r | j] = sw ? x : y;
+                }
+            } else {
+                const uint32_t m = j / R;  // the partner lane is lane ^ m
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)R; r++) {
+                    const uint32_t lo = shfl_xor((uint32_t)v[r], (int)m);
+                    const uint32_t hi = shfl_xor((uint32_t)(v[r] >> 32), (int)m);
+                    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+                    const bool up = ((lane * R + r) & k) == 0;
+                    const bool lower = (lane & m) == 0;  // this lane holds the lower index of the pair
+                    v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+                }
+            }
+        }
+    }
+}
+
+// Sorts keys[0 .. n - 1] ascending (n <= 64 R): through registers.
+template <int R>
+__device__ __forceinline__ void sort_keys_regs(unsigned long long *keys, uint32_t n, uint32_t lane)
+{
+    unsigned long long v[R];
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)R; r++) {
+        const uint32_t i = lane * R + r;
+        v[r] = i < n ? keys[i] : ~0ull;
+    }
+    wave_sort_regs<R>(v, lane);
+    wave_sync();
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)R; r++) {
+        const uint32_t i = lane * R + r;
+        if (i < n)
+            keys[i] = v[r];
+    }
+    wave_sync();
+}
+
+// Sorts a wave's n keys in LDS ascending: in registers up to 512 keys, else
+// the LDS network.
+__device__ __noinline__ void sort_keys(unsigned long long *keys, uint32_t n, uint32_t lane)
+{
+    if (n <= 64)
+        sort_keys_regs<1>(keys, n, lane);
+    else if (n <= 128)
+        sort_keys_regs<2>(keys, n, lane);
+    else if (n <= 256)
+        sort_keys_regs<4>(keys, n, lane);
+    else if (n <= 512)
+        sort_keys_regs<8>(keys, n, lane);
+    else
+        wave_bitonic_sort<unsigned long long>(keys, n, ~0ull, lane);
+}
+
+// Lane s's value of v, as a wave-uniform value.
+__device__ __forceinline__ float lane_float(float v, uint32_t s)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)s));
+}
 
 // A record in one go: its 16-byte chunks issued together, so the coverage
 // test and the key wait once per record instead of once per field they
@@ -2571,17 +2654,16 @@ __device__ __forceinline__ const FrameArgs &frame_at(const OneFrame &src, uint32
 __device__ __forceinline__ uint32_t frame_count(const FrameMap &m) { return m.nf; }
 __device__ __forceinline__ const FrameArgs &frame_at(const FrameMap &m, uint32_t f) { return m.tab[f]; }
 
-// A persistent grid (kFallbackGrid workgroups of one wave) walks the frames
-// in order; in each frame its waves take flagged pixels one at a time from
-// the frame's work counter, so any number of flagged pixels spreads over the
-// whole GPU.
+// A persistent grid (kFallbackGrid workgroups of kFallbackWaves waves) walks
+// the frames in order; in each frame wave g of the grid takes flagged pixels
+// g, g + (waves of the grid), ..., so any number of flagged pixels spreads
+// over the whole GPU.
 template <bool DEBUG, class Src>
 __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
 {
-    extern __shared__ unsigned long long s_fb[];  // [kFallbackWaves][kFallbackBuf] keys, then decoded colours
+    extern __shared__ unsigned long long s_fb[];  // [kFallbackWaves][kFallbackBuf] keys
     const uint32_t blk = blockIdx.x, nblk = gridDim.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     unsigned long long *s_key = s_fb + (size_t)wave * kFallbackBuf;
-    float4 *s_col = reinterpret_cast<float4 *>(s_fb + (size_t)kFallbackWaves * kFallbackBuf) + wave * 64;
     for (uint32_t fi = 0; fi < frame_count(src); fi++) {
         const FrameArgs &a = frame_at(src, fi);
         const QuadXY *__restrict__ xyp = a.xy;
@@ -2597,13 +2679,7 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
         const uint32_t cq = a.ctr->stripe[lane].flag_n;
         const uint32_t incl = wave_incl_scan(cq);
         const uint32_t count = lane_value(incl, 63);
-        for (;;) {
-            uint32_t item = 0;
-            if (lane == 0 && count)
-                item = atomicAdd(&a.ctr->fb_next, 1u);
-            item = uniform(item);
-            if (item >= count)
-                break;
+        for (uint32_t item = blk * kFallbackWaves + wave; item < count; item += nblk * kFallbackWaves) {
             // stripe sq holds items [incl[sq - 1], incl[sq])
             const uint32_t sq = (uint32_t)__popcll(ballot(incl <= item));
             const uint32_t t = item - (sq ? lane_value(incl, sq - 1) : 0);
@@ -2689,26 +2765,48 @@ __global__ __launch_bounds__(kFallbackWaves * 64) void k_fallback(Src src)
                 }
                 if (total == 0)
                     total = seen;
-                wave_bitonic_sort<unsigned long long>(s_key, n, ~0ull, lane);
+                sort_keys(s_key, n, lane);
+                uint32_t cpre[kFallbackColours];  // colours of the next kFallbackColours groups, loaded together
                 for (uint32_t base = 0; base < n && !(cut && T < kCutT); base += 64) {
                     const uint32_t e = base + lane;
-                    uint32_t q = 0, c = 0;
-                    if (e < n) {
-                        q = (uint32_t)(s_key[e] & 0xffffffffu);
-                        c = a.plane[q].rgba;
+                    const uint32_t g = (base / 64) % kFallbackColours;
+                    if (g == 0) {
+#pragma unroll
+                        for (uint32_t k = 0; k < kFallbackColours; k++) {
+                            const uint32_t ek = e + 64 * k;
+                            cpre[k] = ek < n ? a.plane[(uint32_t)(s_key[ek] & 0xffffffffu)].rgba : 0u;
+                        }
                     }
-                    // colours decoded (or interpolated) by all lanes, then blended in order
-                    s_col[lane] = (a.vcol_in && e < n) ? vertex_colour(a, q, i, j) : decode_rgba(c);
-                    wave_sync();
+                    uint32_t c = cpre[0];
+#pragma unroll
+                    for (uint32_t k = 0; k + 1 < kFallbackColours; k++)
+                        cpre[k] = cpre[k + 1];
+                    const uint32_t q = e < n ? (uint32_t)(s_key[e] & 0xffffffffu) : 0u;
+                    // colours decoded (or interpolated) by all lanes, then blended
+                    // in order, each read from its lane as a uniform value
+                    const float4 dl = (a.vcol_in && e < n) ? vertex_colour(a, q, i, j) : decode_rgba(c);
                     const uint32_t lim = min(64u, n - base);
                     uint32_t nb = lim;  // fragments of this group blended
                     if (cut) {
                         nb = 0;
-                        for (uint32_t s = 0; s < lim && !(T < kCutT); s++, nb++)
-                            blend_ftb_cut(s_col[s], T, R, G2, B);
+#pragma unroll
+                        for (uint32_t s = 0; s < 64; s++) {
+                            if (s >= lim || T < kCutT)
+                                break;
+                            const float4 d = make_float4(lane_float(dl.x, s), lane_float(dl.y, s),
+                                                         lane_float(dl.z, s), lane_float(dl.w, s));
+                            blend_ftb_cut(d, T, R, G2, B);
+                            nb++;
+                        }
                     } else {
-                        for (uint32_t s = 0; s < lim; s++)
-                            blend_ftb_dec(s_col[s], T, R, G2, B);
+#pragma unroll
+                        for (uint32_t s = 0; s < 64; s++) {
+                            if (s >= lim)
+                                break;
+                            const float4 d = make_float4(lane_float(dl.x, s), lane_float(dl.y, s),
+                                                         lane_float(dl.z, s), lane_float(dl.w, s));
+                            blend_ftb_dec(d, T, R, G2, B);
+                        }
                     }
                     if (DEBUG && a.dbg_ids && lane < nb && obase + done + e < a.dbg_cap)
                         a.dbg_ids[obase + done + e] = q;
