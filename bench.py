@@ -42,8 +42,9 @@ WORKLOADS = {
            "alpha U[0.8,1.0], seed 2",
 }
 
-KERNELS = {"setup": "k_setup", "bin_count": "k_bin_count", "bin_scan": "k_bin_scan_tiles+k_bin_scan_final",
-           "bin_scatter": "k_bin_scatter", "raster": "k_raster", "fallback": "k_fallback"}
+KERNELS = {"setup": "k_setup", "bin_count": "k_bin_count4 (k_bin_count past 8192 bins)", "bin_scan": "k_bin_scan",
+           "bin_scatter": "k_bin_scatter4 (k_bin_scatter past 8192 bins)", "raster": "k_raster",
+           "fallback": "k_fallback"}
 
 
 def log(msg):
@@ -456,7 +457,7 @@ def frame_leg(torch, lucidraster, autotune, sc, workload, tune, tuning_note, ste
         "ms": ms, "frags": int(frags), "stats": st, "out": out,
         "line": {
             "workload": f"{workload}: {WORKLOADS[workload]}", "tuning": f"bin {b}, K {k}, 8x{bh}",
-            "tuning_note": tuning_note, "fragments": int(frags),
+            "tuning_note": tuning_note, "fragments": int(frags), "visible_quads": int(st["visible"]),
             "ms_per_frame": round(ms, 5), "Mfrags_per_s": round(frags / (ms * 1e-3) / 1e6, 3),
             "frames_per_s": round(1000.0 / ms, 2),
             "p50_ms": round(float(np.percentile(per, 50)), 5), "p99_ms": round(float(np.percentile(per, 99)), 5),
@@ -549,7 +550,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": line["workload"], "width": sc.width, "height": sc.height,
-                   "quads": sc.n, "fragments": int(frags), "bin_size": tune[0],
+                   "quads": sc.n, "visible_quads": line["visible_quads"], "fragments": int(frags),
+                   "bin_size": tune[0],
                    "block": f"8x{tune[2]}", "sorter_depth": tune[1], "tuning": note,
                    "arithmetic": "i32 coverage, f64 depth plane, f32 blend"},
         "frames_per_s": line["frames_per_s"],

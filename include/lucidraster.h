@@ -249,8 +249,10 @@ lr_status lr_upload_scene(lr_context ctx, const lr_quad *q, uint32_t n, int q_on
  * (P0, P1, P2) if T0 covers it, else T1 = (P0, P2, P3), and the barycentric
  * mix of that triangle's vertex colours where the ray through the pixel
  * centre meets the triangle's plane (perspective-correct), blended in fp32
- * without rounding to 8 bits.  Rendering such a scene with
- * LR_FLAG_ALPHA_CUTOFF fails with LR_ERR_INVALID_ARG.  1 <= n <= 2^24;
+ * without rounding to 8 bits.  Such frames sort at depth 16 at most (a
+ * deeper sorter depth is lowered to 16; the image never depends on it).
+ * Rendering such a scene with LR_FLAG_ALPHA_CUTOFF fails with
+ * LR_ERR_INVALID_ARG.  1 <= n <= 2^24;
  * LR_ERR_OUT_OF_MEMORY when the arena is full (68 bytes per quad). */
 lr_status lr_upload_scene_vertex_colors(lr_context ctx, const lr_quad_vc *q, uint32_t n, lr_scene *out);
 
