@@ -1197,7 +1197,7 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 
 
 // Binning with four waves per unit (frames of at most kBin4MaxBins bins).
-// Count: the unit's quads are split over the 256 lanes into one LDS
+// Count: the unit's quads are split over 1,024 lanes into one LDS
 // histogram.  Scatter: one workgroup per unit and band of bin rows; wave w
 // takes the w-th quarter of the unit and counts its pairs in the band into
 // its own histogram; the bin's start (a prefix over the bin counts each
@@ -1207,9 +1207,13 @@ __global__ __launch_bounds__(64) void k_bin_scatter(Src src)
 // still comes out in ascending quad order.
 constexpr uint32_t kBin4MaxBins = 8192;  // the count's histogram: 32 KiB
 constexpr uint32_t kBin4Waves = 4;
+// The count's workgroup: sixteen waves share the histogram of a unit of
+// 2048 quads or more (each lane counts a few of them instead of up to
+// sixteen), four waves that of a smaller unit (more workgroups per CU).
+__host__ __device__ constexpr uint32_t count4_waves(uint32_t unit_quads) { return unit_quads >= 2048 ? 16u : 4u; }
 
-template <class Src>
-__global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
+template <class Src, uint32_t NW>
+__global__ __launch_bounds__(NW * 64) void k_bin_count4(Src src)
 {
     extern __shared__ uint32_t s_hist[];  // [nbins] counts, then [nbins] overlap pixels when gathered
     uint32_t blk;
@@ -1218,18 +1222,18 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
     const uint32_t t = threadIdx.x, u = blk;
     const bool px = a.bin_px != nullptr;
     uint32_t *s_px = s_hist + a.nbins;
-    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64) {
+    for (uint32_t b = t; b < a.nbins; b += NW * 64) {
         s_hist[b] = 0;
         if (px)
             s_px[b] = 0;
     }
     __syncthreads();
     const uint32_t q0 = u * a.unit_quads, q1 = min(q0 + a.unit_quads, a.n);
-    for (uint32_t base = q0; base < q1; base += kBin4Waves * 64 * kBinPrefetch) {
+    for (uint32_t base = q0; base < q1; base += NW * 64 * kBinPrefetch) {
         uint2 bb[kBinPrefetch];
 #pragma unroll
         for (uint32_t k = 0; k < kBinPrefetch; k++) {
-            const uint32_t q = base + kBin4Waves * 64 * k + t;
+            const uint32_t q = base + NW * 64 * k + t;
             bb[k] = make_uint2(0xffffu, 0xffffu);  // no pixel
             if (q < q1)
                 bb[k] = bbox[q];
@@ -1247,10 +1251,11 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_count4(Src src)
             }
         }
     }
-    for_large_share(a, u, t >> 6, kBin4Waves, [&](uint32_t q) { count_one_large(a, q, s_hist, px ? s_px : nullptr); });
+    for_large_share(a, u, t >> 6, NW,
+                    [&](uint32_t q) { count_one_large(a, q, s_hist, px ? s_px : nullptr); });
     __syncthreads();
     uint32_t *row = a.table + (size_t)u * a.nbins;
-    for (uint32_t b = t; b < a.nbins; b += kBin4Waves * 64) {
+    for (uint32_t b = t; b < a.nbins; b += NW * 64) {
         row[b] = s_hist[b];
         if (px && s_px[b])
             atomicAdd(&a.bin_px[b], (unsigned long long)s_px[b]);
@@ -1718,6 +1723,74 @@ __device__ void wave_bitonic_sort(KeyT *keys, uint32_t n, KeyT pad, uint32_t lan
     }
 }
 
+// v of lane (this lane ^ m) for sort keys of 32 or 64 bits.
+__device__ __forceinline__ uint32_t shfl_xor_key(uint32_t v, int m) { return shfl_xor(v, m); }
+__device__ __forceinline__ unsigned long long shfl_xor_key(unsigned long long v, int m)
+{
+    const uint32_t lo = shfl_xor((uint32_t)v, m), hi = shfl_xor((uint32_t)(v >> 32), m);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Ascending bitonic sort of the 64 R keys v[r] at index lane * R + r, in
+// registers: partners in the same lane (the first log2 R steps of every
+// merge) are compared directly, partners in other lanes exchanged with
+// shfl_xor.  Every lane must be active.
+template <int R, typename KeyT>
+__device__ __forceinline__ void wave_sort_regs(KeyT (&v)[R], uint32_t lane)
+{
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * R; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j < (uint32_t)R) {
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)R; r++) {
+                    if (r & j)
+                        continue;
+                    const bool up = ((lane * R + r) & k) == 0;
+                    const KeyT x = v[r], y = v[r | j];
+                    const bool sw = (x > y) == up;
+                    v[r] = sw ? y : x;
+                    v[r | j] = sw ? x : y;
+                }
+            } else {
+                const uint32_t m = j / R;  // the partner lane is lane ^ m
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)R; r++) {
+                    const KeyT o = shfl_xor_key(v[r], (int)m);
+                    const bool up = ((lane * R + r) & k) == 0;
+                    const bool lower = (lane & m) == 0;  // this lane holds the lower index of the pair
+                    v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+                }
+            }
+        }
+    }
+}
+
+// Sorts keys[0 .. n - 1] of a wave's LDS ascending through registers
+// (n <= 64 R; keys[n .. 64 R - 1] must be in bounds, their values are not
+// read).
+template <int R, typename KeyT>
+__device__ __forceinline__ void sort_keys_regs(KeyT *keys, uint32_t n, KeyT pad, uint32_t lane)
+{
+    KeyT v[R];
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)R; r++) {
+        const uint32_t i = lane * R + r;
+        v[r] = keys[i];
+        v[r] = i < n ? v[r] : pad;
+    }
+    wave_sort_regs<R>(v, lane);
+    wave_sync();
+#pragma unroll
+    for (uint32_t r = 0; r < (uint32_t)R; r++) {
+        const uint32_t i = lane * R + r;
+        if (i < n)
+            keys[i] = v[r];
+    }
+    wave_sync();
+}
+
 // An entry's plane, bbox origin and colour as the per-pixel walk reads them
 // (the quad's PlaneRec).
 using Stage = PlaneRec;
@@ -2113,7 +2186,14 @@ __device__ void walk_entries(const FrameArgs &a, WaveLds &L, uint32_t n, uint32_
                              uint32_t rest_after = 0xFFFFFFFFu)
 {
     wave_sync();
-    wave_bitonic_sort<uint32_t>(L.k.key, n, 0xFFFFFFFFu, lane);
+    // the block's keys: in registers up to 256 (flat colours: the cutoff and
+    // vertex-colour kernels have no registers to spare), else the LDS network
+    if (!CUT && !VCOL && n <= 128)
+        sort_keys_regs<2, uint32_t>(L.k.key, n, 0xFFFFFFFFu, lane);
+    else if (!CUT && !VCOL && n <= 256)
+        sort_keys_regs<4, uint32_t>(L.k.key, n, 0xFFFFFFFFu, lane);
+    else
+        wave_bitonic_sort<uint32_t>(L.k.key, n, 0xFFFFFFFFu, lane);
     // CUT: seg_after[s] is the smallest bound code of the entries after segment s
     if (CUT) {
         // segments from the back, four at a time (their loads issued together)
@@ -2551,77 +2631,18 @@ constexpr uint32_t kFallbackWaves = 8;
 constexpr uint32_t kFallbackGrid = 256;
 constexpr size_t kFallbackLds = (size_t)kFallbackWaves * kFallbackBuf * 8;
 
-// Ascending bitonic sort of the 64 R keys v[r] at index lane * R + r, in
-// registers: partners in the same lane (the first log2 R steps of every
-// merge) are compared directly, partners in other lanes exchanged with
-// shfl_xor.  Every lane must be active.
-template <int R>
-__device__ __forceinline__ void wave_sort_regs(unsigned long long (&v)[R], uint32_t lane)
-{
-#pragma unroll
-    for (uint32_t k = 2; k <= 64u * R; k <<= 1) {
-#pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            if (j < (uint32_t)R) {
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)R; r++) {
-                    if (r & j)
-                        continue;
-                    const bool up = ((lane * R + r) & k) == 0;
-                    const unsigned long long x = v[r], y = v[r | j];
-                    const bool sw = (x > y) == up;
-                    v[r] = sw ? y : x;
-                    v[r | j] = sw ? x : y;
-                }
-            } else {
-                const uint32_t m = j / R;  // the partner lane is lane ^ m
-#pragma unroll
-                for (uint32_t r = 0; r < (uint32_t)R; r++) {
-                    const uint32_t lo = shfl_xor((uint32_t)v[r], (int)m);
-                    const uint32_t hi = shfl_xor((uint32_t)(v[r] >> 32), (int)m);
-                    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
-                    const bool up = ((lane * R + r) & k) == 0;
-                    const bool lower = (lane & m) == 0;  // this lane holds the lower index of the pair
-                    v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
-                }
-            }
-        }
-    }
-}
-
-// Sorts keys[0 .. n - 1] ascending (n <= 64 R): through registers.
-template <int R>
-__device__ __forceinline__ void sort_keys_regs(unsigned long long *keys, uint32_t n, uint32_t lane)
-{
-    unsigned long long v[R];
-#pragma unroll
-    for (uint32_t r = 0; r < (uint32_t)R; r++) {
-        const uint32_t i = lane * R + r;
-        v[r] = i < n ? keys[i] : ~0ull;
-    }
-    wave_sort_regs<R>(v, lane);
-    wave_sync();
-#pragma unroll
-    for (uint32_t r = 0; r < (uint32_t)R; r++) {
-        const uint32_t i = lane * R + r;
-        if (i < n)
-            keys[i] = v[r];
-    }
-    wave_sync();
-}
-
 // Sorts a wave's n keys in LDS ascending: in registers up to 512 keys, else
 // the LDS network.
 __device__ __noinline__ void sort_keys(unsigned long long *keys, uint32_t n, uint32_t lane)
 {
     if (n <= 64)
-        sort_keys_regs<1>(keys, n, lane);
+        sort_keys_regs<1>(keys, n, ~0ull, lane);
     else if (n <= 128)
-        sort_keys_regs<2>(keys, n, lane);
+        sort_keys_regs<2>(keys, n, ~0ull, lane);
     else if (n <= 256)
-        sort_keys_regs<4>(keys, n, lane);
+        sort_keys_regs<4>(keys, n, ~0ull, lane);
     else if (n <= 512)
-        sort_keys_regs<8>(keys, n, lane);
+        sort_keys_regs<8>(keys, n, ~0ull, lane);
     else
         wave_bitonic_sort<unsigned long long>(keys, n, ~0ull, lane);
 }
@@ -2950,11 +2971,16 @@ static hipError_t launch_setup_and_bins(const FrameArgs &a, hipStream_t s, hipEv
         (void)hipEventRecord(ev[1], s);
     if (!bins)
         return hipGetLastError();
-    if (a.bin_waves == kBin4Waves)
-        hipLaunchKernelGGL(k_bin_count4<OneFrame>, dim3(a.nunits), dim3(kBin4Waves * 64),
-                           a.nbins * 4 * (a.bin_px ? 2 : 1), s, f);
-    else
+    if (a.bin_waves == kBin4Waves) {
+        if (count4_waves(a.unit_quads) == 16)
+            hipLaunchKernelGGL((k_bin_count4<OneFrame, 16>), dim3(a.nunits), dim3(16 * 64),
+                               a.nbins * 4 * (a.bin_px ? 2 : 1), s, f);
+        else
+            hipLaunchKernelGGL((k_bin_count4<OneFrame, 4>), dim3(a.nunits), dim3(4 * 64),
+                               a.nbins * 4 * (a.bin_px ? 2 : 1), s, f);
+    } else {
         hipLaunchKernelGGL(k_bin_count<OneFrame>, dim3(a.nunits), dim3(64), a.nbins * 4, s, f);
+    }
     if (ev)
         (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_bin_scan<OneFrame>, dim3(scan_groups(a.nbins)), dim3(kScanWaves * 64), 0, s, f);
@@ -3157,8 +3183,16 @@ hipError_t launch_batch(const FrameArgs *host, const FrameArgs *dev, const int *
     });
     if (mu.wg0[nf])
         hipLaunchKernelGGL(k_bin_count<FrameMap>, dim3(mu.wg0[nf]), dim3(64), max_bins * 4, s, mu);
-    if (mu4.wg0[nf])
-        hipLaunchKernelGGL(k_bin_count4<FrameMap>, dim3(mu4.wg0[nf]), dim3(kBin4Waves * 64), max_bins4 * 8, s, mu4);
+    if (mu4.wg0[nf]) {
+        uint32_t max_uq = 0;
+        for (uint32_t f = 0; f < nf; f++)
+            if (host[f].bin_waves == kBin4Waves)
+                max_uq = std::max(max_uq, host[f].unit_quads);
+        if (count4_waves(max_uq) == 16)
+            hipLaunchKernelGGL((k_bin_count4<FrameMap, 16>), dim3(mu4.wg0[nf]), dim3(16 * 64), max_bins4 * 8, s, mu4);
+        else
+            hipLaunchKernelGGL((k_bin_count4<FrameMap, 4>), dim3(mu4.wg0[nf]), dim3(4 * 64), max_bins4 * 8, s, mu4);
+    }
     const FrameMap mt =
         stage_map(dev, nf, [&](uint32_t f) { return scan_groups(host[f].nbins); });
     hipLaunchKernelGGL(k_bin_scan<FrameMap>, dim3(mt.wg0[nf]), dim3(kScanWaves * 64), 0, s, mt);
