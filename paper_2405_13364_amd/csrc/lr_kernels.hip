@@ -1031,6 +1031,9 @@ __device__ __forceinline__ void scatter_small(const FrameArgs &a, uint2 cur, uin
                                               uint32_t *s_pref, uint32_t (*s_rect)[3], uint32_t *s_own, uint32_t lane,
                                               uint32_t lo_lane, uint32_t hi_lane, uint32_t r0, uint32_t r1)
 {
+    // bits that tell the band's bins apart
+    const uint32_t rows = min(r1, a.nby) - r0;
+    const uint32_t mbits = rows * a.nbx > 1 ? 32u - (uint32_t)__builtin_clz(rows * a.nbx - 1) : 1u;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t bx0 = 0, by0 = 0, bw = 1, np = 0;
     quad_bins(cur, a.bin_shift, bx0, by0, bw, np);
@@ -1062,7 +1065,7 @@ __device__ __forceinline__ void scatter_small(const FrameArgs &a, uint2 cur, uin
         }
         // lanes holding the same bin: AND over the bits of the bin index
         uint64_t peers = ballot(valid);
-        for (uint32_t bit = 0; bit < a.match_bits; bit++) {
+        for (uint32_t bit = 0; bit < mbits; bit++) {
             const bool set = (bin >> bit) & 1u;
             const uint64_t bm = ballot(set);
             peers &= set ? bm : ~bm;
