@@ -1887,14 +1887,28 @@ __device__ void scan_bin(const uint2 *__restrict__ bbox, const uint32_t *__restr
 {
     const uint32_t tid = threadIdx.x, lane = tid & 63;
     uint32_t nc = 0;
-    const uint32_t step = cached ? cnt : NW * 64;
+    // a long list comes in windows of list_cap(NW) quads, every thread
+    // loading its share of a window's indices, then of their bboxes, at once
+    constexpr uint32_t kPer = list_cap(NW) / (NW * 64);
+    const uint32_t step = cached ? cnt : list_cap(NW);
     for (uint32_t base = 0; base < cnt; base += step) {
         if (!cached) {
-            const uint32_t t = base + tid;
-            if (t < cnt) {
-                const uint32_t q = pairs[start + t];
-                C.q[tid] = q;
-                C.bb[tid] = bbox[q];
+            uint32_t qw[kPer];
+            uint2 bw[kPer];
+#pragma unroll
+            for (uint32_t k = 0; k < kPer; k++) {
+                const uint32_t t = base + k * NW * 64 + tid;
+                qw[k] = t < cnt ? pairs[start + t] : 0u;
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kPer; k++) {
+                const uint32_t t = base + k * NW * 64 + tid;
+                bw[k] = t < cnt ? bbox[qw[k]] : make_uint2(0xffffu, 0u);
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kPer; k++) {
+                C.q[k * NW * 64 + tid] = qw[k];
+                C.bb[k * NW * 64 + tid] = bw[k];
             }
             __syncthreads();
         }
