@@ -191,6 +191,43 @@ def check_bin_lists(counts, ids, sc, st, bin_size):
     return int(large.sum())
 
 
+@pytest.mark.parametrize("name,bands", [("c2", 2), ("c3", 4)])
+def test_bins_parity_in_row_bands(lr, name, bands):
+    """Frames of more than 2048 bins of 16 px scatter in bands of bin rows
+    (1280x720: two bands of 23 and 22 rows; 1920x1080: four of 17): every
+    bin list holds the oracle's bbox list of small quads in ascending order,
+    and large quads (the 1920x1080 frame has a few) only from its bbox list,
+    once each."""
+    sc = scenes.scene(name)
+    st = oracle.setup(sc.v, sc.camera, sc.width, sc.height)
+    large = large_quads(st)
+    nby = (sc.height + 15) // 16
+    nbx = (sc.width + 15) // 16
+    b = 1
+    while 2 * b <= nby and ((nby + b - 1) // b) * nbx > 2048:
+        b *= 2
+    assert b == bands
+    ctx = lr.Context(arena_bytes=2 << 30, bin_size=16)
+    h = ctx.upload(sc.v, sc.rgba)
+    counts, ids = ctx.debug_bins(h, sc.camera, sc.width, sc.height, 16)
+    ctx.close()
+    rc, roff, rids = oracle.bins(st, sc.width, sc.height, 16)
+    counts = np.asarray(counts).reshape(-1).astype(np.int64)
+    goff = np.concatenate([[0], np.cumsum(counts)])
+    ids = np.asarray(ids, np.int64)
+    rids = rids.astype(np.int64)
+    if not large.any():
+        np.testing.assert_array_equal(counts, rc.reshape(-1))
+        np.testing.assert_array_equal(ids, rids)
+        return
+    for b in range(counts.size):
+        g = ids[goff[b]:goff[b + 1]]
+        r = rids[int(roff[b]):int(roff[b + 1])]
+        np.testing.assert_array_equal(g[~large[g]], r[~large[r]], err_msg=f"bin {b}: small quads")
+        gl = g[large[g]]
+        assert len(np.unique(gl)) == len(gl) and np.isin(gl, r).all(), f"bin {b}: large quads"
+
+
 @pytest.mark.parametrize("bin_size", [16, 32, 64])
 @pytest.mark.parametrize("name", ["small", "c1", "ragged", "wide", "thin_large"])
 def test_bins_parity(lr, name, bin_size):
