@@ -63,6 +63,10 @@ class Server:
         self.budget = int(budget_bytes)
         self.slots = slots
         self.max_batch = max_batch
+        # admission statistics of the last run: batches closed early because
+        # the next request would not fit the budget, times a free slot waited
+        # for memory, and the most bytes ever in flight
+        self.stats = {"budget_cut_batches": 0, "memory_waits": 0, "max_inflight": 0}
 
     def run(self, requests: Sequence[Request]) -> List[Completion]:
         be = self.backend
@@ -73,6 +77,7 @@ class Server:
         done: List[Completion] = []
         nbatch = 0
         fp_cache: Dict[Tuple, int] = {}
+        self.stats = {"budget_cut_batches": 0, "memory_waits": 0, "max_inflight": 0}
 
         def footprint(r: Request) -> int:
             key = (r.scene, r.width, r.height, tuple(r.tune))
@@ -107,12 +112,16 @@ class Server:
                     batch.append(r)
                     fp += footprint(r)
                 if not batch:
+                    self.stats["memory_waits"] += 1
                     break  # wait for memory
+                if waiting and len(batch) < self.max_batch:
+                    self.stats["budget_cut_batches"] += 1
                 slot = free.pop(0)
                 t_sub = be.now()
                 token = be.submit(slot, batch, nbatch)
                 busy[slot] = (token, batch, fp, t_sub)
                 inflight += fp
+                self.stats["max_inflight"] = max(self.stats["max_inflight"], inflight)
                 nbatch += 1
             if not (pending or waiting or busy):
                 break

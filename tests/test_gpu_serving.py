@@ -111,3 +111,34 @@ def test_server_renders_overflowed_frames_again(lr):
     for r in trace:
         check_against_oracle(r, be.outputs[r.rid].cpu().numpy(), by_handle)
     ctx.close()
+
+
+def test_admission_binds_under_a_tight_budget(lr):
+    """A budget of about two and a half of the largest request footprints:
+    requests arriving together are admitted a few at a time (batches closed
+    by the budget, free slots waiting for memory), bytes in flight never
+    exceed the budget, and every served frame still matches the oracle."""
+    ctx = lr.Context(arena_bytes=1 << 30, batch_slots=2, graphs=False)
+    rng = np.random.default_rng(4)
+    meta, by_handle = [], {}
+    for s in range(6):
+        W, H = int(rng.integers(64, 320)), int(rng.integers(48, 240))
+        sc = scenes.small(W, H, int(rng.integers(2000, 20000)), 2100 + s, side=(1.0, 24.0), alpha=(0.05, 0.8))
+        h = ctx.upload(sc.v, sc.rgba)
+        meta.append((h, W, H))
+        by_handle[h] = sc
+    for h, W, H in meta:  # warm-up: plans each scene's capacity
+        ctx.render(h, scenes.Camera(), W, H)
+    trace = poisson_trace(1e7, 40, meta, seed=3200)  # all but simultaneous
+    be = GpuBackend(ctx, slots=2, keep_outputs=True)
+    budget = int(2.5 * max(be.footprint(r) for r in trace))
+    srv = Server(be, budget_bytes=budget, slots=2, max_batch=16)
+    be.start_clock()
+    done = srv.run(trace)
+    ctx.sync()
+    assert sorted(c.rid for c in done) == list(range(len(trace)))
+    assert srv.stats["budget_cut_batches"] > 0
+    assert srv.stats["max_inflight"] <= budget
+    for r in trace:
+        check_against_oracle(r, be.outputs[r.rid].cpu().numpy(), by_handle)
+    ctx.close()

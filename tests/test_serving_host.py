@@ -32,6 +32,10 @@ def test_budget_is_never_exceeded():
     done = srv.run(reqs_at([0.0] * n, scene_of=lambda i: i % 7))
     assert sorted(c.rid for c in done) == list(range(n))
     assert inflight_bytes_over_time(be.log, fp, cost, be.setup) <= 450
+    # the budget, not the batch limit, closed batches, and the server's own
+    # accounting agrees
+    assert srv.stats["budget_cut_batches"] > 0
+    assert 0 < srv.stats["max_inflight"] <= 450
 
 
 def test_batches_fill_free_slots_in_arrival_order():
