@@ -1265,6 +1265,23 @@ __global__ __launch_bounds__(NW * 64) void k_bin_count4(Src src)
     }
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup i to XCD
+// i mod 8).  xcd_order(i, n) numbers the n workgroups of a launch XCD by
+// XCD instead: the ones XCD 0 receives get 0 .. n0 - 1, XCD 1's the next,
+// and so on -- a bijection of [0, n), so consecutive indices share an XCD
+// and its L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_order(uint32_t i, uint32_t n)
+{
+    const uint32_t k = i % kXcds, j = i / kXcds, q = n / kXcds, r = n % kXcds;
+    return k < r ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j;
+}
+
+template <class Src>
+__device__ __forceinline__ constexpr bool is_one_frame() { return false; }
+template <>
+__device__ __forceinline__ constexpr bool is_one_frame<OneFrame>() { return true; }
+
 // Groups of 64 quads whose bboxes a scatter wave loads into registers at
 // once: with loads and stores counted by one completion counter, a load
 // inside the scatter loop would also wait for every scattered store before
@@ -1308,7 +1325,11 @@ __global__ __launch_bounds__(kBin4Waves * 64) void k_bin_scatter4(Src src)
     const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63;
     // workgroup = (unit u, band h of bin rows r0 .. r1 - 1)
     const uint32_t nb = scatter_bands(a.nbx, a.nby), rows = (a.nby + nb - 1) / nb;
-    const uint32_t u = blk / nb, h = blk % nb;
+    // consecutive units of a band on one XCD (single frames): their runs in
+    // each bin list are adjacent, so that XCD's L2 merges their scattered
+    // 4-byte stores into whole lines
+    const uint32_t v = is_one_frame<Src>() ? xcd_order(blk, a.nunits * nb) : blk;
+    const uint32_t u = v % a.nunits, h = v / a.nunits;
     const uint32_t r0 = min(h * rows, a.nby), r1 = min(r0 + rows, a.nby);
     const uint32_t b0 = r0 * a.nbx, nbins = (r1 - r0) * a.nbx;  // the band's bins: b0 .. b0 + nbins - 1
     uint32_t *offs = s_offs + wave * nbins;
