@@ -118,11 +118,10 @@ static_assert(sizeof(StatStripe) == 128, "one line per stripe");
 struct FrameCounters {
     uint32_t pairs_total;      // (bin, quad) pairs found by the scan
     uint32_t error;            // kErr* bits
-    uint32_t fb_next;          // unused
     uint32_t fe_n;             // entries kept for the exact pass (may exceed fe_cap)
     uint32_t n_high;           // bins in high_list
     uint32_t n_large;          // quads in large_list
-    uint32_t pad[26];
+    uint32_t pad[27];
     StatStripe stripe[kStripes];
 };
 
@@ -218,7 +217,6 @@ struct FrameArgs {
     uint32_t *bin_count;    // [nbins]
     uint32_t *pairs;        // [pair_cap]
     uint32_t pair_cap;
-    uint32_t match_bits;    // bits needed to hold a bin index
     // density classes (the paper's Section 4 suggests adapting bins to the
     // density and running low- and high-density rasterizers together): per
     // bin, the sum over its pairs of the quad bbox's pixels inside the bin,

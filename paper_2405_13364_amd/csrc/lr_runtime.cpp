@@ -238,7 +238,7 @@ uint32_t log2u(uint32_t x)
 // Byte layout of a frame workspace.
 struct Plan {
     uint32_t n, W, H, bin, half, shift, nbx, nby, nbins, unit_quads, nunits, bin_waves, pair_cap, nblk_x, nblk_y,
-        match_bits, qcap_blocks;
+        qcap_blocks;
     uint64_t o_cov, o_plane, o_extra, o_xy, o_bbox, o_cull, o_table, o_start, o_count, o_pairs, o_fb, o_ecode, o_emask, o_eid, o_ctr,
         o_femask, o_feid, o_blkent, o_ebound, o_binpx, o_highlist, o_binclass, o_large, o_vcrec, total;
     uint32_t fe_cap;
@@ -278,7 +278,6 @@ Plan make_plan(uint32_t n, uint32_t W, uint32_t H, uint32_t bin, uint32_t half, 
     p.pair_cap = (uint32_t)std::min<uint64_t>(cap, 0xF0000000ull);
     p.nblk_x = (W + 7) / 8;
     p.nblk_y = (H + 7) / 8;
-    p.match_bits = std::max<uint32_t>(1, log2u(p.nbins));
     uint64_t o = 0;
     auto take = [&](uint64_t bytes) {
         uint64_t r = o;
@@ -445,7 +444,6 @@ void fill_frame(const char *scene, uint32_t n, const lr_camera *cam, uint8_t *ou
     a.bin_count = reinterpret_cast<uint32_t *>(base + plan.o_count);
     a.pairs = reinterpret_cast<uint32_t *>(base + plan.o_pairs);
     a.pair_cap = plan.pair_cap;
-    a.match_bits = plan.match_bits;
     a.half_blocks = plan.half;
     a.nblk_x = plan.nblk_x;
     a.nblk_y = plan.nblk_y;
